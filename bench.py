@@ -1,0 +1,158 @@
+"""Throughput benchmark of the fused hybrid LB/FD step on one MI355X.
+
+Workload: the 1024 x 1024 D2Q9 lattice with cold walls at y = 0 and y = 1023, tau = 0.6,
+xi = 0.01, free-energy coefficients b = 0.1, kappa = -0.006, c = 0.0375, Tc = 1, T0 = 1.5,
+Tw = 0.7, Gamma = 0.1, phi0 uniform in [-0.05, 0.05] from seed 1 (synthetic, resident in device
+memory before timing).  One benchmark step is one full time step of the method (force, stream,
+collide, order-parameter sub-steps, temperature); the structure factor and the orientation
+histogram are taken every 1000 steps inside the timed region.
+
+Prints one JSON line: MLUPS (million lattice-site updates per second), the roofline of the
+dominant kernel (fused force/stream/collide kernel; algorithmic bytes per site: populations read
+and written, 2 x 9 x 4 B, plus phi read, 4 B = 76 B), and the FP64 CPU oracle's MLUPS on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "c2_1024sq_tau0.6"
+HBM_PEAK_GBS = 8000.0
+LB_BYTES_PER_SITE = 76       # dominant kernel: 9 populations in + 9 out (FP32) + phi in
+STEP_BYTES_PER_SITE = 80     # whole step minimum: populations in/out + phi in/out
+OBS_EVERY = 1000
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1102_3094_amd", "csrc", "lam_2d.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(n_sites):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken from another version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", f"lb2d_{WORKLOAD}_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(params, phi0, budget_s=12.0):
+    from oracle import Oracle
+    o = Oracle(params).init_fields(phi0)
+    o.step(1)  # first-touch of the arrays outside the timing
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s and steps < 2000:
+        o.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    n = params["nx"] * params["ny"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} steps of the {params['nx']}x{params['ny']} workload "
+                      f"({dt:.1f} s, FP64, OpenMP over sites)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method is built and "
+              "measured on a single MI355X; multi-GPU slab decomposition is not part of it.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1102_3094_amd as lam
+    import synthetic as S
+
+    lam.load()
+    p = S.model_params(WORKLOAD)
+    phi0 = S.initial_phi(WORKLOAD)
+    n_sites = p["nx"] * p["ny"]
+    sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(phi0, dtype=torch.float32))
+    n_phi, n_T = sim.substeps
+
+    def run(k):
+        done = 0
+        while done < k:
+            chunk = min(OBS_EVERY - (sim_step[0] % OBS_EVERY), k - done)
+            sim.step(chunk)
+            done += chunk
+            sim_step[0] += chunk
+            if sim_step[0] % OBS_EVERY == 0:
+                sim.structure_factor(p["nx"] // 2)
+                sim.orientation(18)
+
+    sim_step = [0]
+    run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = n_sites * args.steps / dt / 1e6
+
+    # second pass of the same length with HIP events around every kernel on the library's stream
+    sim.set_timing(True)
+    run(args.steps)
+    kt = sim.kernel_times()
+    sim.set_timing(False)
+    lb_ms, lb_n = kt["lb"]
+    phi_ms, phi_n = kt["phi"]
+    lb_avg_s = lb_ms / max(lb_n, 1) / 1e3
+    achieved = LB_BYTES_PER_SITE * n_sites / lb_avg_s / 1e9
+    traffic = traffic_from_profiles(n_sites)
+    ob = sim.observables()
+
+    out = {
+        "metric": "MLUPS + % HBM roofline; surrogate vs plain wall-time at equal S(k) peak error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D2Q9 {p['nx']}x{p['ny']} cold walls, tau={p['tau']}, "
+                               f"xi={p['xi']}, n_phi={n_phi}, n_T={n_T}, S(k)+orientation "
+                               f"every {OBS_EVERY} steps",
+                   "nx": p["nx"], "ny": p["ny"], "tau": p["tau"], "xi": p["xi"],
+                   "n_phi_sub": n_phi, "seed": 1},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "lb2d (force + stream + collide)",
+                     "bytes_per_site": LB_BYTES_PER_SITE, "avg_launch_us": lb_avg_s * 1e6,
+                     "launches": lb_n},
+        "step_effective_roofline_frac": round(mlups * 1e6 * STEP_BYTES_PER_SITE / 8e12, 4),
+        "kernel_avg_us": {"lb2d": lb_avg_s * 1e6, "phi2d": phi_ms / max(phi_n, 1) * 1e3},
+        "state_finite_at_end": not ob["nonfinite"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, phi0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/* lam.h -- C-ABI of the MI355X (gfx950) library for the hybrid lattice-Boltzmann / finite-difference
+ * model of lamellar fluids under cold thermal fronts (Gonnella, Lamura & Tiribocchi,
+ * arXiv:1102.3094, Sections 2 and 3).
+ *
+ * One simulation holds populations, order parameter and temperature on a D2Q9 (2D) or D3Q19 (3D)
+ * lattice in lattice units (dx = dt = 1, c_s^2 = 1/3, Section 2).  Each call of lam_step advances
+ * the state by whole time steps:
+ *   - reduced temperature a = (T - Tc)/Tc, eq. (aterm);
+ *   - chemical potential mu = a phi + b phi^3 - kappa lap phi + c lap^2 phi, eq. (chem), with the
+ *     second-order 5/7-point Laplacian and its square (13/25-point) as the biharmonic;
+ *   - body force F = -div P of the pressure tensor of Section 2 without its ideal-gas term
+ *     (the lattice pressure n c_s^2 stays; eq. (ff)), or F = -phi grad mu;
+ *   - moments n = sum f, n u = sum f e + F/2, eq. (moment); BGK collision with the second-order
+ *     equilibrium and the forcing term of eq. (latticeforceterm); streaming, with bounce-back on
+ *     walls half a spacing beyond the first and last layers of the last axis;
+ *   - n_phi explicit Euler sub-steps of d_t phi + div(phi u) = Gamma lap mu, eq. (massdiff),
+ *     with u and a held at the step's values;
+ *   - n_T forward-time centred-space sub-steps of d_t T = xi lap T with T = Tw on the wall
+ *     layers (Section 2: walls at fixed temperature).
+ * x (and y in 3D) are periodic; the order parameter is reflected evenly across the walls, so
+ * grad phi, grad lap phi and grad lap^2 phi have zero normal component there and sum(phi) is
+ * conserved exactly (Section 2).
+ *
+ * Memory.  Every device pointer is owned by the caller.  The library allocates no device memory:
+ * the caller passes one workspace of lam_workspace_bytes() bytes to lam_create and keeps it alive
+ * until lam_destroy.  The library owns only its host-side handle.  All work is queued on the
+ * HIP stream given to lam_create; calls that return data to the host synchronise that stream.
+ * A handle is not thread-safe; different handles on different streams are independent.
+ *
+ * Layouts (row-major, x fastest): scalar fields [nz][ny][nx] (nz = 1 in 2D), FP32;
+ * vector fields [dim][nz][ny][nx].  Populations are stored internally as FP32 deviations
+ * f_q - w_q from the rest state.
+ *
+ * Errors.  Every int-returning function returns 0 on success or one of the LAM_E* codes below;
+ * lam_last_error gives a message (for a NULL handle: the last failure of lam_create or
+ * lam_workspace_bytes on the calling thread).
+ */
+#ifndef LAM_H
+#define LAM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAM_OK 0
+#define LAM_EINVAL (-1)      /* invalid argument or parameter set                               */
+#define LAM_EHIP (-2)        /* a HIP runtime call failed (message holds the HIP error string)  */
+#define LAM_ESIZE (-3)       /* workspace or buffer too small                                    */
+#define LAM_ENONFINITE (-4)  /* observables found a NaN or infinite value in the state          */
+#define LAM_ESTATE (-5)      /* checkpoint does not match this simulation                        */
+
+typedef struct lam_params {
+  int32_t dim;               /* 2 (D2Q9) or 3 (D3Q19)                                              */
+  int32_t nx, ny, nz;        /* lattice extents; nz = 1 in 2D; each >= 8                            */
+  int32_t walls;             /* 1: cold walls on the first and last layer of the last axis        */
+  int32_t hydro;             /* 1: lattice Boltzmann coupled; 0: phi and T only (Section 3 runs) */
+  double tau;                /* BGK relaxation time, > 1/2; viscosity (tau - 1/2)/3 (Section 2)  */
+  double Gamma;              /* mobility, eq. (massdiff), >= 0                                      */
+  double b, kappa, c;        /* free-energy coefficients, eq. (fren); b > 0 and c > 0 required     */
+  double Tc, T0, Tw;         /* critical, initial and wall temperatures, eq. (aterm); Tc > 0        */
+  double xi;                 /* thermal conductivity; < 0 means an instantaneous quench (T = Tw)  */
+  int32_t n_phi_sub;         /* Euler sub-steps of phi per step; 0 = smallest stable count        */
+  int32_t n_T_sub;           /* FTCS sub-steps of T per step; 0 = ceil(xi / 0.45)                  */
+  int32_t force_form;        /* 0: F = -div P; 1: F = -phi grad mu                                 */
+  int32_t pop_storage;       /* 0: FP32 population deviations (only value supported)              */
+  int32_t allow_unstable;    /* 1: accept n_phi_sub / n_T_sub below the stability bound           */
+  int32_t reserved_;
+  double body_force[3];      /* uniform acceleration g; the force density n g is added (tests)    */
+} lam_params;
+
+typedef struct lam_obs {
+  double mass_dev;           /* sum over sites of (n - 1)                                          */
+  double mom[3];             /* sum over sites of sum_q f_q e_q (before the F/2 shift)            */
+  double phi_sum;            /* sum over sites of phi                                              */
+  double max_u;              /* max over sites of |u|, u = (sum_q f_q e_q + F/2)/n                 */
+  double mach;               /* max_u / c_s, c_s = 1/sqrt(3); Section 2 asks for Ma < 0.1          */
+  double free_energy;        /* sum of a phi^2/2 + b phi^4/4 + kappa/2 |forward grad phi|^2
+                                + c/2 (lap phi)^2 (eq. fren without the ideal-gas part)           */
+  int64_t step;
+  int32_t nonfinite;         /* 1 if a population or phi value is NaN or infinite                  */
+  int32_t reserved_;
+} lam_obs;
+
+typedef struct lam_sim lam_sim;
+
+/* Bytes of device workspace the parameter set needs (256-byte aligned start required). */
+int lam_workspace_bytes(const lam_params* p, size_t* bytes);
+
+/* Validate p and bind a simulation to the caller's workspace and HIP stream (hipStream_t passed
+ * as void*, NULL = default stream).  The fields are undefined until lam_init_fields. */
+int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+               lam_sim** out);
+
+/* Sub-step counts in use after the automatic rule. */
+int lam_substeps(const lam_sim* s, int32_t* n_phi, int32_t* n_T);
+
+/* Initial state: phi = d_phi0 [N]; populations at equilibrium with density d_n0 [N] (NULL: 1)
+ * and velocity d_u0 [dim][N] (NULL: 0); T = T0 except T = Tw on the wall layers (everywhere if
+ * xi < 0).  Device pointers; the data are copied.  Resets the step counter to 0. */
+int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const float* d_n0);
+
+/* Advance nsteps time steps; asynchronous on the simulation's stream. */
+int lam_step(lam_sim* s, int64_t nsteps);
+
+/* Conserved totals and monitors of the current state (FP64 reductions); synchronises. Returns
+ * LAM_ENONFINITE (with *h_out filled) if the state holds NaN or infinite values. */
+int lam_observables(lam_sim* s, lam_obs* h_out);
+
+/* Structure factor of phi (2D only): h_S[nbins] is the mean of |DFT(phi - mean)|^2 / N over the
+ * modes of each shell floor(|k| / dk), dk = 2 pi / min(nx, ny) (k = 0 left out); k_peak and
+ * S_peak refine the largest shell by a parabola through it and its neighbours (shell centres at
+ * (m + 1/2) dk); k_mean is the |phi_hat|^2-weighted mean |k|.  Output pointers are host memory,
+ * any of the three scalars may be NULL; synchronises. */
+int lam_structure_factor(lam_sim* s, double* h_S, int32_t nbins, double* k_peak, double* S_peak,
+                         double* k_mean);
+
+/* Orientation of phi gradients (2D only): h_hist[nbins] holds the fraction of sum |grad phi|^2
+ * whose gradient angle atan2(g_y, g_x) mod pi falls in each of nbins equal bins of [0, pi);
+ * Q = sum(g_y^2 - g_x^2) / sum |grad phi|^2 (+1: lamellae parallel to the walls); h_Qrow[ny]
+ * (nullable) is the same ratio per row.  Central differences, even reflection at walls.  Host
+ * outputs; synchronises. */
+int lam_orientation(lam_sim* s, double* h_hist, int32_t nbins, double* Q, double* h_Qrow);
+
+/* Fields of the current state into caller device buffers (any may be NULL): phi [N],
+ * u [dim][N] (force-shifted velocity of eq. moment), n [N], T [N]. Asynchronous. */
+int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T);
+
+/* Checkpoint: the complete state (populations, phi, T, step) in lam_state_bytes() bytes of
+ * caller device memory.  lam_set_state returns LAM_ESTATE for a checkpoint of another lattice. */
+int lam_state_bytes(const lam_sim* s, size_t* bytes);
+int lam_get_state(lam_sim* s, void* d_buf, size_t bytes);
+int lam_set_state(lam_sim* s, const void* d_buf, size_t bytes);
+
+/* Profiling aid.  With timing enabled, lam_step brackets each kernel it launches with HIP events
+ * on the simulation's stream.  lam_kernel_times synchronises, writes the accumulated kernel time
+ * in milliseconds and the launch count of each kernel class (LAM_K_LB: the fused force /
+ * stream / collide kernel; LAM_K_PHI: the order-parameter kernel) into h_ms[nk] and
+ * h_launches[nk] (host arrays), and resets the accumulators.  Events are created on first use
+ * and released by lam_destroy. */
+#define LAM_K_LB 0
+#define LAM_K_PHI 1
+#define LAM_NK 2
+int lam_set_timing(lam_sim* s, int32_t enable);
+int lam_kernel_times(lam_sim* s, double* h_ms, int64_t* h_launches, int32_t nk);
+
+const char* lam_last_error(const lam_sim* s);
+void lam_destroy(lam_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

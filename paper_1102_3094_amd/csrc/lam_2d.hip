@@ -1,0 +1,402 @@
+// lam_2d.hip -- gfx950 kernels of one D2Q9 time step (arXiv:1102.3094, Section 2).
+//
+// Storage: populations as FP32 deviations g_q = f_q - w_q in SoA planes g[q][y][x]; the state
+// between steps is the post-collision field of the previous step, so one kernel pulls
+// (streams), takes moments, applies the force and collides.  phi[y][x] FP32; T per row.
+//
+// lb2d: one 64 x TY tile per workgroup of 256 threads (4 waves; each wave owns rows
+//   ty, ty+4, ...).  phi is staged in LDS with a halo of 3, from which the Laplacian (halo 2)
+//   and then the pressure tensor (halo 1) are built in LDS; every site then takes the discrete
+//   divergence of P, pulls its 9 populations (halfway bounce-back at walls), collides with the
+//   BGK + forcing rule and writes 9 populations and the force-shifted velocity.
+// phi2d<S>: S explicit Euler sub-steps of the order-parameter equation on a tile with halo 3S,
+//   all in LDS (temporal blocking), reading phi and u once and writing phi once.  The workgroup
+//   of tile 0 also advances the per-row temperature.
+#include "lam_dev.hpp"
+
+namespace lam {
+
+constexpr int TX = 64;
+constexpr int NT = 256;
+
+enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
+
+template <int TY>
+struct Lb2dSmem {
+  float phi[TY + 6][TX + 6];
+  float L[TY + 4][TX + 4];
+  float P[3][TY + 2][TX + 2];  // Pxx, Pyy, Pxy (or mu in P[0] for the -phi grad mu form)
+  float a[TY + 6];
+  double red[4][R_N];
+};
+
+template <int TY, int MODE>
+__global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __restrict__ gin,
+                                                  float* __restrict__ gout,
+                                                  const float* __restrict__ phi,
+                                                  const float* __restrict__ Trow,
+                                                  float* __restrict__ uout,
+                                                  float* __restrict__ nout,
+                                                  double* __restrict__ partials) {
+  __shared__ Lb2dSmem<TY> S;
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const int tid = threadIdx.x;
+  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, nbx * nby);
+  const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
+
+  // phi with halo 3: periodic in x, reflected (or periodic) in y; a = (T - Tc)/Tc per row
+  for (int i = tid; i < (TY + 6) * (TX + 6); i += NT) {
+    int r = i / (TX + 6), c = i - r * (TX + 6);
+    bool f;
+    int gy = wall_axis(y0 - 3 + r, ny, P.walls, f);
+    int gx = wrap(x0 - 3 + c, nx);
+    S.phi[r][c] = phi[(size_t)gy * nx + gx];
+  }
+  if (tid < TY + 6) {
+    bool f;
+    int gy = wall_axis(y0 - 3 + tid, ny, P.walls, f);
+    S.a[tid] = (Trow[gy] - P.Tc) / P.Tc;
+  }
+  __syncthreads();
+  // L = lap phi on halo 2
+  for (int i = tid; i < (TY + 4) * (TX + 4); i += NT) {
+    int r = i / (TX + 4), c = i - r * (TX + 4);
+    const int R = r + 1, C = c + 1;
+    S.L[r][c] = (S.phi[R][C + 1] + S.phi[R][C - 1]) + (S.phi[R + 1][C] + S.phi[R - 1][C]) -
+                4.f * S.phi[R][C];
+  }
+  __syncthreads();
+  if (MODE != MODE_FIELDS || P.hydro) {
+    // pressure tensor (or mu) on halo 1
+    for (int i = tid; i < (TY + 2) * (TX + 2); i += NT) {
+      int r = i / (TX + 2), c = i - r * (TX + 2);
+      const int R = r + 2, C = c + 2;  // phi coordinates
+      const int r1 = r + 1, c1 = c + 1;  // L coordinates
+      float ph = S.phi[R][C], L = S.L[r1][c1];
+      float M = (S.L[r1][c1 + 1] + S.L[r1][c1 - 1]) + (S.L[r1 + 1][c1] + S.L[r1 - 1][c1]) - 4.f * L;
+      float a = S.a[R];
+      if (P.force_form == 1) {
+        S.P[0][r][c] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
+      } else {
+        float px = 0.5f * (S.phi[R][C + 1] - S.phi[R][C - 1]);
+        float py = 0.5f * (S.phi[R + 1][C] - S.phi[R - 1][C]);
+        float Lx = 0.5f * (S.L[r1][c1 + 1] - S.L[r1][c1 - 1]);
+        float Ly = 0.5f * (S.L[r1 + 1][c1] - S.L[r1 - 1][c1]);
+        float ph2 = ph * ph;
+        float p0 = 0.5f * a * ph2 + 0.75f * P.b * ph2 * ph2 -
+                   P.kappa * (ph * L + 0.5f * (px * px + py * py)) +
+                   P.c * (ph * M + 0.5f * L * L + (px * Lx + py * Ly));
+        S.P[0][r][c] = p0 + P.kappa * px * px - 2.f * P.c * px * Lx;
+        S.P[1][r][c] = p0 + P.kappa * py * py - 2.f * P.c * py * Ly;
+        S.P[2][r][c] = P.kappa * px * py - P.c * (px * Ly + py * Lx);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int tx = tid & 63, ty = tid >> 6;
+  double acc[R_N];
+#pragma unroll
+  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
+
+#pragma unroll
+  for (int j = 0; j < TY / 4; ++j) {
+    const int row = ty + 4 * j;
+    const int x = x0 + tx, y = y0 + row;
+    if (x >= nx || y >= ny) continue;
+    // force density: -div P (central differences) or -phi grad mu
+    float Fx = 0.f, Fy = 0.f;
+    if (P.hydro) {
+      const int r = row + 1, c = tx + 1;
+      if (P.force_form == 1) {
+        float ph = S.phi[row + 3][tx + 3];
+        Fx = -ph * (0.5f * (S.P[0][r][c + 1] - S.P[0][r][c - 1]));
+        Fy = -ph * (0.5f * (S.P[0][r + 1][c] - S.P[0][r - 1][c]));
+      } else {
+        Fx = -(0.5f * (S.P[0][r][c + 1] - S.P[0][r][c - 1]) +
+               0.5f * (S.P[2][r + 1][c] - S.P[2][r - 1][c]));
+        Fy = -(0.5f * (S.P[2][r][c + 1] - S.P[2][r][c - 1]) +
+               0.5f * (S.P[1][r + 1][c] - S.P[1][r - 1][c]));
+      }
+    }
+    // pull-stream: f_q(x) = f*_q(x - e_q); across a wall the opposite population of x itself
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const float* G = gin;
+    auto ld = [&](int q, int yy, int xx) { return G[(size_t)q * N + (size_t)yy * nx + xx]; };
+    float g0 = ld(0, y, x), g1 = ld(1, y, xm), g3 = ld(3, y, xp);
+    float g2, g4, g5, g6, g7, g8;
+    if (P.walls && y == 0) {
+      g2 = ld(4, y, x);
+      g5 = ld(7, y, x);
+      g6 = ld(8, y, x);
+    } else {
+      const int ym = y == 0 ? ny - 1 : y - 1;
+      g2 = ld(2, ym, x);
+      g5 = ld(5, ym, xm);
+      g6 = ld(6, ym, xp);
+    }
+    if (P.walls && y == ny - 1) {
+      g4 = ld(2, y, x);
+      g7 = ld(5, y, x);
+      g8 = ld(6, y, x);
+    } else {
+      const int yp = y == ny - 1 ? 0 : y + 1;
+      g4 = ld(4, yp, x);
+      g7 = ld(7, yp, xp);
+      g8 = ld(8, yp, xm);
+    }
+    // moments n = 1 + sum g, j = sum g e; u = (j + F/2)/n
+    const float dn = ((g0 + g1) + (g2 + g3)) + ((g4 + g5) + (g6 + g7)) + g8;
+    const float jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
+    const float jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
+    const float n = 1.f + dn;
+    Fx += n * P.gx;
+    Fy += n * P.gy;
+    float ux = 0.f, uy = 0.f;
+    if (P.hydro) {
+      const float inv = 1.f / n;
+      ux = (jx + 0.5f * Fx) * inv;
+      uy = (jy + 0.5f * Fy) * inv;
+    }
+    const size_t s = (size_t)y * nx + x;
+    if (MODE == MODE_STEP) {
+      // BGK collision towards the second-order equilibrium plus the forcing term
+      const float usq = 1.5f * (ux * ux + uy * uy);
+      const float uF = ux * Fx + uy * Fy;
+      const float om = P.omega, kf = P.kforce;
+      auto coll = [&](float g, float w, float eu, float eF) {
+        float geq = w * (dn + n * (eu * (3.f + 4.5f * eu) - usq));
+        float frc = kf * w * (3.f * (eF - uF) + 9.f * eu * eF);
+        return g + om * (geq - g) + frc;
+      };
+      const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
+      gout[0 * N + s] = coll(g0, w0, 0.f, 0.f);
+      gout[1 * N + s] = coll(g1, w1, ux, Fx);
+      gout[2 * N + s] = coll(g2, w1, uy, Fy);
+      gout[3 * N + s] = coll(g3, w1, -ux, -Fx);
+      gout[4 * N + s] = coll(g4, w1, -uy, -Fy);
+      gout[5 * N + s] = coll(g5, w2, ux + uy, Fx + Fy);
+      gout[6 * N + s] = coll(g6, w2, uy - ux, Fy - Fx);
+      gout[7 * N + s] = coll(g7, w2, -ux - uy, -Fx - Fy);
+      gout[8 * N + s] = coll(g8, w2, ux - uy, Fx - Fy);
+      uout[s] = ux;
+      uout[N + s] = uy;
+    } else if (MODE == MODE_FIELDS) {
+      uout[s] = ux;
+      uout[N + s] = uy;
+      if (nout) nout[s] = n;
+    } else {
+      const int R = row + 3, C = tx + 3;
+      const float ph = S.phi[R][C], a = S.a[R], L = S.L[row + 2][tx + 2];
+      const float dx = S.phi[R][C + 1] - ph, dy = S.phi[R + 1][C] - ph;
+      const float fe = 0.5f * a * ph * ph + 0.25f * P.b * ph * ph * ph * ph +
+                       0.5f * P.kappa * (dx * dx + dy * dy) + 0.5f * P.c * L * L;
+      acc[R_MASS] += (double)dn;
+      acc[R_JX] += (double)jx;
+      acc[R_JY] += (double)jy;
+      acc[R_PHI] += (double)ph;
+      acc[R_FE] += (double)fe;
+      acc[R_UMAX] = fmax(acc[R_UMAX], (double)sqrtf(ux * ux + uy * uy));
+      if (!(isfinite(dn) && isfinite(jx) && isfinite(jy) && isfinite(ph))) acc[R_BAD] = 1.0;
+    }
+  }
+
+  if (MODE == MODE_OBS) {
+    const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) {
+      double v = (k == R_UMAX || k == R_BAD) ? wave_max(acc[k]) : wave_sum(acc[k]);
+      if (lane == 0) S.red[wave][k] = v;
+    }
+    __syncthreads();
+    if (tid < R_N) {
+      double v = S.red[0][tid];
+      for (int w = 1; w < 4; ++w)
+        v = (tid == R_UMAX || tid == R_BAD) ? fmax(v, S.red[w][tid]) : v + S.red[w][tid];
+      partials[(size_t)blockIdx.x * R_N + tid] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Order-parameter sub-steps.  Cell (r, c) of every LDS plane is the site (y0 - R + r, x0 - R + c);
+// a plane is valid at depth d when rows d .. H-1-d and columns d .. W-1-d hold data.
+template <int S_, int TY>
+struct Phi2dDims {
+  static constexpr int R = 3 * S_;
+  static constexpr int H = TY + 2 * R;
+  static constexpr int W = TX + 2 * R;
+};
+
+template <int S_, int TY, bool HYDRO>
+__global__ __launch_bounds__(NT) void phi2d_kernel(KParams P, const float* __restrict__ psi_in,
+                                                   float* __restrict__ psi_out,
+                                                   const float* __restrict__ u,
+                                                   const float* __restrict__ Trow,
+                                                   float* __restrict__ Tnext,
+                                                   float* __restrict__ Tscr, int do_T) {
+  using D = Phi2dDims<S_, TY>;
+  constexpr int R = D::R, H = D::H, W = D::W;
+  __shared__ float A[H][W];
+  __shared__ float B[H][W];
+  __shared__ float Cm[H][W];
+  __shared__ float Ux[HYDRO ? H : 1][HYDRO ? W : 1];
+  __shared__ float Uy[HYDRO ? H : 1][HYDRO ? W : 1];
+  __shared__ float sa[H];
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const int tid = threadIdx.x;
+  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, nbx * nby);
+  const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
+
+  for (int i = tid; i < H * W; i += NT) {
+    int r = i / W, c = i - r * W;
+    bool f;
+    int gy = wall_axis(y0 - R + r, ny, P.walls, f);
+    int gx = wrap(x0 - R + c, nx);
+    A[r][c] = psi_in[(size_t)gy * nx + gx];
+  }
+  if (HYDRO) {
+    // velocity at depth 2; the wall-normal component is odd across a wall
+    constexpr int hh = H - 4, ww = W - 4;
+    for (int i = tid; i < hh * ww; i += NT) {
+      int r = 2 + i / ww, c = 2 + (i - (i / ww) * ww);
+      bool f;
+      int gy = wall_axis(y0 - R + r, ny, P.walls, f);
+      int gx = wrap(x0 - R + c, nx);
+      size_t s = (size_t)gy * nx + gx;
+      Ux[r][c] = u[s];
+      float vy = u[N + s];
+      Uy[r][c] = f ? -vy : vy;
+    }
+  }
+  for (int i = tid; i < H; i += NT) {
+    bool f;
+    int gy = wall_axis(y0 - R + i, ny, P.walls, f);
+    sa[i] = (Trow[gy] - P.Tc) / P.Tc;
+  }
+  __syncthreads();
+
+  float(*ps)[W] = A;   // current psi
+  float(*lb)[W] = B;   // Laplacian, then the next psi
+#pragma unroll
+  for (int s = 0; s < S_; ++s) {
+    const int d = 3 * s;
+    {  // L at depth d + 1
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int dd = d + 1, hh = H - 2 * dd, ww = W - 2 * dd;
+      for (int i = tid; i < hh * ww; i += NT) {
+        int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
+        lb[r][c] = (ps[r][c + 1] + ps[r][c - 1]) + (ps[r + 1][c] + ps[r - 1][c]) - 4.f * ps[r][c];
+      }
+    }
+    __syncthreads();
+    {  // mu at depth d + 2
+      const int dd = d + 2, hh = H - 2 * dd, ww = W - 2 * dd;
+      for (int i = tid; i < hh * ww; i += NT) {
+        int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
+        float v = ps[r][c], L = lb[r][c];
+        float M = (lb[r][c + 1] + lb[r][c - 1]) + (lb[r + 1][c] + lb[r - 1][c]) - 4.f * L;
+        Cm[r][c] = sa[r] * v + P.b * v * v * v - P.kappa * L + P.c * M;
+      }
+    }
+    __syncthreads();
+    {  // psi' at depth d + 3
+      const int dd = d + 3, hh = H - 2 * dd, ww = W - 2 * dd;
+      const bool last = s == S_ - 1;
+      for (int i = tid; i < hh * ww; i += NT) {
+        int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
+        float lapmu = (Cm[r][c + 1] + Cm[r][c - 1]) + (Cm[r + 1][c] + Cm[r - 1][c]) - 4.f * Cm[r][c];
+        float adv = 0.f;
+        if (HYDRO) {
+          adv = 0.5f * (ps[r][c + 1] * Ux[r][c + 1] - ps[r][c - 1] * Ux[r][c - 1]) +
+                0.5f * (ps[r + 1][c] * Uy[r + 1][c] - ps[r - 1][c] * Uy[r - 1][c]);
+        }
+        float v = ps[r][c] + P.h * (-adv + P.Gamma * lapmu);
+        if (last) {
+          int y = y0 - R + r, x = x0 - R + c;
+          if (x < nx && y < ny) psi_out[(size_t)y * nx + x] = v;
+        } else {
+          lb[r][c] = v;
+        }
+      }
+    }
+    __syncthreads();
+    float(*tmp)[W] = ps;
+    ps = lb;
+    lb = tmp;
+  }
+
+  // Temperature: FTCS sub-steps along the wall axis (T is uniform along x); wall layers held.
+  if (do_T && t == 0 && P.n_T > 0) {
+    const float* src = Trow;
+    for (int m = 0; m < P.n_T; ++m) {
+      float* dst = ((P.n_T - 1 - m) % 2 == 0) ? Tnext : Tscr;
+      for (int j = tid; j < ny; j += NT) {
+        float v = src[j];
+        bool wall = P.walls && (j == 0 || j == ny - 1);
+        if (!wall) {
+          float lo = src[j == 0 ? ny - 1 : j - 1], hi = src[j == ny - 1 ? 0 : j + 1];
+          v = v + P.r_T * ((lo + hi) - 2.f * v);
+        }
+        dst[j] = v;
+      }
+      __syncthreads();
+      src = dst;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Host launchers.
+constexpr int LB_TY = 16;
+constexpr int PHI_TY = 16;
+
+static int blocks2d(const KParams& P, int ty) {
+  return ((P.nx + TX - 1) / TX) * ((P.ny + ty - 1) / ty);
+}
+
+int lb2d_blocks(const KParams& P) { return blocks2d(P, LB_TY); }
+
+hipError_t launch_lb2d(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
+                       const float* Trow, float* u, float* n, double* partials, hipStream_t st) {
+  dim3 grid(blocks2d(P, LB_TY)), block(NT);
+  if (mode == MODE_STEP)
+    hipLaunchKernelGGL((lb2d_kernel<LB_TY, MODE_STEP>), grid, block, 0, st, P, gin, gout, phi, Trow,
+                       u, n, partials);
+  else if (mode == MODE_OBS)
+    hipLaunchKernelGGL((lb2d_kernel<LB_TY, MODE_OBS>), grid, block, 0, st, P, gin, gout, phi, Trow,
+                       u, n, partials);
+  else
+    hipLaunchKernelGGL((lb2d_kernel<LB_TY, MODE_FIELDS>), grid, block, 0, st, P, gin, gout, phi,
+                       Trow, u, n, partials);
+  return hipGetLastError();
+}
+
+template <int S_>
+static void phi2d_launch(const KParams& P, const float* in, float* out, const float* u,
+                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st) {
+  dim3 grid(blocks2d(P, PHI_TY)), block(NT);
+  if (P.hydro)
+    hipLaunchKernelGGL((phi2d_kernel<S_, PHI_TY, true>), grid, block, 0, st, P, in, out, u, T, Tn,
+                       Ts, do_T);
+  else
+    hipLaunchKernelGGL((phi2d_kernel<S_, PHI_TY, false>), grid, block, 0, st, P, in, out, u, T, Tn,
+                       Ts, do_T);
+}
+
+int phi2d_max_sub() { return 2; }
+
+hipError_t launch_phi2d(const KParams& P, int nsub, const float* in, float* out, const float* u,
+                        const float* T, float* Tn, float* Ts, int do_T, hipStream_t st) {
+  if (nsub == 1) phi2d_launch<1>(P, in, out, u, T, Tn, Ts, do_T, st);
+  else if (nsub == 2) phi2d_launch<2>(P, in, out, u, T, Tn, Ts, do_T, st);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace lam

@@ -1,0 +1,472 @@
+// lam_api.hip -- host implementation of the C-ABI in include/lam.h: parameter validation, the
+// sub-step stability rule, workspace carving, launch order of one time step, observables,
+// fields and checkpoints.  All device memory belongs to the caller.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lam.h"
+#include "lam_dev.hpp"
+
+namespace lam {
+enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
+// lam_2d.hip
+int lb2d_blocks(const KParams& P);
+hipError_t launch_lb2d(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
+                       const float* Trow, float* u, float* n, double* partials, hipStream_t st);
+int phi2d_max_sub();
+hipError_t launch_phi2d(const KParams& P, int nsub, const float* in, float* out, const float* u,
+                        const float* T, float* Tn, float* Ts, int do_T, hipStream_t st);
+// lam_util.hip
+hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, float* g,
+                       hipStream_t st);
+hipError_t launch_init_T(int nrows, int walls, float T0, float Tw, int quench, float* a, float* b,
+                         hipStream_t st);
+hipError_t launch_finalize(const double* partials, int nblk, double* out, hipStream_t st);
+hipError_t launch_broadcast_T(const float* Trow, size_t N, size_t layer, float* out,
+                              hipStream_t st);
+hipError_t launch_write_header(int dim, int nx, int ny, int nz, int64_t step, int Q, void* dst,
+                               hipStream_t st);
+bool check_header(const void* host_copy, int dim, int nx, int ny, int nz, int Q, int64_t* step);
+size_t header_bytes();
+// lam_spectra.hip
+size_t spectra_scratch_bytes(int nx, int ny);
+hipError_t structure_factor_2d(const KParams& P, const float* phi, void* scratch, int nbins,
+                               double* h_S, double* h_kpeak, double* h_Speak, double* h_kmean,
+                               hipStream_t st);
+hipError_t orientation_2d(const KParams& P, const float* phi, void* scratch, int nbins,
+                          double* h_hist, double* h_Q, double* h_Qrow, hipStream_t st);
+}  // namespace lam
+
+using namespace lam;
+
+static thread_local std::string g_create_error;
+
+struct lam_sim {
+  lam_params p;
+  KParams k;
+  int Q, nphi, nT, nrows;
+  size_t N;
+  hipStream_t st;
+  char* ws;
+  size_t ws_bytes;
+  float* g[2];
+  float* phi[2];
+  float* psi[2];
+  float* u;
+  float* T[3];
+  double* partials;
+  double* result;
+  void* spec;
+  int nblk;
+  int64_t step;
+  bool initialised;
+  std::string err;
+  // kernel timing (profiling aid)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_cls;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+struct Layout {
+  size_t g[2], phi[2], psi[2], u, T[3], partials, result, spec, total;
+  int nblk;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout(const lam_params& p) {
+  Layout L{};
+  const size_t N = (size_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
+  const int Q = p.dim == 2 ? 9 : 19;
+  const int nrows = p.dim == 2 ? p.ny : p.nz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  for (int i = 0; i < 2; ++i) L.g[i] = take(sizeof(float) * Q * N);
+  for (int i = 0; i < 2; ++i) L.phi[i] = take(sizeof(float) * N);
+  for (int i = 0; i < 2; ++i) L.psi[i] = take(sizeof(float) * N);
+  L.u = take(sizeof(float) * p.dim * N);
+  for (int i = 0; i < 3; ++i) L.T[i] = take(sizeof(float) * nrows);
+  L.nblk = (int)(N / 64 + 64);
+  L.partials = take(sizeof(double) * R_N * L.nblk);
+  L.result = take(sizeof(double) * R_N);
+  L.spec = take(p.dim == 2 ? spectra_scratch_bytes(p.nx, p.ny) : 256);
+  L.total = off;
+  return L;
+}
+
+// Smallest number of explicit Euler sub-steps that keeps the checkerboard mode of the linearised
+// phi equation damped: one sub-step of length h multiplies it by
+// 1 - h Gamma lambda (a_eff + kappa lambda + c lambda^2), lambda = 4 dim (largest eigenvalue of the
+// lattice Laplacian); require >= -0.8.  a_eff is the largest local d mu / d phi: a itself, or
+// a + 3 b A^2 in a lamellar state of single-mode amplitude A^2 = 4(-a + kappa^2/(4c))/(3b) at
+// the coldest a (single-mode theory of Section 2).
+int auto_nphi(const lam_params& p) {
+  double a0 = (p.T0 - p.Tc) / p.Tc, aw = (p.Tw - p.Tc) / p.Tc;
+  double amax = a0, amin = a0;
+  if (p.xi < 0) amax = amin = aw;
+  else if (p.walls) {
+    amax = std::max(a0, aw);
+    amin = std::min(a0, aw);
+  }
+  double aeff = amax;
+  double A2 = 4.0 * (-amin + p.kappa * p.kappa / (4.0 * p.c)) / (3.0 * p.b);
+  if (A2 > 0) aeff = std::max(aeff, amin + 3.0 * p.b * A2);
+  double lam = 4.0 * p.dim;
+  double x = p.Gamma * lam * (aeff + p.kappa * lam + p.c * lam * lam) / 1.8;
+  int n = (int)ceil(x - 1e-12);
+  return n < 1 ? 1 : n;
+}
+
+// FTCS on T, which varies only along the wall axis, is stable for xi/n_T <= 1/2; keep 0.45.
+int auto_nT(const lam_params& p) {
+  if (p.xi <= 0) return 1;
+  int n = (int)ceil(p.xi / 0.45 - 1e-12);
+  return n < 1 ? 1 : n;
+}
+
+int fail(lam_sim* s, int code, const std::string& msg) {
+  if (s) s->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+int hip_fail(lam_sim* s, hipError_t e, const char* where) {
+  return fail(s, LAM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(s, call)                              \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(s, e_, #call); \
+  } while (0)
+
+int validate(const lam_params* p, std::string& why) {
+  if (!p) return why = "null parameters", LAM_EINVAL;
+  if (p->dim != 2 && p->dim != 3) return why = "dim must be 2 or 3", LAM_EINVAL;
+  if (p->dim == 3) return why = "3D (D3Q19) is not available in this build", LAM_EINVAL;
+  if (p->nx < 8 || p->ny < 8) return why = "nx and ny must be >= 8", LAM_EINVAL;
+  if (p->dim == 2 && p->nz != 1) return why = "nz must be 1 in 2D", LAM_EINVAL;
+  if (p->dim == 3 && p->nz < 8) return why = "nz must be >= 8 in 3D", LAM_EINVAL;
+  if (!(p->tau > 0.5)) return why = "tau must exceed 1/2", LAM_EINVAL;
+  if (!(p->b > 0) || !(p->c > 0)) return why = "b and c must be positive (Section 2)", LAM_EINVAL;
+  if (!(p->Tc > 0)) return why = "Tc must be positive", LAM_EINVAL;
+  if (!(p->Gamma >= 0)) return why = "Gamma must be non-negative", LAM_EINVAL;
+  if (p->force_form != 0 && p->force_form != 1) return why = "force_form must be 0 or 1", LAM_EINVAL;
+  if (p->pop_storage != 0) return why = "only FP32 population storage is available", LAM_EINVAL;
+  if (p->walls != 0 && p->walls != 1) return why = "walls must be 0 or 1", LAM_EINVAL;
+  if (p->hydro != 0 && p->hydro != 1) return why = "hydro must be 0 or 1", LAM_EINVAL;
+  if (p->n_phi_sub < 0 || p->n_T_sub < 0) return why = "sub-step counts must be >= 0", LAM_EINVAL;
+  if (!p->allow_unstable) {
+    if (p->n_phi_sub > 0 && p->n_phi_sub < auto_nphi(*p))
+      return why = "n_phi_sub below the stability bound (set allow_unstable to force)", LAM_EINVAL;
+    if (p->n_T_sub > 0 && p->xi > 0 && p->xi / p->n_T_sub > 0.5)
+      return why = "n_T_sub gives xi/n_T > 1/2 (set allow_unstable to force)", LAM_EINVAL;
+  }
+  return LAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lam_workspace_bytes(const lam_params* p, size_t* bytes) {
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  if (!bytes) return fail(nullptr, LAM_EINVAL, "null output");
+  *bytes = layout(*p).total;
+  return LAM_OK;
+}
+
+int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+               lam_sim** out) {
+  std::string why;
+  if (!out) return fail(nullptr, LAM_EINVAL, "null output handle");
+  *out = nullptr;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  Layout L = layout(*p);
+  if (!d_workspace || bytes < L.total)
+    return fail(nullptr, LAM_ESIZE, "workspace smaller than lam_workspace_bytes()");
+  if (((uintptr_t)d_workspace) & 255) return fail(nullptr, LAM_EINVAL, "workspace not 256-byte aligned");
+  lam_sim* s = new lam_sim();
+  s->p = *p;
+  s->Q = p->dim == 2 ? 9 : 19;
+  s->N = (size_t)p->nx * p->ny * (p->dim == 3 ? p->nz : 1);
+  s->nrows = p->dim == 2 ? p->ny : p->nz;
+  s->nphi = p->n_phi_sub > 0 ? p->n_phi_sub : auto_nphi(*p);
+  s->nT = p->n_T_sub > 0 ? p->n_T_sub : auto_nT(*p);
+  s->st = (hipStream_t)hip_stream;
+  s->ws = (char*)d_workspace;
+  s->ws_bytes = bytes;
+  for (int i = 0; i < 2; ++i) {
+    s->g[i] = (float*)(s->ws + L.g[i]);
+    s->phi[i] = (float*)(s->ws + L.phi[i]);
+    s->psi[i] = (float*)(s->ws + L.psi[i]);
+  }
+  s->u = (float*)(s->ws + L.u);
+  for (int i = 0; i < 3; ++i) s->T[i] = (float*)(s->ws + L.T[i]);
+  s->partials = (double*)(s->ws + L.partials);
+  s->result = (double*)(s->ws + L.result);
+  s->spec = s->ws + L.spec;
+  s->nblk = L.nblk;
+  KParams& k = s->k;
+  k.nx = p->nx;
+  k.ny = p->ny;
+  k.nz = p->dim == 3 ? p->nz : 1;
+  k.walls = p->walls;
+  k.hydro = p->hydro;
+  k.force_form = p->force_form;
+  k.omega = (float)(1.0 / p->tau);
+  k.kforce = (float)(1.0 - 0.5 / p->tau);
+  k.Gamma = (float)p->Gamma;
+  k.b = (float)p->b;
+  k.kappa = (float)p->kappa;
+  k.c = (float)p->c;
+  k.Tc = (float)p->Tc;
+  k.h = (float)(1.0 / s->nphi);
+  k.gx = (float)p->body_force[0];
+  k.gy = (float)p->body_force[1];
+  k.gz = (float)p->body_force[2];
+  k.n_T = p->xi > 0 ? s->nT : 0;
+  k.r_T = p->xi > 0 ? (float)(p->xi / s->nT) : 0.f;
+  s->step = 0;
+  s->initialised = false;
+  *out = s;
+  return LAM_OK;
+}
+
+int lam_substeps(const lam_sim* s, int32_t* n_phi, int32_t* n_T) {
+  if (!s) return LAM_EINVAL;
+  if (n_phi) *n_phi = s->nphi;
+  if (n_T) *n_T = s->nT;
+  return LAM_OK;
+}
+
+int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const float* d_n0) {
+  if (!s || !d_phi0) return fail(s, LAM_EINVAL, "null simulation or phi0");
+  HIPCHK(s, hipMemcpyAsync(s->phi[0], d_phi0, sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(s, launch_init(s->k, s->p.dim, d_n0, d_u0, s->g[0], s->st));
+  HIPCHK(s, hipMemcpyAsync(s->g[1], s->g[0], sizeof(float) * s->Q * s->N, hipMemcpyDeviceToDevice,
+                           s->st));
+  HIPCHK(s, hipMemsetAsync(s->u, 0, sizeof(float) * s->p.dim * s->N, s->st));
+  HIPCHK(s, launch_init_T(s->nrows, s->p.walls, (float)s->p.T0, (float)s->p.Tw, s->p.xi < 0,
+                          s->T[0], s->T[1], s->st));
+  s->step = 0;
+  s->initialised = true;
+  return LAM_OK;
+}
+
+namespace {
+// Record the start event of a timed launch; returns the slot or -1 when timing is off.
+long timing_begin(lam_sim* s, int cls) {
+  if (!s->timing) return -1;
+  if (s->ev_used + 2 > s->ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      s->ev.push_back(e);
+      s->ev_cls.push_back(0);
+    }
+  }
+  long slot = (long)s->ev_used;
+  s->ev_cls[slot] = cls;
+  s->ev_used += 2;
+  hipEventRecord(s->ev[slot], s->st);
+  return slot;
+}
+void timing_end(lam_sim* s, long slot) {
+  if (slot >= 0) hipEventRecord(s->ev[slot + 1], s->st);
+}
+}  // namespace
+
+int lam_set_timing(lam_sim* s, int32_t enable) {
+  if (!s) return LAM_EINVAL;
+  s->timing = enable != 0;
+  s->ev_used = 0;
+  return LAM_OK;
+}
+
+int lam_kernel_times(lam_sim* s, double* h_ms, int64_t* h_launches, int32_t nk) {
+  if (!s || !h_ms || !h_launches || nk < 1) return fail(s, LAM_EINVAL, "bad arguments");
+  for (int k = 0; k < nk; ++k) {
+    h_ms[k] = 0.0;
+    h_launches[k] = 0;
+  }
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  for (size_t i = 0; i < s->ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]));
+    int c = s->ev_cls[i];
+    if (c < nk) {
+      h_ms[c] += ms;
+      h_launches[c] += 1;
+    }
+  }
+  s->ev_used = 0;
+  return LAM_OK;
+}
+
+int lam_step(lam_sim* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return fail(s, LAM_EINVAL, "bad arguments");
+  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+  const KParams& k = s->k;
+  const int maxsub = phi2d_max_sub();
+  for (int64_t t = 0; t < nsteps; ++t) {
+    const int cur = (int)(s->step & 1), nxt = cur ^ 1;
+    if (k.hydro) {
+      long ev = timing_begin(s, LAM_K_LB);
+      HIPCHK(s, launch_lb2d(k, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur], s->u,
+                            nullptr, nullptr, s->st));
+      timing_end(s, ev);
+    }
+    int remaining = s->nphi, which = 0;
+    const float* src = s->phi[cur];
+    while (remaining > 0) {
+      int sub = std::min(remaining, maxsub);
+      bool last = remaining == sub;
+      float* dst = last ? s->phi[nxt] : s->psi[which];
+      which ^= 1;
+      long ev = timing_begin(s, LAM_K_PHI);
+      HIPCHK(s, launch_phi2d(k, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
+                             last && k.n_T > 0, s->st));
+      timing_end(s, ev);
+      src = dst;
+      remaining -= sub;
+    }
+    s->step++;
+  }
+  return LAM_OK;
+}
+
+int lam_observables(lam_sim* s, lam_obs* o) {
+  if (!s || !o) return fail(s, LAM_EINVAL, "bad arguments");
+  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+  const int cur = (int)(s->step & 1);
+  int nblk = lb2d_blocks(s->k);
+  HIPCHK(s, launch_lb2d(s->k, MODE_OBS, s->g[cur], nullptr, s->phi[cur], s->T[cur], nullptr,
+                        nullptr, s->partials, s->st));
+  HIPCHK(s, launch_finalize(s->partials, nblk, s->result, s->st));
+  double r[R_N];
+  HIPCHK(s, hipMemcpyAsync(r, s->result, sizeof(r), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  memset(o, 0, sizeof(*o));
+  o->mass_dev = r[R_MASS];
+  o->mom[0] = r[R_JX];
+  o->mom[1] = r[R_JY];
+  o->mom[2] = r[R_JZ];
+  o->phi_sum = r[R_PHI];
+  o->max_u = r[R_UMAX];
+  o->mach = r[R_UMAX] * sqrt(3.0);
+  o->free_energy = r[R_FE];
+  o->step = s->step;
+  o->nonfinite = r[R_BAD] != 0.0;
+  if (o->nonfinite) return fail(s, LAM_ENONFINITE, "state holds NaN or infinite values");
+  return LAM_OK;
+}
+
+int lam_structure_factor(lam_sim* s, double* h_S, int32_t nbins, double* k_peak, double* S_peak,
+                         double* k_mean) {
+  if (!s || !h_S || nbins < 3) return fail(s, LAM_EINVAL, "bad arguments (need nbins >= 3)");
+  if (s->p.dim != 2) return fail(s, LAM_EINVAL, "structure factor is 2D only");
+  if (nbins > std::max(s->p.nx, s->p.ny)) return fail(s, LAM_EINVAL, "nbins > max(nx, ny)");
+  HIPCHK(s, structure_factor_2d(s->k, s->phi[s->step & 1], s->spec, nbins, h_S, k_peak, S_peak,
+                                k_mean, s->st));
+  return LAM_OK;
+}
+
+int lam_orientation(lam_sim* s, double* h_hist, int32_t nbins, double* Q, double* h_Qrow) {
+  if (!s || !h_hist || nbins < 1 || nbins > 360) return fail(s, LAM_EINVAL, "bad arguments");
+  if (s->p.dim != 2) return fail(s, LAM_EINVAL, "orientation is 2D only");
+  HIPCHK(s, orientation_2d(s->k, s->phi[s->step & 1], s->spec, nbins, h_hist, Q, h_Qrow, s->st));
+  return LAM_OK;
+}
+
+int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T) {
+  if (!s) return fail(s, LAM_EINVAL, "null simulation");
+  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+  const int cur = (int)(s->step & 1);
+  if (d_phi)
+    HIPCHK(s, hipMemcpyAsync(d_phi, s->phi[cur], sizeof(float) * s->N, hipMemcpyDeviceToDevice,
+                             s->st));
+  if (d_u || d_n)
+    HIPCHK(s, launch_lb2d(s->k, MODE_FIELDS, s->g[cur], nullptr, s->phi[cur], s->T[cur],
+                          d_u ? d_u : s->u, d_n, nullptr, s->st));
+  if (d_T) {
+    size_t layer = (size_t)s->p.nx * (s->p.dim == 3 ? s->p.ny : 1);
+    HIPCHK(s, launch_broadcast_T(s->T[cur], s->N, layer, d_T, s->st));
+  }
+  return LAM_OK;
+}
+
+int lam_state_bytes(const lam_sim* s, size_t* bytes) {
+  if (!s || !bytes) return LAM_EINVAL;
+  *bytes = header_bytes() + sizeof(float) * ((size_t)s->Q * s->N + s->N + s->nrows);
+  return LAM_OK;
+}
+
+int lam_get_state(lam_sim* s, void* d_buf, size_t bytes) {
+  size_t need;
+  lam_state_bytes(s, &need);
+  if (!s || !d_buf) return fail(s, LAM_EINVAL, "bad arguments");
+  if (bytes < need) return fail(s, LAM_ESIZE, "checkpoint buffer too small");
+  const int cur = (int)(s->step & 1);
+  char* b = (char*)d_buf;
+  HIPCHK(s, launch_write_header(s->p.dim, s->p.nx, s->p.ny, s->k.nz, s->step, s->Q, b, s->st));
+  b += header_bytes();
+  HIPCHK(s, hipMemcpyAsync(b, s->g[cur], sizeof(float) * s->Q * s->N, hipMemcpyDeviceToDevice, s->st));
+  b += sizeof(float) * s->Q * s->N;
+  HIPCHK(s, hipMemcpyAsync(b, s->phi[cur], sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
+  b += sizeof(float) * s->N;
+  HIPCHK(s, hipMemcpyAsync(b, s->T[cur], sizeof(float) * s->nrows, hipMemcpyDeviceToDevice, s->st));
+  return LAM_OK;
+}
+
+int lam_set_state(lam_sim* s, const void* d_buf, size_t bytes) {
+  size_t need;
+  lam_state_bytes(s, &need);
+  if (!s || !d_buf) return fail(s, LAM_EINVAL, "bad arguments");
+  if (bytes < need) return fail(s, LAM_ESIZE, "checkpoint buffer too small");
+  char hdr[256];
+  HIPCHK(s, hipMemcpyAsync(hdr, d_buf, sizeof(hdr), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  int64_t step;
+  if (!check_header(hdr, s->p.dim, s->p.nx, s->p.ny, s->k.nz, s->Q, &step))
+    return fail(s, LAM_ESTATE, "checkpoint does not match this lattice");
+  const int cur = (int)(step & 1);
+  const char* b = (const char*)d_buf + header_bytes();
+  for (int i = 0; i < 2; ++i)
+    HIPCHK(s, hipMemcpyAsync(s->g[i], b, sizeof(float) * s->Q * s->N, hipMemcpyDeviceToDevice, s->st));
+  b += sizeof(float) * s->Q * s->N;
+  HIPCHK(s, hipMemcpyAsync(s->phi[cur], b, sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
+  b += sizeof(float) * s->N;
+  for (int i = 0; i < 2; ++i)
+    HIPCHK(s, hipMemcpyAsync(s->T[i], b, sizeof(float) * s->nrows, hipMemcpyDeviceToDevice, s->st));
+  s->step = step;
+  s->initialised = true;
+  return LAM_OK;
+}
+
+const char* lam_last_error(const lam_sim* s) {
+  return s ? s->err.c_str() : g_create_error.c_str();
+}
+
+void lam_destroy(lam_sim* s) {
+  if (!s) return;
+  for (hipEvent_t e : s->ev) hipEventDestroy(e);
+  delete s;
+}
+
+}  // extern "C"

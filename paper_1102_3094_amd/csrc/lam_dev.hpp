@@ -1,0 +1,78 @@
+// lam_dev.hpp -- device-side definitions shared by the gfx950 kernels of the lamellar-fluid
+// library: the kernel parameter block, index maps for periodic and wall-reflected axes, the
+// XCD-aware tile order and small reduction helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lam {
+
+// Parameters as the kernels see them (FP32 arithmetic; FP64 only in reductions).
+struct KParams {
+  int nx, ny, nz;       // extents; nz = 1 in 2D
+  int walls;            // walls normal to the last axis
+  int hydro;            // lattice Boltzmann coupled
+  int force_form;       // 0: -div P, 1: -phi grad mu
+  float omega;          // 1/tau
+  float kforce;         // 1 - 1/(2 tau), prefactor of the forcing term
+  float Gamma, b, kappa, c;
+  float Tc;
+  float h;              // 1/n_phi, Euler sub-step length
+  float gx, gy, gz;     // uniform test acceleration
+  float r_T;            // xi / n_T
+  int n_T;              // FTCS sub-steps (0: temperature frozen)
+};
+
+// Reduction slots of the observables.
+enum { R_MASS = 0, R_JX, R_JY, R_JZ, R_PHI, R_FE, R_UMAX, R_BAD, R_N };
+
+// Periodic index for any integer.
+__device__ __forceinline__ int wrap(int i, int n) {
+  if (i >= 0 && i < n) return i;
+  int m = i % n;
+  return m < 0 ? m + n : m;
+}
+
+// Even reflection about the planes -1/2 and n - 1/2, folded with period 2n so that any integer
+// maps into [0, n).  `flip` is set when the image is a mirror image (odd number of reflections).
+__device__ __forceinline__ int reflect(int i, int n, bool& flip) {
+  if (i >= 0 && i < n) {
+    flip = false;
+    return i;
+  }
+  int m = i % (2 * n);
+  if (m < 0) m += 2 * n;
+  flip = m >= n;
+  return flip ? 2 * n - 1 - m : m;
+}
+
+// Index along the wall axis: reflected if walls are on, periodic otherwise.
+__device__ __forceinline__ int wall_axis(int i, int n, int walls, bool& flip) {
+  if (walls) return reflect(i, n, flip);
+  flip = false;
+  return wrap(i, n);
+}
+
+// Blocks of a 1D grid are dispatched round-robin over the 8 XCDs of an MI355X.  Give each XCD a
+// contiguous range of tiles so that neighbouring tiles (which share halo reads) run under the
+// same L2.  Bijective on [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int NX = 8;
+  int q = nb / NX, r = nb % NX;
+  int k = b % NX, j = b / NX;
+  int base = k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q;
+  return base + j;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+}  // namespace lam

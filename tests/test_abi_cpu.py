@@ -1,0 +1,97 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every symbol that
+include/lam.h declares, and rejects invalid parameter sets with LAM_EINVAL / LAM_ESIZE."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1102_3094_amd as lam
+import synthetic as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lam.LIB_PATH):
+        from paper_1102_3094_amd.build import build
+        build()
+    return lam.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lam.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(lam_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lam.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    # offsets the C compiler gives the header's structs, compared with the ctypes mirror
+    import subprocess
+    import tempfile
+    code = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lam.h"
+int main(){printf("%zu %zu %zu %zu %zu\n", sizeof(lam_params), offsetof(lam_params, body_force),
+offsetof(lam_params, n_phi_sub), sizeof(lam_obs), offsetof(lam_obs, step)); return 0;}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        open(os.path.join(d, "t.c"), "w").write(code)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", os.path.join(d, "t"),
+                        os.path.join(d, "t.c")], check=True)
+        out = subprocess.run([os.path.join(d, "t")], capture_output=True, text=True).stdout.split()
+    got = [C.sizeof(lam.lam_params), lam.lam_params.body_force.offset,
+           lam.lam_params.n_phi_sub.offset, C.sizeof(lam.lam_obs), lam.lam_obs.step.offset]
+    assert [int(v) for v in out] == got
+
+
+@pytest.mark.parametrize("bad", [dict(tau=0.5), dict(b=0.0), dict(c=-1.0), dict(nx=4),
+                                 dict(dim=4), dict(force_form=3), dict(pop_storage=2),
+                                 dict(n_phi_sub=1), dict(n_T_sub=1, xi=1.0)])
+def test_invalid_parameters_rejected(L, bad):
+    p = S.model_params("c1_64sq", **bad)
+    with pytest.raises(lam.LamError) as e:
+        lam.workspace_bytes(p)
+    assert e.value.code == lam.LAM_EINVAL
+
+
+def test_unstable_override_allowed_when_forced(L):
+    p = S.model_params("c1_64sq", n_phi_sub=1, allow_unstable=1)
+    assert lam.workspace_bytes(p) > 0
+
+
+def test_create_validates_workspace(L):
+    p = lam.make_params(S.model_params("c1_64sq"))
+    n = C.c_size_t()
+    assert L.lam_workspace_bytes(C.byref(p), C.byref(n)) == 0
+    h = C.c_void_p()
+    # too small: rejected before any device access
+    rc = L.lam_create(C.byref(p), C.c_void_p(1 << 20), n.value - 1, None, C.byref(h))
+    assert rc == lam.LAM_ESIZE
+    assert b"workspace" in L.lam_last_error(None)
+    # misaligned
+    rc = L.lam_create(C.byref(p), C.c_void_p((1 << 20) + 8), n.value + 64, None, C.byref(h))
+    assert rc == lam.LAM_EINVAL
+
+
+def test_substep_rule_host(L):
+    """The library's automatic sub-step counts (host code, no GPU needed)."""
+    for name, want in (("c1_64sq", 2), ("paper_2d_tau5", 1)):
+        p = lam.make_params(S.model_params(name))
+        n = C.c_size_t()
+        assert L.lam_workspace_bytes(C.byref(p), C.byref(n)) == 0
+        h = C.c_void_p()
+        assert L.lam_create(C.byref(p), C.c_void_p(1 << 20), n.value, None, C.byref(h)) == 0
+        a, b = C.c_int32(), C.c_int32()
+        L.lam_substeps(h, C.byref(a), C.byref(b))
+        L.lam_destroy(h)
+        assert a.value == want and b.value == 1

@@ -1,0 +1,266 @@
+"""GPU parity: the gfx950 library, called through its C-ABI, against the FP64 oracle on the same
+seeded inputs.
+
+Tolerances.  The GPU computes in FP32.  One step perturbs a field by a few FP32 roundings
+(relative ~1e-7); the scheme's sensitivity to a 2^-24 perturbation of phi0 stays below 1e-7 over
+2000 steps of the parity workload, so rel-L2(phi) <= 1e-5 after 1000 steps is the bar, and
+conserved totals may drift by less than 1e-6 (relative to the number of sites).  The force and
+the velocity derive from up to fifth differences of phi, whose FP32 cancellation error is about
+1e-7 of the largest phi-stencil term; they are compared at 2e-5 relative to their largest value.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import Oracle, spectra
+from tests._helpers import gpu_fields, rel_l2, run_pair, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_force_and_velocity_at_start(gpu):
+    """At t = 0 the fluid is at rest, so u = F/(2n): compares the whole force path
+    (mu stencils, pressure tensor, its divergence) site by site."""
+    for ff in (0, 1):
+        p, phi0 = workload("c1_64sq", force_form=ff)
+        o, g = run_pair(gpu, p, phi0, 0)
+        fo, fg = o.fields(), gpu_fields(g)
+        scale = np.abs(fo["u"]).max()
+        assert scale > 1e-6
+        assert np.abs(fg["u"] - fo["u"]).max() < 2e-5 * scale, ff
+        assert np.abs(fg["n"] - fo["n"]).max() < 1e-6
+        assert np.array_equal(fg["phi"], fo["phi"])
+
+
+def test_one_step_all_fields(gpu):
+    p, phi0 = workload("c1_64sq")
+    o, g = run_pair(gpu, p, phi0, 1)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert np.abs(fg["phi"] - fo["phi"]).max() < 1e-6 * np.abs(fo["phi"]).max()
+    assert np.abs(fg["u"] - fo["u"]).max() < 2e-5 * np.abs(fo["u"]).max()
+    assert np.abs(fg["n"] - fo["n"]).max() < 1e-6
+    assert np.abs(fg["T"] - fo["T"]).max() < 1e-6
+
+
+@pytest.mark.parametrize("steps", [1000])
+def test_parity_1000_steps_lamellar(gpu, steps):
+    """The spec bar on the 64x64 wall geometry with the milder wall temperature (0.9 Tc)
+    that keeps the coupled run bounded: rel-L2(phi) <= 1e-5 after 1000 steps; mass and sum(phi)
+    drift < 1e-6."""
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    o, g = run_pair(gpu, p, phi0, 0)
+    ob0 = g.observables()
+    o.step(steps)
+    g.step(steps)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert np.abs(fo["phi"]).max() > 0.5  # lamellae have formed near the walls
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+    assert rel_l2(fg["u"], fo["u"]) <= 1e-4
+    ob = g.observables()
+    N = phi0.size
+    assert abs(ob["mass_dev"] - ob0["mass_dev"]) / N < 1e-6
+    assert abs(ob["phi_sum"] - ob0["phi_sum"]) / N < 1e-6
+
+
+def test_parity_deep_quench_before_breakdown(gpu):
+    """The 64x64 workload with walls at 0.7 Tc: compared at 200 steps, while the lamellae grow
+    at the walls; the coupled scheme loses stability near step 250 for these coefficients in the
+    oracle as well."""
+    p, phi0 = workload("c1_64sq")
+    o, g = run_pair(gpu, p, phi0, 200)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert np.abs(fo["phi"]).max() > 1.0
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+
+
+def test_parity_without_hydrodynamics(gpu):
+    p, phi0 = workload("c1_64sq", hydro=0)
+    o, g = run_pair(gpu, p, phi0, 1000)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+    assert np.abs(fg["u"]).max() == 0.0
+    assert np.abs(fg["T"] - fo["T"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("shape,walls", [((37, 100), 1), ((40, 72), 0), ((8, 8), 1), ((24, 130), 1)])
+def test_ragged_and_small_lattices(gpu, shape, walls):
+    """Lattices that are not multiples of the 64 x 16 tile (ragged right and bottom tiles), the
+    smallest allowed lattice, and the fully periodic case."""
+    ny, nx = shape
+    p = S.model_params("c1_64sq", nx=nx, ny=ny, walls=walls, Tw=0.9 if walls else 1.5,
+                       T0=1.5 if walls else 0.95)
+    phi0 = S.phi0(shape, seed=5)
+    o, g = run_pair(gpu, p, phi0, 60)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+    assert rel_l2(fg["u"], fo["u"]) <= 1e-4
+
+
+def test_body_force_and_shear(gpu):
+    """Uniform acceleration: u = (t + 1/2) g everywhere; a shear wave decays as in the oracle."""
+    p = S.model_params("c1_64sq", walls=0, T0=1.5, Tw=1.5, body_force=(1e-5, -2e-5))
+    phi0 = np.zeros((64, 64))
+    o, g = run_pair(gpu, p, phi0, 20)
+    u = gpu_fields(g)["u"]
+    np.testing.assert_allclose(u[0], 20.5e-5, rtol=1e-5)
+    np.testing.assert_allclose(u[1], -41e-5, rtol=1e-5)
+    L = 64
+    y = np.arange(L)
+    u0 = np.zeros((2, L, 16))
+    u0[0] = (1e-3 * np.sin(2 * np.pi * y / L))[:, None]
+    p = S.model_params("c1_64sq", nx=16, walls=0, T0=1.5, Tw=1.5, tau=0.6)
+    o, g = run_pair(gpu, p, np.zeros((L, 16)), 300, u0=u0)
+    assert rel_l2(gpu_fields(g)["u"], o.fields()["u"]) < 1e-5
+
+
+def test_observables_parity(gpu):
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    o, g = run_pair(gpu, p, phi0, 0)
+    for steps in (0, 300):
+        o.step(steps)
+        g.step(steps)
+        a, b = o.observables(), g.observables()
+        N = phi0.size
+        assert abs(a["mass_dev"] - b["mass_dev"]) / N < 1e-6
+        assert abs(a["phi_sum"] - b["phi_sum"]) / N < 1e-6
+        assert np.abs(np.array(a["mom"]) - np.array(b["mom"])).max() / N < 1e-7
+        assert b["max_u"] == pytest.approx(a["max_u"], rel=1e-4)
+        assert b["free_energy"] == pytest.approx(a["free_energy"], rel=1e-5, abs=1e-6 * N * 1e-4)
+        assert b["step"] == a["step"] and b["nonfinite"] == 0
+
+
+def test_nonfinite_is_reported(gpu):
+    p, phi0 = workload("c1_64sq")
+    phi0 = phi0.copy()
+    phi0[3, 7] = np.nan
+    import torch
+    g = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32))
+    ob = g.observables()
+    assert ob["nonfinite"] == 1
+    with pytest.raises(gpu.LamError) as e:
+        g.observables(raise_nonfinite=True)
+    assert e.value.code == gpu.LAM_ENONFINITE
+
+
+def test_x_roll_equivariance_bitwise(gpu):
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    import torch
+    a = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32)).step(50)
+    b = gpu.Sim(p).init_fields(torch.tensor(np.roll(phi0, 5, 1), dtype=torch.float32)).step(50)
+    fa, fb = gpu_fields(a), gpu_fields(b)
+    assert np.array_equal(np.roll(fa["phi"], 5, 1), fb["phi"])
+    assert np.array_equal(np.roll(fa["u"], 5, 2), fb["u"])
+
+
+def test_checkpoint_resume_bitwise(gpu):
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    import torch
+    ref = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32)).step(101)
+    a = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32)).step(51)
+    blob = a.get_state()
+    b = gpu.Sim(p).set_state(blob).step(50)
+    fr, fb = gpu_fields(ref), gpu_fields(b)
+    for k in ("phi", "u", "n", "T"):
+        assert np.array_equal(fr[k], fb[k]), k
+    assert b.observables()["step"] == 101
+    other = gpu.Sim(S.model_params("c1_64sq", nx=72))
+    with pytest.raises(gpu.LamError) as e:
+        other.set_state(blob)
+    assert e.value.code in (gpu.LAM_ESTATE, gpu.LAM_ESIZE)
+
+
+def test_deterministic_repeat(gpu):
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    import torch
+    r = []
+    for _ in range(2):
+        g = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32)).step(40)
+        r.append((gpu_fields(g)["phi"], g.observables()))
+    assert np.array_equal(r[0][0], r[1][0])
+    assert r[0][1] == r[1][1]
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (96, 80), (128, 256)])
+def test_structure_factor_parity(gpu, shape):
+    """S(k) of the same seeded field: powers of two (FFT) and other lengths (direct DFT)."""
+    ny, nx = shape
+    p = S.model_params("c1_64sq", nx=nx, ny=ny)
+    y, x = np.mgrid[0:ny, 0:nx]
+    phi0 = S.phi0(shape, seed=9) + 0.3 * np.cos(2 * np.pi * (3 * x / nx + 2 * y / ny))
+    phi0 = phi0.astype(np.float32).astype(np.float64)
+    nbins = min(nx, ny) // 2
+    ref = spectra.structure_factor(phi0, nbins)
+    import torch
+    g = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32))
+    got = g.structure_factor(nbins)
+    Sref = ref["S"]
+    big = Sref > 1e-3 * Sref.max()
+    np.testing.assert_allclose(np.array(got["S"])[big], Sref[big], rtol=2e-5)
+    np.testing.assert_allclose(np.array(got["S"])[~big], Sref[~big], atol=2e-5 * Sref.max())
+    assert got["k_peak"] == pytest.approx(ref["k_peak"], rel=1e-5)
+    assert got["k_mean"] == pytest.approx(ref["k_mean"], rel=1e-5)
+
+
+def test_orientation_parity(gpu):
+    """Q and the gradient-angle histogram of a developed lamellar field (the oracle's phi after
+    300 steps, rounded to FP32 and given to both sides).  A site whose angle lies within 1e-4 rad
+    of a bin edge may land on either side in FP32: its weight may move to the neighbour bin."""
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    phi = Oracle(p).init_fields(phi0).step(300).fields()["phi"]
+    phi = phi.astype(np.float32).astype(np.float64)
+    import torch
+    g = gpu.Sim(p).init_fields(torch.tensor(phi, dtype=torch.float32))
+    nb = 18
+    ref = spectra.orientation(phi, nb, walls=True)
+    got = g.orientation(nb)
+    assert got["Q"] == pytest.approx(ref["Q"], abs=1e-5)
+    np.testing.assert_allclose(got["Q_row"], ref["Q_row"], atol=1e-5)
+    width = math.pi / nb
+    th, w = ref["theta"].ravel(), ref["weight"].ravel() / ref["total_weight"]
+    frac = th / width - np.floor(th / width)
+    amb = (frac < 1e-4 / width) | (frac > 1 - 1e-4 / width)
+    slack = np.zeros(nb)
+    b = np.minimum((th / width).astype(int), nb - 1)
+    np.add.at(slack, b[amb], w[amb])
+    np.add.at(slack, (b[amb] + 1) % nb, w[amb])
+    np.add.at(slack, (b[amb] - 1) % nb, w[amb])
+    assert np.all(np.abs(np.array(got["hist"]) - ref["hist"]) <= slack + 1e-5)
+
+
+def test_structure_factor_of_developed_field(gpu):
+    p, phi0 = workload("c1_64sq", Tw=0.9)
+    phi = Oracle(p).init_fields(phi0).step(600).fields()["phi"]
+    phi = phi.astype(np.float32).astype(np.float64)
+    import torch
+    g = gpu.Sim(p).init_fields(torch.tensor(phi, dtype=torch.float32))
+    ref = spectra.structure_factor(phi, 32)
+    got = g.structure_factor(32)
+    np.testing.assert_allclose(got["S"], ref["S"], rtol=1e-4, atol=1e-5 * ref["S"].max())
+    assert got["k_peak"] == pytest.approx(ref["k_peak"], rel=1e-4)
+
+
+@pytest.mark.parametrize("name,steps", [("c2_1024sq_tau0.6", 20), ("c2_1024sq_tau2.0", 20)])
+def test_full_size_parity(gpu, name, steps):
+    """The 1024 x 1024 throughput workload in the benchmark's launch configuration, compared
+    site by site with the oracle after a few steps."""
+    p, phi0 = workload(name)
+    o, g = run_pair(gpu, p, phi0, steps)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-6
+    assert rel_l2(fg["u"], fo["u"]) <= 1e-4
+    assert np.abs(fg["n"] - fo["n"]).max() < 1e-6
+
+
+def test_full_size_conservation_long(gpu):
+    """1024 x 1024, 400 steps: total mass and sum(phi) conserved to FP32 round-off."""
+    p, phi0 = workload("c2_1024sq_tau2.0")
+    import torch
+    g = gpu.Sim(p).init_fields(torch.tensor(phi0, dtype=torch.float32))
+    a = g.observables()
+    g.step(400)
+    b = g.observables()
+    N = phi0.size
+    assert abs(b["mass_dev"] - a["mass_dev"]) / N < 1e-6
+    assert abs(b["phi_sum"] - a["phi_sum"]) / N < 1e-6
