@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="for rocprofv3 counter runs: a few steps of the workload, then one plain "
+                         "device copy of 512 MiB whose counters calibrate the byte counts")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method is built and "
@@ -89,6 +92,15 @@ def main():
     n_sites = p["nx"] * p["ny"]
     sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(phi0, dtype=torch.float32))
     n_phi, n_T = sim.substeps
+    if args.profile_pass:
+        sim.step(args.warmup)
+        sim.step(args.steps)
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": True, "steps": args.steps, "copy_bytes": src.numel() * 4}))
+        return
 
     def run(k):
         done = 0

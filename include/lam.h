@@ -66,7 +66,9 @@ typedef struct lam_params {
   int32_t force_form;        /* 0: F = -div P; 1: F = -phi grad mu                                 */
   int32_t pop_storage;       /* 0: FP32 population deviations (only value supported)              */
   int32_t allow_unstable;    /* 1: accept n_phi_sub / n_T_sub below the stability bound           */
-  int32_t reserved_;
+  int32_t tile_hint;         /* 0: automatic; 8, 16, 32 or 64: tile height of the step kernels. The
+                                per-site arithmetic is the same for every tile: bit-identical
+                                fields (used to test the tiling)                                  */
   double body_force[3];      /* uniform acceleration g; the force density n g is added (tests)    */
 } lam_params;
 

@@ -28,7 +28,7 @@ class lam_params(C.Structure):
                 ("T0", C.c_double), ("Tw", C.c_double), ("xi", C.c_double),
                 ("n_phi_sub", C.c_int32), ("n_T_sub", C.c_int32), ("force_form", C.c_int32),
                 ("pop_storage", C.c_int32), ("allow_unstable", C.c_int32),
-                ("reserved_", C.c_int32), ("body_force", C.c_double * 3)]
+                ("tile_hint", C.c_int32), ("body_force", C.c_double * 3)]
 
 
 class lam_obs(C.Structure):
@@ -92,6 +92,7 @@ def make_params(p: dict) -> lam_params:
     q.force_form = int(p.get("force_form", 0))
     q.pop_storage = int(p.get("pop_storage", 0))
     q.allow_unstable = int(p.get("allow_unstable", 0))
+    q.tile_hint = int(p.get("tile_hint", 0))
     g = list(p.get("body_force", (0.0, 0.0, 0.0))) + [0.0, 0.0, 0.0]
     for k in range(3):
         q.body_force[k] = float(g[k])

@@ -4,11 +4,12 @@
 // between steps is the post-collision field of the previous step, so one kernel pulls
 // (streams), takes moments, applies the force and collides.  phi[y][x] FP32; T per row.
 //
-// lb2d: one 64 x TY tile per workgroup of 256 threads (4 waves; each wave owns rows
-//   ty, ty+4, ...).  phi is staged in LDS with a halo of 3, from which the Laplacian (halo 2)
-//   and then the pressure tensor (halo 1) are built in LDS; every site then takes the discrete
-//   divergence of P, pulls its 9 populations (halfway bounce-back at walls), collides with the
-//   BGK + forcing rule and writes 9 populations and the force-shifted velocity.
+// lb2d: one 64 x TY tile per workgroup of 16 TY threads (TY/4 waves; each thread owns four
+//   sites of one column).  Each thread first issues the pulls of its 36 populations (halfway
+//   bounce-back at walls), so that their latency overlaps the stencil work: phi is staged in LDS
+//   with a halo of 3, from which the Laplacian (halo 2) and the pressure tensor (halo 1) are
+//   built in LDS.  Every site then takes the discrete divergence of P, its moments, collides with
+//   the BGK + forcing rule and writes 9 populations and the force-shifted velocity.
 // phi2d<S>: S explicit Euler sub-steps of the order-parameter equation on a tile with halo 3S,
 //   all in LDS (temporal blocking), reading phi and u once and writing phi once.  The workgroup
 //   of tile 0 also advances the per-row temperature.
@@ -17,7 +18,6 @@
 namespace lam {
 
 constexpr int TX = 64;
-constexpr int NT = 256;
 
 enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
 
@@ -27,17 +27,51 @@ struct Lb2dSmem {
   float L[TY + 4][TX + 4];
   float P[3][TY + 2][TX + 2];  // Pxx, Pyy, Pxy (or mu in P[0] for the -phi grad mu form)
   float a[TY + 6];
-  double red[4][R_N];
+  double red[TY / 4][R_N];
 };
 
+// Pull of the 9 populations of site (x, y): f_q(x) = f*_q(x - e_q); across a wall the opposite
+// population of x itself (halfway bounce-back).
+__device__ __forceinline__ void pull9(const float* __restrict__ G, size_t N, int nx, int ny,
+                                      int walls, int x, int y, float g[9]) {
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  auto ld = [&](int q, int yy, int xx) { return G[(size_t)q * N + (size_t)yy * nx + xx]; };
+  g[0] = ld(0, y, x);
+  g[1] = ld(1, y, xm);
+  g[3] = ld(3, y, xp);
+  if (walls && y == 0) {
+    g[2] = ld(4, y, x);
+    g[5] = ld(7, y, x);
+    g[6] = ld(8, y, x);
+  } else {
+    const int ym = y == 0 ? ny - 1 : y - 1;
+    g[2] = ld(2, ym, x);
+    g[5] = ld(5, ym, xm);
+    g[6] = ld(6, ym, xp);
+  }
+  if (walls && y == ny - 1) {
+    g[4] = ld(2, y, x);
+    g[7] = ld(5, y, x);
+    g[8] = ld(6, y, x);
+  } else {
+    const int yp = y == ny - 1 ? 0 : y + 1;
+    g[4] = ld(4, yp, x);
+    g[7] = ld(7, yp, xp);
+    g[8] = ld(8, yp, xm);
+  }
+}
+
+// One workgroup of 16*TY threads (TY/4 waves) per 64 x TY tile; every thread owns the 4 sites
+// (tx, ty + k TY/4), k < 4, of one column.
 template <int TY, int MODE>
-__global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __restrict__ gin,
-                                                  float* __restrict__ gout,
-                                                  const float* __restrict__ phi,
-                                                  const float* __restrict__ Trow,
-                                                  float* __restrict__ uout,
-                                                  float* __restrict__ nout,
-                                                  double* __restrict__ partials) {
+__global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const float* __restrict__ gin,
+                                                       float* __restrict__ gout,
+                                                       const float* __restrict__ phi,
+                                                       const float* __restrict__ Trow,
+                                                       float* __restrict__ uout,
+                                                       float* __restrict__ nout,
+                                                       double* __restrict__ partials) {
+  constexpr int NTH = 16 * TY, NW = TY / 4;
   __shared__ Lb2dSmem<TY> S;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
@@ -45,9 +79,18 @@ __global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __rest
   const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY;
   const int t = xcd_tile(blockIdx.x, nbx * nby);
   const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
+  const int tx = tid & 63, ty = tid >> 6;
+
+  // issue the population pulls first so that their latency overlaps the stencil phases
+  float g[4][9];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int x = x0 + tx, y = y0 + ty + NW * j;
+    if (x < nx && y < ny) pull9(gin, N, nx, ny, P.walls, x, y, g[j]);
+  }
 
   // phi with halo 3: periodic in x, reflected (or periodic) in y; a = (T - Tc)/Tc per row
-  for (int i = tid; i < (TY + 6) * (TX + 6); i += NT) {
+  for (int i = tid; i < (TY + 6) * (TX + 6); i += NTH) {
     int r = i / (TX + 6), c = i - r * (TX + 6);
     bool f;
     int gy = wall_axis(y0 - 3 + r, ny, P.walls, f);
@@ -61,18 +104,18 @@ __global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __rest
   }
   __syncthreads();
   // L = lap phi on halo 2
-  for (int i = tid; i < (TY + 4) * (TX + 4); i += NT) {
+  for (int i = tid; i < (TY + 4) * (TX + 4); i += NTH) {
     int r = i / (TX + 4), c = i - r * (TX + 4);
     const int R = r + 1, C = c + 1;
     S.L[r][c] = (S.phi[R][C + 1] + S.phi[R][C - 1]) + (S.phi[R + 1][C] + S.phi[R - 1][C]) -
                 4.f * S.phi[R][C];
   }
   __syncthreads();
-  if (MODE != MODE_FIELDS || P.hydro) {
+  if (P.hydro) {
     // pressure tensor (or mu) on halo 1
-    for (int i = tid; i < (TY + 2) * (TX + 2); i += NT) {
+    for (int i = tid; i < (TY + 2) * (TX + 2); i += NTH) {
       int r = i / (TX + 2), c = i - r * (TX + 2);
-      const int R = r + 2, C = c + 2;  // phi coordinates
+      const int R = r + 2, C = c + 2;    // phi coordinates
       const int r1 = r + 1, c1 = c + 1;  // L coordinates
       float ph = S.phi[R][C], L = S.L[r1][c1];
       float M = (S.L[r1][c1 + 1] + S.L[r1][c1 - 1]) + (S.L[r1 + 1][c1] + S.L[r1 - 1][c1]) - 4.f * L;
@@ -96,14 +139,13 @@ __global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __rest
     __syncthreads();
   }
 
-  const int tx = tid & 63, ty = tid >> 6;
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
 
 #pragma unroll
-  for (int j = 0; j < TY / 4; ++j) {
-    const int row = ty + 4 * j;
+  for (int j = 0; j < 4; ++j) {
+    const int row = ty + NW * j;
     const int x = x0 + tx, y = y0 + row;
     if (x >= nx || y >= ny) continue;
     // force density: -div P (central differences) or -phi grad mu
@@ -121,32 +163,8 @@ __global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __rest
                0.5f * (S.P[1][r + 1][c] - S.P[1][r - 1][c]));
       }
     }
-    // pull-stream: f_q(x) = f*_q(x - e_q); across a wall the opposite population of x itself
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const float* G = gin;
-    auto ld = [&](int q, int yy, int xx) { return G[(size_t)q * N + (size_t)yy * nx + xx]; };
-    float g0 = ld(0, y, x), g1 = ld(1, y, xm), g3 = ld(3, y, xp);
-    float g2, g4, g5, g6, g7, g8;
-    if (P.walls && y == 0) {
-      g2 = ld(4, y, x);
-      g5 = ld(7, y, x);
-      g6 = ld(8, y, x);
-    } else {
-      const int ym = y == 0 ? ny - 1 : y - 1;
-      g2 = ld(2, ym, x);
-      g5 = ld(5, ym, xm);
-      g6 = ld(6, ym, xp);
-    }
-    if (P.walls && y == ny - 1) {
-      g4 = ld(2, y, x);
-      g7 = ld(5, y, x);
-      g8 = ld(6, y, x);
-    } else {
-      const int yp = y == ny - 1 ? 0 : y + 1;
-      g4 = ld(4, yp, x);
-      g7 = ld(7, yp, xp);
-      g8 = ld(8, yp, xm);
-    }
+    const float g0 = g[j][0], g1 = g[j][1], g2 = g[j][2], g3 = g[j][3], g4 = g[j][4];
+    const float g5 = g[j][5], g6 = g[j][6], g7 = g[j][7], g8 = g[j][8];
     // moments n = 1 + sum g, j = sum g e; u = (j + F/2)/n
     const float dn = ((g0 + g1) + (g2 + g3)) + ((g4 + g5) + (g6 + g7)) + g8;
     const float jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
@@ -166,10 +184,10 @@ __global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __rest
       const float usq = 1.5f * (ux * ux + uy * uy);
       const float uF = ux * Fx + uy * Fy;
       const float om = P.omega, kf = P.kforce;
-      auto coll = [&](float g, float w, float eu, float eF) {
+      auto coll = [&](float gq, float w, float eu, float eF) {
         float geq = w * (dn + n * (eu * (3.f + 4.5f * eu) - usq));
         float frc = kf * w * (3.f * (eF - uF) + 9.f * eu * eF);
-        return g + om * (geq - g) + frc;
+        return gq + om * (geq - gq) + frc;
       };
       const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
       gout[0 * N + s] = coll(g0, w0, 0.f, 0.f);
@@ -213,7 +231,7 @@ __global__ __launch_bounds__(NT) void lb2d_kernel(KParams P, const float* __rest
     __syncthreads();
     if (tid < R_N) {
       double v = S.red[0][tid];
-      for (int w = 1; w < 4; ++w)
+      for (int w = 1; w < NW; ++w)
         v = (tid == R_UMAX || tid == R_BAD) ? fmax(v, S.red[w][tid]) : v + S.red[w][tid];
       partials[(size_t)blockIdx.x * R_N + tid] = v;
     }
@@ -231,19 +249,21 @@ struct Phi2dDims {
 };
 
 template <int S_, int TY, bool HYDRO>
-__global__ __launch_bounds__(NT) void phi2d_kernel(KParams P, const float* __restrict__ psi_in,
-                                                   float* __restrict__ psi_out,
-                                                   const float* __restrict__ u,
-                                                   const float* __restrict__ Trow,
-                                                   float* __restrict__ Tnext,
-                                                   float* __restrict__ Tscr, int do_T) {
+__global__ __launch_bounds__(16 * TY) void phi2d_kernel(KParams P, const float* __restrict__ psi_in,
+                                                        float* __restrict__ psi_out,
+                                                        const float* __restrict__ u,
+                                                        const float* __restrict__ Trow,
+                                                        float* __restrict__ Tnext,
+                                                        float* __restrict__ Tscr, int do_T) {
   using D = Phi2dDims<S_, TY>;
   constexpr int R = D::R, H = D::H, W = D::W;
+  constexpr int NTH = 16 * TY;
+  constexpr int HU = H - 4, WU = W - 4;  // planes used from depth 2 on (mu, velocity)
   __shared__ float A[H][W];
   __shared__ float B[H][W];
-  __shared__ float Cm[H][W];
-  __shared__ float Ux[HYDRO ? H : 1][HYDRO ? W : 1];
-  __shared__ float Uy[HYDRO ? H : 1][HYDRO ? W : 1];
+  __shared__ float Cm[HU][WU];
+  __shared__ float Ux[HYDRO ? HU : 1][HYDRO ? WU : 1];
+  __shared__ float Uy[HYDRO ? HU : 1][HYDRO ? WU : 1];
   __shared__ float sa[H];
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
@@ -252,28 +272,27 @@ __global__ __launch_bounds__(NT) void phi2d_kernel(KParams P, const float* __res
   const int t = xcd_tile(blockIdx.x, nbx * nby);
   const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
 
-  for (int i = tid; i < H * W; i += NT) {
-    int r = i / W, c = i - r * W;
-    bool f;
-    int gy = wall_axis(y0 - R + r, ny, P.walls, f);
-    int gx = wrap(x0 - R + c, nx);
-    A[r][c] = psi_in[(size_t)gy * nx + gx];
-  }
   if (HYDRO) {
-    // velocity at depth 2; the wall-normal component is odd across a wall
-    constexpr int hh = H - 4, ww = W - 4;
-    for (int i = tid; i < hh * ww; i += NT) {
-      int r = 2 + i / ww, c = 2 + (i - (i / ww) * ww);
+    // velocity at depth 2 (plane offset 2); the wall-normal component is odd across a wall
+    for (int i = tid; i < HU * WU; i += NTH) {
+      int r = i / WU, c = i - (i / WU) * WU;
       bool f;
-      int gy = wall_axis(y0 - R + r, ny, P.walls, f);
-      int gx = wrap(x0 - R + c, nx);
+      int gy = wall_axis(y0 - R + 2 + r, ny, P.walls, f);
+      int gx = wrap(x0 - R + 2 + c, nx);
       size_t s = (size_t)gy * nx + gx;
       Ux[r][c] = u[s];
       float vy = u[N + s];
       Uy[r][c] = f ? -vy : vy;
     }
   }
-  for (int i = tid; i < H; i += NT) {
+  for (int i = tid; i < H * W; i += NTH) {
+    int r = i / W, c = i - r * W;
+    bool f;
+    int gy = wall_axis(y0 - R + r, ny, P.walls, f);
+    int gx = wrap(x0 - R + c, nx);
+    A[r][c] = psi_in[(size_t)gy * nx + gx];
+  }
+  for (int i = tid; i < H; i += NTH) {
     bool f;
     int gy = wall_axis(y0 - R + i, ny, P.walls, f);
     sa[i] = (Trow[gy] - P.Tc) / P.Tc;
@@ -281,54 +300,52 @@ __global__ __launch_bounds__(NT) void phi2d_kernel(KParams P, const float* __res
   __syncthreads();
 
   float(*ps)[W] = A;   // current psi
-  float(*lb)[W] = B;   // Laplacian, then the next psi
+  float(*nx_)[W] = B;  // next psi
 #pragma unroll
   for (int s = 0; s < S_; ++s) {
     const int d = 3 * s;
-    {  // L at depth d + 1
-      constexpr int dummy = 0;
-      (void)dummy;
-      const int dd = d + 1, hh = H - 2 * dd, ww = W - 2 * dd;
-      for (int i = tid; i < hh * ww; i += NT) {
-        int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
-        lb[r][c] = (ps[r][c + 1] + ps[r][c - 1]) + (ps[r + 1][c] + ps[r - 1][c]) - 4.f * ps[r][c];
-      }
-    }
-    __syncthreads();
-    {  // mu at depth d + 2
+    {  // mu at depth d + 2: lap^2 as the 13-point square of the 5-point Laplacian
       const int dd = d + 2, hh = H - 2 * dd, ww = W - 2 * dd;
-      for (int i = tid; i < hh * ww; i += NT) {
+#pragma unroll 2
+      for (int i = tid; i < hh * ww; i += NTH) {
         int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
-        float v = ps[r][c], L = lb[r][c];
-        float M = (lb[r][c + 1] + lb[r][c - 1]) + (lb[r + 1][c] + lb[r - 1][c]) - 4.f * L;
-        Cm[r][c] = sa[r] * v + P.b * v * v * v - P.kappa * L + P.c * M;
+        const float v = ps[r][c];
+        const float e = ps[r][c + 1], w = ps[r][c - 1], n = ps[r + 1][c], so = ps[r - 1][c];
+        const float L = (e + w) + (n + so) - 4.f * v;
+        const float diag = (ps[r + 1][c + 1] + ps[r + 1][c - 1]) + (ps[r - 1][c + 1] + ps[r - 1][c - 1]);
+        const float far = (ps[r][c + 2] + ps[r][c - 2]) + (ps[r + 2][c] + ps[r - 2][c]);
+        const float M = 20.f * v - 8.f * ((e + w) + (n + so)) + 2.f * diag + far;
+        Cm[r - 2][c - 2] = sa[r] * v + P.b * v * v * v - P.kappa * L + P.c * M;
       }
     }
     __syncthreads();
     {  // psi' at depth d + 3
       const int dd = d + 3, hh = H - 2 * dd, ww = W - 2 * dd;
       const bool last = s == S_ - 1;
-      for (int i = tid; i < hh * ww; i += NT) {
+#pragma unroll 2
+      for (int i = tid; i < hh * ww; i += NTH) {
         int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
-        float lapmu = (Cm[r][c + 1] + Cm[r][c - 1]) + (Cm[r + 1][c] + Cm[r - 1][c]) - 4.f * Cm[r][c];
+        const int r2 = r - 2, c2 = c - 2;
+        float lapmu = (Cm[r2][c2 + 1] + Cm[r2][c2 - 1]) + (Cm[r2 + 1][c2] + Cm[r2 - 1][c2]) -
+                      4.f * Cm[r2][c2];
         float adv = 0.f;
         if (HYDRO) {
-          adv = 0.5f * (ps[r][c + 1] * Ux[r][c + 1] - ps[r][c - 1] * Ux[r][c - 1]) +
-                0.5f * (ps[r + 1][c] * Uy[r + 1][c] - ps[r - 1][c] * Uy[r - 1][c]);
+          adv = 0.5f * (ps[r][c + 1] * Ux[r2][c2 + 1] - ps[r][c - 1] * Ux[r2][c2 - 1]) +
+                0.5f * (ps[r + 1][c] * Uy[r2 + 1][c2] - ps[r - 1][c] * Uy[r2 - 1][c2]);
         }
         float v = ps[r][c] + P.h * (-adv + P.Gamma * lapmu);
         if (last) {
           int y = y0 - R + r, x = x0 - R + c;
           if (x < nx && y < ny) psi_out[(size_t)y * nx + x] = v;
         } else {
-          lb[r][c] = v;
+          nx_[r][c] = v;
         }
       }
     }
     __syncthreads();
     float(*tmp)[W] = ps;
-    ps = lb;
-    lb = tmp;
+    ps = nx_;
+    nx_ = tmp;
   }
 
   // Temperature: FTCS sub-steps along the wall axis (T is uniform along x); wall layers held.
@@ -336,7 +353,7 @@ __global__ __launch_bounds__(NT) void phi2d_kernel(KParams P, const float* __res
     const float* src = Trow;
     for (int m = 0; m < P.n_T; ++m) {
       float* dst = ((P.n_T - 1 - m) % 2 == 0) ? Tnext : Tscr;
-      for (int j = tid; j < ny; j += NT) {
+      for (int j = tid; j < ny; j += NTH) {
         float v = src[j];
         bool wall = P.walls && (j == 0 || j == ny - 1);
         if (!wall) {
@@ -352,50 +369,70 @@ __global__ __launch_bounds__(NT) void phi2d_kernel(KParams P, const float* __res
 }
 
 // ------------------------------------------------------------------------------------------------
-// Host launchers.
-constexpr int LB_TY = 16;
-constexpr int PHI_TY = 16;
-
+// Host launchers.  Tile heights 8, 16, 32 and 64 are compiled; the per-site arithmetic does not
+// depend on the tile, so every choice gives bit-identical fields.
 static int blocks2d(const KParams& P, int ty) {
   return ((P.nx + TX - 1) / TX) * ((P.ny + ty - 1) / ty);
 }
 
-int lb2d_blocks(const KParams& P) { return blocks2d(P, LB_TY); }
+int lb2d_blocks(const KParams& P, int ty) { return blocks2d(P, ty); }
 
-hipError_t launch_lb2d(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
-                       const float* Trow, float* u, float* n, double* partials, hipStream_t st) {
-  dim3 grid(blocks2d(P, LB_TY)), block(NT);
+template <int TY>
+static void lb2d_launch(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
+                        const float* Trow, float* u, float* n, double* partials, hipStream_t st) {
+  dim3 grid(blocks2d(P, TY)), block(16 * TY);
   if (mode == MODE_STEP)
-    hipLaunchKernelGGL((lb2d_kernel<LB_TY, MODE_STEP>), grid, block, 0, st, P, gin, gout, phi, Trow,
+    hipLaunchKernelGGL((lb2d_kernel<TY, MODE_STEP>), grid, block, 0, st, P, gin, gout, phi, Trow,
                        u, n, partials);
   else if (mode == MODE_OBS)
-    hipLaunchKernelGGL((lb2d_kernel<LB_TY, MODE_OBS>), grid, block, 0, st, P, gin, gout, phi, Trow,
+    hipLaunchKernelGGL((lb2d_kernel<TY, MODE_OBS>), grid, block, 0, st, P, gin, gout, phi, Trow,
                        u, n, partials);
   else
-    hipLaunchKernelGGL((lb2d_kernel<LB_TY, MODE_FIELDS>), grid, block, 0, st, P, gin, gout, phi,
+    hipLaunchKernelGGL((lb2d_kernel<TY, MODE_FIELDS>), grid, block, 0, st, P, gin, gout, phi,
                        Trow, u, n, partials);
+}
+
+hipError_t launch_lb2d(const KParams& P, int ty, int mode, const float* gin, float* gout,
+                       const float* phi, const float* Trow, float* u, float* n, double* partials,
+                       hipStream_t st) {
+  if (ty == 8) lb2d_launch<8>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
+  else if (ty == 16) lb2d_launch<16>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
+  else if (ty == 32) lb2d_launch<32>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
+  else if (ty == 64) lb2d_launch<64>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template <int S_>
+template <int S_, int TY>
 static void phi2d_launch(const KParams& P, const float* in, float* out, const float* u,
                          const float* T, float* Tn, float* Ts, int do_T, hipStream_t st) {
-  dim3 grid(blocks2d(P, PHI_TY)), block(NT);
+  dim3 grid(blocks2d(P, TY)), block(16 * TY);
   if (P.hydro)
-    hipLaunchKernelGGL((phi2d_kernel<S_, PHI_TY, true>), grid, block, 0, st, P, in, out, u, T, Tn,
-                       Ts, do_T);
+    hipLaunchKernelGGL((phi2d_kernel<S_, TY, true>), grid, block, 0, st, P, in, out, u, T, Tn, Ts,
+                       do_T);
   else
-    hipLaunchKernelGGL((phi2d_kernel<S_, PHI_TY, false>), grid, block, 0, st, P, in, out, u, T, Tn,
+    hipLaunchKernelGGL((phi2d_kernel<S_, TY, false>), grid, block, 0, st, P, in, out, u, T, Tn,
                        Ts, do_T);
 }
 
 int phi2d_max_sub() { return 2; }
 
-hipError_t launch_phi2d(const KParams& P, int nsub, const float* in, float* out, const float* u,
-                        const float* T, float* Tn, float* Ts, int do_T, hipStream_t st) {
-  if (nsub == 1) phi2d_launch<1>(P, in, out, u, T, Tn, Ts, do_T, st);
-  else if (nsub == 2) phi2d_launch<2>(P, in, out, u, T, Tn, Ts, do_T, st);
-  else return hipErrorInvalidValue;
+hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, float* out,
+                        const float* u, const float* T, float* Tn, float* Ts, int do_T,
+                        hipStream_t st) {
+  if (nsub < 1 || nsub > 2 || (ty != 8 && ty != 16 && ty != 32 && ty != 64))
+    return hipErrorInvalidValue;
+  if (nsub == 1) {
+    if (ty == 8) phi2d_launch<1, 8>(P, in, out, u, T, Tn, Ts, do_T, st);
+    else if (ty == 16) phi2d_launch<1, 16>(P, in, out, u, T, Tn, Ts, do_T, st);
+    else if (ty == 32) phi2d_launch<1, 32>(P, in, out, u, T, Tn, Ts, do_T, st);
+    else phi2d_launch<1, 64>(P, in, out, u, T, Tn, Ts, do_T, st);
+  } else {
+    if (ty == 8) phi2d_launch<2, 8>(P, in, out, u, T, Tn, Ts, do_T, st);
+    else if (ty == 16) phi2d_launch<2, 16>(P, in, out, u, T, Tn, Ts, do_T, st);
+    else if (ty == 32) phi2d_launch<2, 32>(P, in, out, u, T, Tn, Ts, do_T, st);
+    else phi2d_launch<2, 64>(P, in, out, u, T, Tn, Ts, do_T, st);
+  }
   return hipGetLastError();
 }
 

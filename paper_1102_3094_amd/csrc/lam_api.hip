@@ -15,12 +15,14 @@
 namespace lam {
 enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
 // lam_2d.hip
-int lb2d_blocks(const KParams& P);
-hipError_t launch_lb2d(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
-                       const float* Trow, float* u, float* n, double* partials, hipStream_t st);
+int lb2d_blocks(const KParams& P, int ty);
+hipError_t launch_lb2d(const KParams& P, int ty, int mode, const float* gin, float* gout,
+                       const float* phi, const float* Trow, float* u, float* n, double* partials,
+                       hipStream_t st);
 int phi2d_max_sub();
-hipError_t launch_phi2d(const KParams& P, int nsub, const float* in, float* out, const float* u,
-                        const float* T, float* Tn, float* Ts, int do_T, hipStream_t st);
+hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, float* out,
+                        const float* u, const float* T, float* Tn, float* Ts, int do_T,
+                        hipStream_t st);
 // lam_util.hip
 hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, float* g,
                        hipStream_t st);
@@ -50,6 +52,7 @@ struct lam_sim {
   lam_params p;
   KParams k;
   int Q, nphi, nT, nrows;
+  int ty_lb, ty_phi;  // tile heights of the two step kernels
   size_t N;
   hipStream_t st;
   char* ws;
@@ -98,7 +101,8 @@ Layout layout(const lam_params& p) {
   for (int i = 0; i < 2; ++i) L.psi[i] = take(sizeof(float) * N);
   L.u = take(sizeof(float) * p.dim * N);
   for (int i = 0; i < 3; ++i) L.T[i] = take(sizeof(float) * nrows);
-  L.nblk = (int)(N / 64 + 64);
+  // one partial per workgroup of the largest grid (2D tiles 64 x 8; 3D handled by its kernels)
+  L.nblk = (int)((size_t)((p.nx + 63) / 64) * ((p.ny + 7) / 8) * (p.dim == 3 ? p.nz : 1) + 1);
   L.partials = take(sizeof(double) * R_N * L.nblk);
   L.result = take(sizeof(double) * R_N);
   L.spec = take(p.dim == 2 ? spectra_scratch_bytes(p.nx, p.ny) : 256);
@@ -168,6 +172,9 @@ int validate(const lam_params* p, std::string& why) {
   if (p->walls != 0 && p->walls != 1) return why = "walls must be 0 or 1", LAM_EINVAL;
   if (p->hydro != 0 && p->hydro != 1) return why = "hydro must be 0 or 1", LAM_EINVAL;
   if (p->n_phi_sub < 0 || p->n_T_sub < 0) return why = "sub-step counts must be >= 0", LAM_EINVAL;
+  if (p->tile_hint != 0 && p->tile_hint != 8 && p->tile_hint != 16 && p->tile_hint != 32 &&
+      p->tile_hint != 64)
+    return why = "tile_hint must be 0, 8, 16, 32 or 64", LAM_EINVAL;
   if (!p->allow_unstable) {
     if (p->n_phi_sub > 0 && p->n_phi_sub < auto_nphi(*p))
       return why = "n_phi_sub below the stability bound (set allow_unstable to force)", LAM_EINVAL;
@@ -209,6 +216,8 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   s->nphi = p->n_phi_sub > 0 ? p->n_phi_sub : auto_nphi(*p);
   s->nT = p->n_T_sub > 0 ? p->n_T_sub : auto_nT(*p);
   s->st = (hipStream_t)hip_stream;
+  s->ty_lb = p->tile_hint ? p->tile_hint : 16;
+  s->ty_phi = p->tile_hint ? p->tile_hint : 16;
   s->ws = (char*)d_workspace;
   s->ws_bytes = bytes;
   for (int i = 0; i < 2; ++i) {
@@ -328,8 +337,8 @@ int lam_step(lam_sim* s, int64_t nsteps) {
     const int cur = (int)(s->step & 1), nxt = cur ^ 1;
     if (k.hydro) {
       long ev = timing_begin(s, LAM_K_LB);
-      HIPCHK(s, launch_lb2d(k, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur], s->u,
-                            nullptr, nullptr, s->st));
+      HIPCHK(s, launch_lb2d(k, s->ty_lb, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur],
+                            s->u, nullptr, nullptr, s->st));
       timing_end(s, ev);
     }
     int remaining = s->nphi, which = 0;
@@ -340,7 +349,7 @@ int lam_step(lam_sim* s, int64_t nsteps) {
       float* dst = last ? s->phi[nxt] : s->psi[which];
       which ^= 1;
       long ev = timing_begin(s, LAM_K_PHI);
-      HIPCHK(s, launch_phi2d(k, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
+      HIPCHK(s, launch_phi2d(k, s->ty_phi, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
                              last && k.n_T > 0, s->st));
       timing_end(s, ev);
       src = dst;
@@ -355,9 +364,9 @@ int lam_observables(lam_sim* s, lam_obs* o) {
   if (!s || !o) return fail(s, LAM_EINVAL, "bad arguments");
   if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
   const int cur = (int)(s->step & 1);
-  int nblk = lb2d_blocks(s->k);
-  HIPCHK(s, launch_lb2d(s->k, MODE_OBS, s->g[cur], nullptr, s->phi[cur], s->T[cur], nullptr,
-                        nullptr, s->partials, s->st));
+  int nblk = lb2d_blocks(s->k, s->ty_lb);
+  HIPCHK(s, launch_lb2d(s->k, s->ty_lb, MODE_OBS, s->g[cur], nullptr, s->phi[cur], s->T[cur],
+                        nullptr, nullptr, s->partials, s->st));
   HIPCHK(s, launch_finalize(s->partials, nblk, s->result, s->st));
   double r[R_N];
   HIPCHK(s, hipMemcpyAsync(r, s->result, sizeof(r), hipMemcpyDeviceToHost, s->st));
@@ -402,8 +411,8 @@ int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T)
     HIPCHK(s, hipMemcpyAsync(d_phi, s->phi[cur], sizeof(float) * s->N, hipMemcpyDeviceToDevice,
                              s->st));
   if (d_u || d_n)
-    HIPCHK(s, launch_lb2d(s->k, MODE_FIELDS, s->g[cur], nullptr, s->phi[cur], s->T[cur],
-                          d_u ? d_u : s->u, d_n, nullptr, s->st));
+    HIPCHK(s, launch_lb2d(s->k, s->ty_lb, MODE_FIELDS, s->g[cur], nullptr, s->phi[cur],
+                          s->T[cur], d_u ? d_u : s->u, d_n, nullptr, s->st));
   if (d_T) {
     size_t layer = (size_t)s->p.nx * (s->p.dim == 3 ? s->p.ny : 1);
     HIPCHK(s, launch_broadcast_T(s->T[cur], s->N, layer, d_T, s->st));

@@ -26,7 +26,9 @@ static SpecLayout spec_layout(int nx, int ny) {
   L.mean = o;  o = al(o + 8 * 4);
   L.rowsum = o; o = al(o + 8 * (size_t)(nx > ny ? nx : ny));
   L.buf = o;   o = al(o + 8 * (size_t)nx * ny);              // float2 transposed spectrum
-  L.part = o;  o = al(o + 16 * (size_t)nx * nb);             // per-row (sum, count) per shell
+  // per-row (sum, count) per shell; also holds the orientation row partials (ny x (36 + 2))
+  const size_t part = 16 * (size_t)nx * nb, orient = 8 * (size_t)ny * 38;
+  L.part = o;  o = al(o + (part > orient ? part : orient));
   L.kpart = o; o = al(o + 16 * (size_t)(nx > ny ? nx : ny)); // per-row (sum |k| P, sum P)
   L.bins = o;  o = al(o + 8 * (size_t)(nb + 8));
   L.total = o;
@@ -217,40 +219,57 @@ __global__ void fft_y_bin_kernel(const float2* __restrict__ buf, int nx, int ny,
   if (threadIdx.x == 0) kpart[row] = make_double2(sk[0], sp[0]);
 }
 
-// Combine rows in a fixed order; S per shell, parabolic peak refinement and <k>.
-// out: [0, nbins) S; nbins: k_peak; nbins+1: S_peak; nbins+2: k_mean.
-__global__ void spec_final_kernel(const double2* __restrict__ part, const double2* __restrict__ kpart,
-                                  int nrows, int nbmax, int nbins, double dk,
-                                  double* __restrict__ out) {
-  __shared__ double sk[256], sp[256];
-  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
-    double s = 0.0, c = 0.0;
-    for (int r = 0; r < nrows; ++r) {
-      double2 v = part[(size_t)r * nbmax + b];
-      s += v.x;
-      c += v.y;
+// Column sums of a row-major [nrows][ld] matrix of doubles, one workgroup per column, fixed
+// order (strided per-thread sums, then a tree).
+__global__ void colsum_kernel(const double* __restrict__ M, int nrows, int ld,
+                              double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int col = blockIdx.x;
+  double v = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += 256) v += M[(size_t)r * ld + col];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[col] = sm[0];
+}
+
+// S per shell from (sum, count) column sums; the largest shell (first one on ties), its
+// parabolic refinement and <k>.  out: [0, nbins) S; nbins: k_peak; nbins+1: S_peak;
+// nbins+2: k_mean.
+__global__ void spec_final_kernel(const double* __restrict__ sc, const double* __restrict__ kk,
+                                  int nbins, double dk, double* __restrict__ out) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  double best = -1.0;
+  int bidx = 0;
+  for (int b = threadIdx.x; b < nbins; b += 256) {
+    double c = sc[2 * b + 1];
+    double v = c > 0 ? sc[2 * b] / c : 0.0;
+    out[b] = v;
+    if (v > best) {
+      best = v;
+      bidx = b;
     }
-    out[b] = c > 0 ? s / c : 0.0;
   }
-  double ks = 0.0, ps = 0.0;
-  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
-    ks += kpart[r].x;
-    ps += kpart[r].y;
-  }
-  sk[threadIdx.x] = ks;
-  sp[threadIdx.x] = ps;
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
-      sk[threadIdx.x] += sk[threadIdx.x + o];
-      sp[threadIdx.x] += sp[threadIdx.x + o];
+      double v2 = bv[threadIdx.x + o];
+      int i2 = bi[threadIdx.x + o];
+      if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+        bv[threadIdx.x] = v2;
+        bi[threadIdx.x] = i2;
+      }
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    int m = 0;
-    for (int b = 1; b < nbins; ++b)
-      if (out[b] > out[m]) m = b;
+    const int m = bi[0];
     double kp = (m + 0.5) * dk, Sp = out[m];
     if (m > 0 && m < nbins - 1) {
       double den = out[m - 1] - 2.0 * out[m] + out[m + 1];
@@ -262,7 +281,7 @@ __global__ void spec_final_kernel(const double2* __restrict__ part, const double
     }
     out[nbins] = kp;
     out[nbins + 1] = Sp;
-    out[nbins + 2] = sp[0] > 0 ? sk[0] / sp[0] : 0.0;
+    out[nbins + 2] = kk[1] > 0 ? kk[0] / kk[1] : 0.0;
   }
 }
 
@@ -290,8 +309,13 @@ hipError_t structure_factor_2d(const KParams& P, const float* phi, void* scratch
   hipLaunchKernelGGL(fft_y_bin_kernel, dim3(nx), dim3(256), dft_lds_bytes(ny, py), st, buf, nx, ny,
                      nbmax, part, kpart, py);
   const double dk = 6.283185307179586 / (nx < ny ? nx : ny);
-  hipLaunchKernelGGL(spec_final_kernel, dim3(1), dim3(256), 0, st, part, kpart, nx, nbmax, nbins,
-                     dk, bins);
+  double* colsums = (double*)buf;  // the transposed spectrum is no longer needed
+  hipLaunchKernelGGL(colsum_kernel, dim3(2 * nbmax), dim3(256), 0, st, (const double*)part, nx,
+                     2 * nbmax, colsums);
+  hipLaunchKernelGGL(colsum_kernel, dim3(2), dim3(256), 0, st, (const double*)kpart, nx, 2,
+                     colsums + 2 * nbmax);
+  hipLaunchKernelGGL(spec_final_kernel, dim3(1), dim3(256), 0, st, colsums, colsums + 2 * nbmax,
+                     nbins, dk, bins);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double tail[3];
@@ -358,28 +382,15 @@ __global__ __launch_bounds__(OR_NT) void orient_row_kernel(const float* __restri
   if (t < nbins) out[2 + t] = hist[t][0];
 }
 
-// rows in fixed order: out[0] Q, out[1 .. nbins] histogram fractions, out[1+nbins ..] Q per row
-__global__ void orient_final_kernel(const double* __restrict__ rowpart, int ny, int nbins,
+// out[0] Q, out[1 .. nbins] histogram fractions, out[1+nbins ..] Q per row; tot = column sums
+// of the row partials (sum |grad phi|^2, sum (g_y^2 - g_x^2), bins).
+__global__ void orient_final_kernel(const double* __restrict__ rowpart,
+                                    const double* __restrict__ tot, int ny, int nbins,
                                     double* __restrict__ out) {
   const int t = threadIdx.x;
   const int stride = nbins + 2;
-  __shared__ double tot[2];
-  if (t == 0) {
-    double sw = 0.0, sq = 0.0;
-    for (int y = 0; y < ny; ++y) {
-      sw += rowpart[(size_t)y * stride];
-      sq += rowpart[(size_t)y * stride + 1];
-    }
-    tot[0] = sw;
-    tot[1] = sq;
-    out[0] = sw > 0 ? sq / sw : 0.0;
-  }
-  __syncthreads();
-  for (int b = t; b < nbins; b += blockDim.x) {
-    double h = 0.0;
-    for (int y = 0; y < ny; ++y) h += rowpart[(size_t)y * stride + 2 + b];
-    out[1 + b] = tot[0] > 0 ? h / tot[0] : h;
-  }
+  if (t == 0) out[0] = tot[0] > 0 ? tot[1] / tot[0] : 0.0;
+  for (int b = t; b < nbins; b += blockDim.x) out[1 + b] = tot[0] > 0 ? tot[2 + b] / tot[0] : tot[2 + b];
   for (int y = t; y < ny; y += blockDim.x) {
     double w = rowpart[(size_t)y * stride], q = rowpart[(size_t)y * stride + 1];
     out[1 + nbins + y] = w > 0 ? q / w : 0.0;
@@ -394,7 +405,11 @@ hipError_t orientation_2d(const KParams& P, const float* phi, void* scratch, int
   double* res = (double*)((char*)scratch + L.buf);        // 1 + nbins + ny doubles fit here
   hipLaunchKernelGGL(orient_row_kernel, dim3(P.ny), dim3(OR_NT), 0, st, phi, P.nx, P.ny, P.walls,
                      nbins, rowpart);
-  hipLaunchKernelGGL(orient_final_kernel, dim3(1), dim3(256), 0, st, rowpart, P.ny, nbins, res);
+  double* tot = res + 1 + nbins + P.ny;
+  hipLaunchKernelGGL(colsum_kernel, dim3(nbins + 2), dim3(256), 0, st, rowpart, P.ny, nbins + 2,
+                     tot);
+  hipLaunchKernelGGL(orient_final_kernel, dim3(1), dim3(256), 0, st, rowpart, tot, P.ny, nbins,
+                     res);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double Q;
