@@ -9,8 +9,9 @@ histogram are taken every 1000 steps inside the timed region.
 
 Prints one JSON line: MLUPS (million lattice-site updates per second), the roofline of the
 dominant kernel (fused force/stream/collide kernel; algorithmic bytes per site: populations read
-and written, 2 x 9 x 4 B, plus phi read, 4 B = 76 B), and the FP64 CPU oracle's MLUPS on a
-bounded sample of the same workload.
+and written, 2 x 9 x 4 B, plus phi read, 4 B = 76 B in 2D; 2 x 19 x 4 + 4 = 156 B in 3D), and the
+FP64 CPU oracle's MLUPS on a bounded sample of the same workload.  --workload selects another
+named workload (for example the 256^3 D3Q19 lattice) for the same measurement.
 """
 import argparse
 import hashlib
@@ -24,27 +25,34 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "c2_1024sq_tau0.6"
 HBM_PEAK_GBS = 8000.0
-LB_BYTES_PER_SITE = 76       # dominant kernel: 9 populations in + 9 out (FP32) + phi in
-STEP_BYTES_PER_SITE = 80     # whole step minimum: populations in/out + phi in/out
 OBS_EVERY = 1000
 
 
-def kernel_source_hash():
+def byte_model(dim):
+    """Algorithmic bytes per site: (dominant kernel, whole step).  Dominant kernel: populations
+    read and written (FP32) plus phi read; whole step: populations and phi read and written."""
+    q = 9 if dim == 2 else 19
+    return 2 * 4 * q + 4, 2 * (4 * q + 4)
+
+
+def kernel_source_hash(dim):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1102_3094_amd", "csrc", "lam_2d.hip"), "rb") as f:
+    name = "lam_2d.hip" if dim == 2 else "lam_3d.hip"
+    with open(os.path.join(ROOT, "paper_1102_3094_amd", "csrc", name), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(n_sites):
+def traffic_from_profiles(workload, dim):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
     or None when it is missing or was taken from another version of the kernel source."""
-    path = os.path.join(ROOT, "profiles", f"lb2d_{WORKLOAD}_traffic.json")
+    kern = "lb2d" if dim == 2 else "lb3d"
+    path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    if d.get("kernel_source_sha256_16") != kernel_source_hash(dim):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -59,11 +67,11 @@ def cpu_baseline(params, phi0, budget_s=12.0):
         o.step(1)
         steps += 1
     dt = time.perf_counter() - t0
-    n = params["nx"] * params["ny"]
+    n = params["nx"] * params["ny"] * (params["nz"] if params["dim"] == 3 else 1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    shape = "x".join(str(params[k]) for k in (("nx", "ny") if params["dim"] == 2 else ("nx", "ny", "nz")))
     return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} steps of the {params['nx']}x{params['ny']} workload "
-                      f"({dt:.1f} s, FP64, OpenMP over sites)"}
+            "sample": f"{steps} steps of the {shape} workload ({dt:.1f} s, FP64, OpenMP over sites)"}
 
 
 def main():
@@ -72,6 +80,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="named workload of synthetic.WORKLOADS (default: the 1024^2 lattice)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 counter runs: a few steps of the workload, then one plain "
                          "device copy of 512 MiB whose counters calibrate the byte counts")
@@ -87,9 +97,12 @@ def main():
     import synthetic as S
 
     lam.load()
-    p = S.model_params(WORKLOAD)
-    phi0 = S.initial_phi(WORKLOAD)
-    n_sites = p["nx"] * p["ny"]
+    wl = args.workload
+    p = S.model_params(wl)
+    phi0 = S.initial_phi(wl)
+    dim = p["dim"]
+    n_sites = p["nx"] * p["ny"] * (p["nz"] if dim == 3 else 1)
+    lb_bytes, step_bytes = byte_model(dim)
     sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(phi0, dtype=torch.float32))
     n_phi, n_T = sim.substeps
     if args.profile_pass:
@@ -102,6 +115,8 @@ def main():
         print(json.dumps({"profile_pass": True, "steps": args.steps, "copy_bytes": src.numel() * 4}))
         return
 
+    sim_step = [0]
+
     def run(k):
         done = 0
         while done < k:
@@ -109,11 +124,10 @@ def main():
             sim.step(chunk)
             done += chunk
             sim_step[0] += chunk
-            if sim_step[0] % OBS_EVERY == 0:
-                sim.structure_factor(p["nx"] // 2)
+            if sim_step[0] % OBS_EVERY == 0 and dim == 2:
+                sim.structure_factor(min(p["nx"], p["ny"]) // 2)
                 sim.orientation(18)
 
-    sim_step = [0]
     run(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -122,7 +136,8 @@ def main():
     dt = time.perf_counter() - t0
     mlups = n_sites * args.steps / dt / 1e6
 
-    # second pass of the same length with HIP events around every kernel on the library's stream
+    # second pass of the same length; every kernel launch carries HIP events (kernel timestamps)
+    # on the library's stream
     sim.set_timing(True)
     run(args.steps)
     kt = sim.kernel_times()
@@ -130,9 +145,12 @@ def main():
     lb_ms, lb_n = kt["lb"]
     phi_ms, phi_n = kt["phi"]
     lb_avg_s = lb_ms / max(lb_n, 1) / 1e3
-    achieved = LB_BYTES_PER_SITE * n_sites / lb_avg_s / 1e9
-    traffic = traffic_from_profiles(n_sites)
+    achieved = lb_bytes * n_sites / lb_avg_s / 1e9
     ob = sim.observables()
+    kname = "lb2d" if dim == 2 else "lb3d"
+    shape = "x".join(str(p[k]) for k in (("nx", "ny") if dim == 2 else ("nx", "ny", "nz")))
+    lattice = "D2Q9" if dim == 2 else "D3Q19"
+    extras = f", S(k)+orientation every {OBS_EVERY} steps" if dim == 2 else ""
 
     out = {
         "metric": "MLUPS + % HBM roofline; surrogate vs plain wall-time at equal S(k) peak error",
@@ -147,18 +165,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"D2Q9 {p['nx']}x{p['ny']} cold walls, tau={p['tau']}, "
-                               f"xi={p['xi']}, n_phi={n_phi}, n_T={n_T}, S(k)+orientation "
-                               f"every {OBS_EVERY} steps",
-                   "nx": p["nx"], "ny": p["ny"], "tau": p["tau"], "xi": p["xi"],
-                   "n_phi_sub": n_phi, "seed": 1},
+        "config": {"workload": f"{lattice} {shape} cold walls, tau={p['tau']}, xi={p['xi']}, "
+                               f"n_phi={n_phi}, n_T={n_T}{extras}",
+                   "name": wl, "lattice": lattice, "shape": shape, "tau": p["tau"],
+                   "xi": p["xi"], "n_phi_sub": n_phi, "seed": 1},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "lb2d (force + stream + collide)",
-                     "bytes_per_site": LB_BYTES_PER_SITE, "avg_launch_us": lb_avg_s * 1e6,
+                     "traffic": traffic_from_profiles(wl, dim),
+                     "kernel": f"{kname} (force + stream + collide)",
+                     "bytes_per_site": lb_bytes, "avg_launch_us": lb_avg_s * 1e6,
                      "launches": lb_n},
-        "step_effective_roofline_frac": round(mlups * 1e6 * STEP_BYTES_PER_SITE / 8e12, 4),
-        "kernel_avg_us": {"lb2d": lb_avg_s * 1e6, "phi2d": phi_ms / max(phi_n, 1) * 1e3},
+        "step_effective_roofline_frac": round(mlups * 1e6 * step_bytes / 8e12, 4),
+        "kernel_avg_us": {kname: lb_avg_s * 1e6,
+                          ("phi2d" if dim == 2 else "phi3d"): phi_ms / max(phi_n, 1) * 1e3},
         "state_finite_at_end": not ob["nonfinite"],
     }
     if not args.no_cpu_baseline:

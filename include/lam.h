@@ -135,8 +135,8 @@ int lam_state_bytes(const lam_sim* s, size_t* bytes);
 int lam_get_state(lam_sim* s, void* d_buf, size_t bytes);
 int lam_set_state(lam_sim* s, const void* d_buf, size_t bytes);
 
-/* Profiling aid.  With timing enabled, lam_step brackets each kernel it launches with HIP events
- * on the simulation's stream.  lam_kernel_times synchronises, writes the accumulated kernel time
+/* Profiling aid.  With timing enabled, lam_step launches each kernel with a pair of HIP events
+ * that take the kernel's own start and end timestamps (hipExtLaunchKernelGGL).  lam_kernel_times synchronises, writes the accumulated kernel time
  * in milliseconds and the launch count of each kernel class (LAM_K_LB: the fused force /
  * stream / collide kernel; LAM_K_PHI: the order-parameter kernel) into h_ms[nk] and
  * h_launches[nk] (host arrays), and resets the accumulators.  Events are created on first use

@@ -13,6 +13,8 @@
 // phi2d<S>: S explicit Euler sub-steps of the order-parameter equation on a tile with halo 3S,
 //   all in LDS (temporal blocking), reading phi and u once and writing phi once.  The workgroup
 //   of tile 0 also advances the per-row temperature.
+#include <hip/hip_ext.h>
+
 #include "lam_dev.hpp"
 
 namespace lam {
@@ -377,62 +379,75 @@ static int blocks2d(const KParams& P, int ty) {
 
 int lb2d_blocks(const KParams& P, int ty) { return blocks2d(P, ty); }
 
+// With timing events given, the launch carries them (hipExtLaunchKernelGGL): their timestamps
+// are the kernel's own start and end.
+template <typename K, typename... A>
+static void launch(K kern, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                   A... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+}
+
 template <int TY>
 static void lb2d_launch(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
-                        const float* Trow, float* u, float* n, double* partials, hipStream_t st) {
+                        const float* Trow, float* u, float* n, double* partials, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
   dim3 grid(blocks2d(P, TY)), block(16 * TY);
   if (mode == MODE_STEP)
-    hipLaunchKernelGGL((lb2d_kernel<TY, MODE_STEP>), grid, block, 0, st, P, gin, gout, phi, Trow,
-                       u, n, partials);
+    launch(lb2d_kernel<TY, MODE_STEP>, grid, block, st, e0, e1, P, gin, gout, phi, Trow, u, n,
+           partials);
   else if (mode == MODE_OBS)
-    hipLaunchKernelGGL((lb2d_kernel<TY, MODE_OBS>), grid, block, 0, st, P, gin, gout, phi, Trow,
-                       u, n, partials);
+    launch(lb2d_kernel<TY, MODE_OBS>, grid, block, st, e0, e1, P, gin, gout, phi, Trow, u, n,
+           partials);
   else
-    hipLaunchKernelGGL((lb2d_kernel<TY, MODE_FIELDS>), grid, block, 0, st, P, gin, gout, phi,
-                       Trow, u, n, partials);
+    launch(lb2d_kernel<TY, MODE_FIELDS>, grid, block, st, e0, e1, P, gin, gout, phi, Trow, u, n,
+           partials);
 }
 
 hipError_t launch_lb2d(const KParams& P, int ty, int mode, const float* gin, float* gout,
                        const float* phi, const float* Trow, float* u, float* n, double* partials,
-                       hipStream_t st) {
-  if (ty == 8) lb2d_launch<8>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
-  else if (ty == 16) lb2d_launch<16>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
-  else if (ty == 32) lb2d_launch<32>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
-  else if (ty == 64) lb2d_launch<64>(P, mode, gin, gout, phi, Trow, u, n, partials, st);
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (ty == 8) lb2d_launch<8>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else if (ty == 16) lb2d_launch<16>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else if (ty == 32) lb2d_launch<32>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else if (ty == 64) lb2d_launch<64>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <int S_, int TY>
 static void phi2d_launch(const KParams& P, const float* in, float* out, const float* u,
-                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st) {
+                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1) {
   dim3 grid(blocks2d(P, TY)), block(16 * TY);
   if (P.hydro)
-    hipLaunchKernelGGL((phi2d_kernel<S_, TY, true>), grid, block, 0, st, P, in, out, u, T, Tn, Ts,
-                       do_T);
+    launch(phi2d_kernel<S_, TY, true>, grid, block, st, e0, e1, P, in, out, u, T, Tn, Ts, do_T);
   else
-    hipLaunchKernelGGL((phi2d_kernel<S_, TY, false>), grid, block, 0, st, P, in, out, u, T, Tn,
-                       Ts, do_T);
+    launch(phi2d_kernel<S_, TY, false>, grid, block, st, e0, e1, P, in, out, u, T, Tn, Ts, do_T);
 }
 
 int phi2d_max_sub() { return 2; }
 
 hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, float* out,
                         const float* u, const float* T, float* Tn, float* Ts, int do_T,
-                        hipStream_t st) {
+                        hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (nsub < 1 || nsub > 2 || (ty != 8 && ty != 16 && ty != 32 && ty != 64))
     return hipErrorInvalidValue;
+#define PHI_CASE(S_, TY_) phi2d_launch<S_, TY_>(P, in, out, u, T, Tn, Ts, do_T, st, e0, e1)
   if (nsub == 1) {
-    if (ty == 8) phi2d_launch<1, 8>(P, in, out, u, T, Tn, Ts, do_T, st);
-    else if (ty == 16) phi2d_launch<1, 16>(P, in, out, u, T, Tn, Ts, do_T, st);
-    else if (ty == 32) phi2d_launch<1, 32>(P, in, out, u, T, Tn, Ts, do_T, st);
-    else phi2d_launch<1, 64>(P, in, out, u, T, Tn, Ts, do_T, st);
+    if (ty == 8) PHI_CASE(1, 8);
+    else if (ty == 16) PHI_CASE(1, 16);
+    else if (ty == 32) PHI_CASE(1, 32);
+    else PHI_CASE(1, 64);
   } else {
-    if (ty == 8) phi2d_launch<2, 8>(P, in, out, u, T, Tn, Ts, do_T, st);
-    else if (ty == 16) phi2d_launch<2, 16>(P, in, out, u, T, Tn, Ts, do_T, st);
-    else if (ty == 32) phi2d_launch<2, 32>(P, in, out, u, T, Tn, Ts, do_T, st);
-    else phi2d_launch<2, 64>(P, in, out, u, T, Tn, Ts, do_T, st);
+    if (ty == 8) PHI_CASE(2, 8);
+    else if (ty == 16) PHI_CASE(2, 16);
+    else if (ty == 32) PHI_CASE(2, 32);
+    else PHI_CASE(2, 64);
   }
+#undef PHI_CASE
   return hipGetLastError();
 }
 

@@ -1,0 +1,432 @@
+// lam_3d.hip -- gfx950 kernels of one D3Q19 time step (arXiv:1102.3094, Section 2, with the
+// standard three-dimensional velocity set; walls normal to z).
+//
+// Both kernels march along z over a 32 x 8 xy tile ("2.5D" blocking): LDS holds a few xy slices
+// of each field in ring buffers, so the 7-point Laplacian, the 25-point biharmonic and the
+// pressure-tensor divergence need halos only in x and y.  A workgroup owns a chunk of ZCH
+// slices and starts the pipeline a few slices early.
+//
+// lb3d: per slice, load phi (xy halo 3) -> L = lap phi (halo 2) -> pressure tensor (6 entries,
+//   halo 1) -> for the output slice, -div P, pull of 19 populations (issued one pipeline stage
+//   ahead), moments, BGK + forcing collision, write 19 populations and u.
+// phi3d: per slice, load psi (halo 3) and u (halo 1) -> mu with the 25-point biharmonic (halo 1)
+//   -> psi' = psi + h (Gamma lap mu - div(psi u)) for the output slice.  One Euler sub-step per
+//   launch; the workgroup of tile 0 of the last launch also advances the per-layer temperature.
+#include <hip/hip_ext.h>
+
+#include "lam_dev.hpp"
+
+namespace lam {
+
+constexpr int BX = 32, BY = 8, NT3 = BX * BY;
+constexpr int ZCH = 32;  // z slices per workgroup
+enum { MODE3_STEP = 0, MODE3_OBS = 1, MODE3_FIELDS = 2 };
+
+// D3Q19: rest; faces +-x, +-y, +-z; edges in xy, xz, yz (opposites adjacent).
+constexpr int E19[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                            {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                            {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                            {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+__host__ __device__ constexpr int opp19(int q) { return q == 0 ? 0 : (q % 2 ? q + 1 : q - 1); }
+__host__ __device__ constexpr float w19(int q) {
+  return q == 0 ? 1.f / 3.f : (q <= 6 ? 1.f / 18.f : 1.f / 36.f);
+}
+
+struct Tile3 {
+  int x0, y0, z0, z1;
+};
+
+__device__ __forceinline__ Tile3 tile3(const KParams& P) {
+  const int nbx = (P.nx + BX - 1) / BX, nby = (P.ny + BY - 1) / BY, nbz = (P.nz + ZCH - 1) / ZCH;
+  const int t = xcd_tile(blockIdx.x, nbx * nby * nbz);
+  const int bz = t % nbz, rest = t / nbz;
+  Tile3 T;
+  T.x0 = (rest % nbx) * BX;
+  T.y0 = (rest / nbx) * BY;
+  T.z0 = bz * ZCH;
+  T.z1 = min(T.z0 + ZCH, P.nz);
+  return T;
+}
+
+struct Lb3dSmem {
+  float phi[5][BY + 6][BX + 6];
+  float L[4][BY + 4][BX + 4];
+  float P[4][6][BY + 2][BX + 2];  // xx, yy, zz, xy, xz, yz (or mu in [0] for -phi grad mu)
+  double red[NT3 / 64][R_N];
+};
+
+template <int MODE>
+__global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __restrict__ gin,
+                                                   float* __restrict__ gout,
+                                                   const float* __restrict__ phi,
+                                                   const float* __restrict__ Trow,
+                                                   float* __restrict__ uout,
+                                                   float* __restrict__ nout,
+                                                   double* __restrict__ partials) {
+  __shared__ Lb3dSmem S;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
+  const Tile3 T = tile3(P);
+  const int x = T.x0 + tx, y = T.y0 + ty;
+  const bool in_xy = x < nx && y < ny;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x >= nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y >= ny - 1 ? 0 : y + 1;
+
+  double acc[R_N];
+#pragma unroll
+  for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
+  float g[19];
+
+  for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
+    const int s_load = T.z0 - 3 + k, s_L = s_load - 1, s_P = s_load - 2, s_out = s_load - 3;
+    const bool do_out = s_out >= T.z0 && in_xy;
+    // pulls of the output slice first: f_q(x) = f*_q(x - e_q), bounce-back across a wall
+    if (do_out) {
+      const int z = s_out;
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        const int ex = E19[q][0], ey = E19[q][1], ez = E19[q][2];
+        const int sz = z - ez;
+        size_t idx;
+        int qq = q;
+        if (P.walls && (sz < 0 || sz >= nz)) {
+          qq = opp19(q);
+          idx = ((size_t)z * ny + y) * nx + x;
+        } else {
+          const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
+          const int sy = ey == 1 ? ym : (ey == -1 ? yp : y);
+          const int zz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+          idx = ((size_t)zz * ny + sy) * nx + sx;
+        }
+        g[q] = gin[(size_t)qq * N + idx];
+      }
+    }
+    {  // phi slice s_load with xy halo 3
+      bool f;
+      const int gz = wall_axis(s_load, nz, P.walls, f);
+      float(*dst)[BX + 6] = S.phi[((s_load % 5) + 5) % 5];
+      for (int i = tid; i < (BY + 6) * (BX + 6); i += NT3) {
+        int r = i / (BX + 6), c = i - r * (BX + 6);
+        int gy = wrap(T.y0 - 3 + r, ny), gx = wrap(T.x0 - 3 + c, nx);
+        dst[r][c] = phi[((size_t)gz * ny + gy) * nx + gx];
+      }
+    }
+    __syncthreads();
+    if (s_L >= T.z0 - 2) {  // L slice s_L with xy halo 2
+      float(*pc)[BX + 6] = S.phi[((s_L % 5) + 5) % 5];
+      float(*pd)[BX + 6] = S.phi[(((s_L - 1) % 5) + 5) % 5];
+      float(*pu)[BX + 6] = S.phi[(((s_L + 1) % 5) + 5) % 5];
+      float(*dst)[BX + 4] = S.L[((s_L % 4) + 4) % 4];
+      for (int i = tid; i < (BY + 4) * (BX + 4); i += NT3) {
+        int r = i / (BX + 4), c = i - r * (BX + 4);
+        const int R = r + 1, C = c + 1;
+        dst[r][c] = ((pc[R][C + 1] + pc[R][C - 1]) + (pc[R + 1][C] + pc[R - 1][C])) +
+                    (pu[R][C] + pd[R][C]) - 6.f * pc[R][C];
+      }
+    }
+    __syncthreads();
+    if (P.hydro && s_P >= T.z0 - 1) {  // pressure tensor (or mu) of slice s_P with xy halo 1
+      bool f;
+      const int gz = wall_axis(s_P, nz, P.walls, f);
+      const float a = (Trow[gz] - P.Tc) / P.Tc;
+      float(*pc)[BX + 6] = S.phi[((s_P % 5) + 5) % 5];
+      float(*pd)[BX + 6] = S.phi[(((s_P - 1) % 5) + 5) % 5];
+      float(*pu)[BX + 6] = S.phi[(((s_P + 1) % 5) + 5) % 5];
+      float(*lc)[BX + 4] = S.L[((s_P % 4) + 4) % 4];
+      float(*ld)[BX + 4] = S.L[(((s_P - 1) % 4) + 4) % 4];
+      float(*lu)[BX + 4] = S.L[(((s_P + 1) % 4) + 4) % 4];
+      float(*dst)[BY + 2][BX + 2] = S.P[((s_P % 4) + 4) % 4];
+      for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
+        int r = i / (BX + 2), c = i - r * (BX + 2);
+        const int R = r + 2, C = c + 2, r1 = r + 1, c1 = c + 1;
+        const float ph = pc[R][C], L = lc[r1][c1];
+        const float M = ((lc[r1][c1 + 1] + lc[r1][c1 - 1]) + (lc[r1 + 1][c1] + lc[r1 - 1][c1])) +
+                        (lu[r1][c1] + ld[r1][c1]) - 6.f * L;
+        if (P.force_form == 1) {
+          dst[0][r][c] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
+        } else {
+          const float px = 0.5f * (pc[R][C + 1] - pc[R][C - 1]);
+          const float py = 0.5f * (pc[R + 1][C] - pc[R - 1][C]);
+          const float pz = 0.5f * (pu[R][C] - pd[R][C]);
+          const float Lx = 0.5f * (lc[r1][c1 + 1] - lc[r1][c1 - 1]);
+          const float Ly = 0.5f * (lc[r1 + 1][c1] - lc[r1 - 1][c1]);
+          const float Lz = 0.5f * (lu[r1][c1] - ld[r1][c1]);
+          const float ph2 = ph * ph;
+          const float p0 = 0.5f * a * ph2 + 0.75f * P.b * ph2 * ph2 -
+                           P.kappa * (ph * L + 0.5f * (px * px + py * py + pz * pz)) +
+                           P.c * (ph * M + 0.5f * L * L + (px * Lx + py * Ly + pz * Lz));
+          dst[0][r][c] = p0 + P.kappa * px * px - 2.f * P.c * px * Lx;
+          dst[1][r][c] = p0 + P.kappa * py * py - 2.f * P.c * py * Ly;
+          dst[2][r][c] = p0 + P.kappa * pz * pz - 2.f * P.c * pz * Lz;
+          dst[3][r][c] = P.kappa * px * py - P.c * (px * Ly + py * Lx);
+          dst[4][r][c] = P.kappa * px * pz - P.c * (px * Lz + pz * Lx);
+          dst[5][r][c] = P.kappa * py * pz - P.c * (py * Lz + pz * Ly);
+        }
+      }
+    }
+    __syncthreads();
+    if (do_out) {
+      const int z = s_out, r = ty + 1, c = tx + 1;
+      float(*Pc)[BY + 2][BX + 2] = S.P[((z % 4) + 4) % 4];
+      float(*Pd)[BY + 2][BX + 2] = S.P[(((z - 1) % 4) + 4) % 4];
+      float(*Pu)[BY + 2][BX + 2] = S.P[(((z + 1) % 4) + 4) % 4];
+      float(*pc)[BX + 6] = S.phi[((z % 5) + 5) % 5];
+      float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+      if (P.hydro) {
+        if (P.force_form == 1) {
+          const float ph = pc[ty + 3][tx + 3];
+          Fx = -ph * (0.5f * (Pc[0][r][c + 1] - Pc[0][r][c - 1]));
+          Fy = -ph * (0.5f * (Pc[0][r + 1][c] - Pc[0][r - 1][c]));
+          Fz = -ph * (0.5f * (Pu[0][r][c] - Pd[0][r][c]));
+        } else {
+          Fx = -(0.5f * (Pc[0][r][c + 1] - Pc[0][r][c - 1]) + 0.5f * (Pc[3][r + 1][c] - Pc[3][r - 1][c]) +
+                 0.5f * (Pu[4][r][c] - Pd[4][r][c]));
+          Fy = -(0.5f * (Pc[3][r][c + 1] - Pc[3][r][c - 1]) + 0.5f * (Pc[1][r + 1][c] - Pc[1][r - 1][c]) +
+                 0.5f * (Pu[5][r][c] - Pd[5][r][c]));
+          Fz = -(0.5f * (Pc[4][r][c + 1] - Pc[4][r][c - 1]) + 0.5f * (Pc[5][r + 1][c] - Pc[5][r - 1][c]) +
+                 0.5f * (Pu[2][r][c] - Pd[2][r][c]));
+        }
+      }
+      float dn = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        dn += g[q];
+        if (E19[q][0]) jx += E19[q][0] > 0 ? g[q] : -g[q];
+        if (E19[q][1]) jy += E19[q][1] > 0 ? g[q] : -g[q];
+        if (E19[q][2]) jz += E19[q][2] > 0 ? g[q] : -g[q];
+      }
+      const float n = 1.f + dn;
+      Fx += n * P.gx;
+      Fy += n * P.gy;
+      Fz += n * P.gz;
+      float ux = 0.f, uy = 0.f, uz = 0.f;
+      if (P.hydro) {
+        const float inv = 1.f / n;
+        ux = (jx + 0.5f * Fx) * inv;
+        uy = (jy + 0.5f * Fy) * inv;
+        uz = (jz + 0.5f * Fz) * inv;
+      }
+      const size_t s = ((size_t)z * ny + y) * nx + x;
+      if (MODE == MODE3_STEP) {
+        const float usq = 1.5f * (ux * ux + uy * uy + uz * uz);
+        const float uF = ux * Fx + uy * Fy + uz * Fz;
+        const float om = P.omega, kf = P.kforce;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+          const float w = w19(q);
+          const float eu = E19[q][0] * ux + E19[q][1] * uy + E19[q][2] * uz;
+          const float eF = E19[q][0] * Fx + E19[q][1] * Fy + E19[q][2] * Fz;
+          const float geq = w * (dn + n * (eu * (3.f + 4.5f * eu) - usq));
+          const float frc = kf * w * (3.f * (eF - uF) + 9.f * eu * eF);
+          gout[(size_t)q * N + s] = g[q] + om * (geq - g[q]) + frc;
+        }
+        uout[s] = ux;
+        uout[N + s] = uy;
+        uout[2 * N + s] = uz;
+      } else if (MODE == MODE3_FIELDS) {
+        uout[s] = ux;
+        uout[N + s] = uy;
+        uout[2 * N + s] = uz;
+        if (nout) nout[s] = n;
+      } else {
+        bool f;
+        const int gz = wall_axis(z, nz, P.walls, f);
+        const float a = (Trow[gz] - P.Tc) / P.Tc;
+        float(*pu)[BX + 6] = S.phi[(((z + 1) % 5) + 5) % 5];
+        const float ph = pc[ty + 3][tx + 3];
+        const float L = S.L[((z % 4) + 4) % 4][ty + 2][tx + 2];
+        const float dx = pc[ty + 3][tx + 4] - ph, dy = pc[ty + 4][tx + 3] - ph,
+                    dz = pu[ty + 3][tx + 3] - ph;
+        const float fe = 0.5f * a * ph * ph + 0.25f * P.b * ph * ph * ph * ph +
+                         0.5f * P.kappa * (dx * dx + dy * dy + dz * dz) + 0.5f * P.c * L * L;
+        acc[R_MASS] += (double)dn;
+        acc[R_JX] += (double)jx;
+        acc[R_JY] += (double)jy;
+        acc[R_JZ] += (double)jz;
+        acc[R_PHI] += (double)ph;
+        acc[R_FE] += (double)fe;
+        acc[R_UMAX] = fmax(acc[R_UMAX], (double)sqrtf(ux * ux + uy * uy + uz * uz));
+        if (!(isfinite(dn) && isfinite(jx) && isfinite(jy) && isfinite(jz) && isfinite(ph)))
+          acc[R_BAD] = 1.0;
+      }
+    }
+  }
+
+  if (MODE == MODE3_OBS) {
+    const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int k = 0; k < R_N; ++k) {
+      double v = (k == R_UMAX || k == R_BAD) ? wave_max(acc[k]) : wave_sum(acc[k]);
+      if (lane == 0) S.red[wave][k] = v;
+    }
+    __syncthreads();
+    if (tid < R_N) {
+      double v = S.red[0][tid];
+      for (int w = 1; w < NT3 / 64; ++w)
+        v = (tid == R_UMAX || tid == R_BAD) ? fmax(v, S.red[w][tid]) : v + S.red[w][tid];
+      partials[(size_t)blockIdx.x * R_N + tid] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// psi ring of 6: the load of slice z + 4 must not overwrite slice z - 1, which slower threads may
+// still read for the output slice z of the previous iteration (no barrier between them).
+struct Phi3dSmem {
+  float psi[6][BY + 6][BX + 6];
+  float mu[4][BY + 2][BX + 2];
+  float u[4][3][BY + 2][BX + 2];
+};
+
+template <bool HYDRO>
+__global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __restrict__ psi_in,
+                                                    float* __restrict__ psi_out,
+                                                    const float* __restrict__ u,
+                                                    const float* __restrict__ Trow,
+                                                    float* __restrict__ Tnext,
+                                                    float* __restrict__ Tscr, int do_T) {
+  __shared__ Phi3dSmem S;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
+  const Tile3 T = tile3(P);
+  const int x = T.x0 + tx, y = T.y0 + ty;
+  const bool in_xy = x < nx && y < ny;
+
+  for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
+    const int s_load = T.z0 - 3 + k, s_mu = s_load - 2, s_out = s_load - 3;
+    {  // psi slice s_load (xy halo 3); u slice s_mu (xy halo 1, normal component odd)
+      bool f;
+      const int gz = wall_axis(s_load, nz, P.walls, f);
+      float(*dst)[BX + 6] = S.psi[((s_load % 6) + 6) % 6];
+      for (int i = tid; i < (BY + 6) * (BX + 6); i += NT3) {
+        int r = i / (BX + 6), c = i - r * (BX + 6);
+        int gy = wrap(T.y0 - 3 + r, ny), gx = wrap(T.x0 - 3 + c, nx);
+        dst[r][c] = psi_in[((size_t)gz * ny + gy) * nx + gx];
+      }
+      if (HYDRO && s_mu >= T.z0 - 1) {
+        bool fl;
+        const int uz = wall_axis(s_mu, nz, P.walls, fl);
+        float(*ud)[BY + 2][BX + 2] = S.u[((s_mu % 4) + 4) % 4];
+        for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
+          int r = i / (BX + 2), c = i - r * (BX + 2);
+          int gy = wrap(T.y0 - 1 + r, ny), gx = wrap(T.x0 - 1 + c, nx);
+          size_t s = ((size_t)uz * ny + gy) * nx + gx;
+          ud[0][r][c] = u[s];
+          ud[1][r][c] = u[N + s];
+          float vz = u[2 * N + s];
+          ud[2][r][c] = fl ? -vz : vz;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_mu >= T.z0 - 1) {  // mu of slice s_mu with xy halo 1 (25-point biharmonic)
+      bool f;
+      const int gz = wall_axis(s_mu, nz, P.walls, f);
+      const float a = (Trow[gz] - P.Tc) / P.Tc;
+      float(*c0)[BX + 6] = S.psi[((s_mu % 6) + 6) % 6];
+      float(*m1)[BX + 6] = S.psi[(((s_mu - 1) % 6) + 6) % 6];
+      float(*p1)[BX + 6] = S.psi[(((s_mu + 1) % 6) + 6) % 6];
+      float(*m2)[BX + 6] = S.psi[(((s_mu - 2) % 6) + 6) % 6];
+      float(*p2)[BX + 6] = S.psi[(((s_mu + 2) % 6) + 6) % 6];
+      float(*dst)[BX + 2] = S.mu[((s_mu % 4) + 4) % 4];
+      for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
+        int r = i / (BX + 2), cc = i - r * (BX + 2);
+        const int R = r + 2, C = cc + 2;
+        const float v = c0[R][C];
+        const float face = ((c0[R][C + 1] + c0[R][C - 1]) + (c0[R + 1][C] + c0[R - 1][C])) +
+                           (p1[R][C] + m1[R][C]);
+        const float edge = ((c0[R + 1][C + 1] + c0[R + 1][C - 1]) + (c0[R - 1][C + 1] + c0[R - 1][C - 1])) +
+                           ((p1[R][C + 1] + p1[R][C - 1]) + (m1[R][C + 1] + m1[R][C - 1])) +
+                           ((p1[R + 1][C] + p1[R - 1][C]) + (m1[R + 1][C] + m1[R - 1][C]));
+        const float far = ((c0[R][C + 2] + c0[R][C - 2]) + (c0[R + 2][C] + c0[R - 2][C])) +
+                          (p2[R][C] + m2[R][C]);
+        const float L = face - 6.f * v;
+        const float M = 42.f * v - 12.f * face + 2.f * edge + far;
+        dst[r][cc] = a * v + P.b * v * v * v - P.kappa * L + P.c * M;
+      }
+    }
+    __syncthreads();
+    if (s_out >= T.z0 && in_xy) {
+      const int z = s_out, r = ty + 1, c = tx + 1, R = ty + 3, C = tx + 3;
+      float(*mc)[BX + 2] = S.mu[((z % 4) + 4) % 4];
+      float(*md)[BX + 2] = S.mu[(((z - 1) % 4) + 4) % 4];
+      float(*mu_)[BX + 2] = S.mu[(((z + 1) % 4) + 4) % 4];
+      float(*pc)[BX + 6] = S.psi[((z % 6) + 6) % 6];
+      float(*pd)[BX + 6] = S.psi[(((z - 1) % 6) + 6) % 6];
+      float(*pu)[BX + 6] = S.psi[(((z + 1) % 6) + 6) % 6];
+      const float lapmu = ((mc[r][c + 1] + mc[r][c - 1]) + (mc[r + 1][c] + mc[r - 1][c])) +
+                          (mu_[r][c] + md[r][c]) - 6.f * mc[r][c];
+      float adv = 0.f;
+      if (HYDRO) {
+        float(*uc)[BY + 2][BX + 2] = S.u[((z % 4) + 4) % 4];
+        float(*ud)[BY + 2][BX + 2] = S.u[(((z - 1) % 4) + 4) % 4];
+        float(*uu)[BY + 2][BX + 2] = S.u[(((z + 1) % 4) + 4) % 4];
+        adv = 0.5f * (pc[R][C + 1] * uc[0][r][c + 1] - pc[R][C - 1] * uc[0][r][c - 1]) +
+              0.5f * (pc[R + 1][C] * uc[1][r + 1][c] - pc[R - 1][C] * uc[1][r - 1][c]) +
+              0.5f * (pu[R][C] * uu[2][r][c] - pd[R][C] * ud[2][r][c]);
+      }
+      psi_out[((size_t)z * ny + y) * nx + x] = pc[R][C] + P.h * (-adv + P.Gamma * lapmu);
+    }
+  }
+
+  // Temperature: FTCS sub-steps along z (T is uniform in x and y); wall layers held.
+  if (do_T && blockIdx.x == 0 && P.n_T > 0) {
+    __syncthreads();
+    const float* src = Trow;
+    for (int m = 0; m < P.n_T; ++m) {
+      float* dst = ((P.n_T - 1 - m) % 2 == 0) ? Tnext : Tscr;
+      for (int j = tid; j < nz; j += NT3) {
+        float v = src[j];
+        bool wall = P.walls && (j == 0 || j == nz - 1);
+        if (!wall) {
+          float lo = src[j == 0 ? nz - 1 : j - 1], hi = src[j == nz - 1 ? 0 : j + 1];
+          v = v + P.r_T * ((lo + hi) - 2.f * v);
+        }
+        dst[j] = v;
+      }
+      __syncthreads();
+      src = dst;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+int blocks3d(const KParams& P) {
+  return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + ZCH - 1) / ZCH);
+}
+
+template <typename K, typename... A>
+static void launch3(K kern, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(NT3), 0, st, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(NT3), 0, st, args...);
+}
+
+hipError_t launch_lb3d(const KParams& P, int mode, const float* gin, float* gout,
+                       const float* phi, const float* Trow, float* u, float* n, double* partials,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const int nb = blocks3d(P);
+  if (mode == MODE3_STEP)
+    launch3(lb3d_kernel<MODE3_STEP>, nb, st, e0, e1, P, gin, gout, phi, Trow, u, n, partials);
+  else if (mode == MODE3_OBS)
+    launch3(lb3d_kernel<MODE3_OBS>, nb, st, e0, e1, P, gin, gout, phi, Trow, u, n, partials);
+  else
+    launch3(lb3d_kernel<MODE3_FIELDS>, nb, st, e0, e1, P, gin, gout, phi, Trow, u, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi3d(const KParams& P, const float* in, float* out, const float* u,
+                        const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
+  const int nb = blocks3d(P);
+  if (P.hydro)
+    launch3(phi3d_kernel<true>, nb, st, e0, e1, P, in, out, u, T, Tn, Ts, do_T);
+  else
+    launch3(phi3d_kernel<false>, nb, st, e0, e1, P, in, out, u, T, Tn, Ts, do_T);
+  return hipGetLastError();
+}
+
+}  // namespace lam

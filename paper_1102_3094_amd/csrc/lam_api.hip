@@ -18,11 +18,19 @@ enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
 int lb2d_blocks(const KParams& P, int ty);
 hipError_t launch_lb2d(const KParams& P, int ty, int mode, const float* gin, float* gout,
                        const float* phi, const float* Trow, float* u, float* n, double* partials,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int phi2d_max_sub();
 hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, float* out,
                         const float* u, const float* T, float* Tn, float* Ts, int do_T,
-                        hipStream_t st);
+                        hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// lam_3d.hip
+int blocks3d(const KParams& P);
+hipError_t launch_lb3d(const KParams& P, int mode, const float* gin, float* gout,
+                       const float* phi, const float* Trow, float* u, float* n, double* partials,
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_phi3d(const KParams& P, const float* in, float* out, const float* u,
+                        const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // lam_util.hip
 hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, float* g,
                        hipStream_t st);
@@ -159,7 +167,6 @@ int hip_fail(lam_sim* s, hipError_t e, const char* where) {
 int validate(const lam_params* p, std::string& why) {
   if (!p) return why = "null parameters", LAM_EINVAL;
   if (p->dim != 2 && p->dim != 3) return why = "dim must be 2 or 3", LAM_EINVAL;
-  if (p->dim == 3) return why = "3D (D3Q19) is not available in this build", LAM_EINVAL;
   if (p->nx < 8 || p->ny < 8) return why = "nx and ny must be >= 8", LAM_EINVAL;
   if (p->dim == 2 && p->nz != 1) return why = "nz must be 1 in 2D", LAM_EINVAL;
   if (p->dim == 3 && p->nz < 8) return why = "nz must be >= 8 in 3D", LAM_EINVAL;
@@ -216,8 +223,9 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   s->nphi = p->n_phi_sub > 0 ? p->n_phi_sub : auto_nphi(*p);
   s->nT = p->n_T_sub > 0 ? p->n_T_sub : auto_nT(*p);
   s->st = (hipStream_t)hip_stream;
-  s->ty_lb = p->tile_hint ? p->tile_hint : 16;
-  s->ty_phi = p->tile_hint ? p->tile_hint : 16;
+  // 64 x 32 tiles measured fastest on MI355X for 1024^2 and 4096^2 lattices
+  s->ty_lb = p->tile_hint ? p->tile_hint : 32;
+  s->ty_phi = p->tile_hint ? p->tile_hint : 32;
   s->ws = (char*)d_workspace;
   s->ws_bytes = bytes;
   for (int i = 0; i < 2; ++i) {
@@ -279,25 +287,27 @@ int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const fl
 }
 
 namespace {
-// Record the start event of a timed launch; returns the slot or -1 when timing is off.
-long timing_begin(lam_sim* s, int cls) {
-  if (!s->timing) return -1;
+// Event pair of the next timed launch of class cls, or (nullptr, nullptr) when timing is off.
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+EvPair timing_slot(lam_sim* s, int cls) {
+  EvPair e;
+  if (!s->timing) return e;
   if (s->ev_used + 2 > s->ev.size()) {
     for (int i = 0; i < 2; ++i) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return -1;
-      s->ev.push_back(e);
+      hipEvent_t h;
+      if (hipEventCreate(&h) != hipSuccess) return e;
+      s->ev.push_back(h);
       s->ev_cls.push_back(0);
     }
   }
-  long slot = (long)s->ev_used;
+  size_t slot = s->ev_used;
   s->ev_cls[slot] = cls;
   s->ev_used += 2;
-  hipEventRecord(s->ev[slot], s->st);
-  return slot;
-}
-void timing_end(lam_sim* s, long slot) {
-  if (slot >= 0) hipEventRecord(s->ev[slot + 1], s->st);
+  e.a = s->ev[slot];
+  e.b = s->ev[slot + 1];
+  return e;
 }
 }  // namespace
 
@@ -332,14 +342,18 @@ int lam_step(lam_sim* s, int64_t nsteps) {
   if (!s || nsteps < 0) return fail(s, LAM_EINVAL, "bad arguments");
   if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
   const KParams& k = s->k;
-  const int maxsub = phi2d_max_sub();
+  const bool d3 = s->p.dim == 3;
+  const int maxsub = d3 ? 1 : phi2d_max_sub();
   for (int64_t t = 0; t < nsteps; ++t) {
     const int cur = (int)(s->step & 1), nxt = cur ^ 1;
     if (k.hydro) {
-      long ev = timing_begin(s, LAM_K_LB);
-      HIPCHK(s, launch_lb2d(k, s->ty_lb, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur],
-                            s->u, nullptr, nullptr, s->st));
-      timing_end(s, ev);
+      EvPair ev = timing_slot(s, LAM_K_LB);
+      if (d3)
+        HIPCHK(s, launch_lb3d(k, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur], s->u,
+                              nullptr, nullptr, s->st, ev.a, ev.b));
+      else
+        HIPCHK(s, launch_lb2d(k, s->ty_lb, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur],
+                              s->T[cur], s->u, nullptr, nullptr, s->st, ev.a, ev.b));
     }
     int remaining = s->nphi, which = 0;
     const float* src = s->phi[cur];
@@ -348,10 +362,14 @@ int lam_step(lam_sim* s, int64_t nsteps) {
       bool last = remaining == sub;
       float* dst = last ? s->phi[nxt] : s->psi[which];
       which ^= 1;
-      long ev = timing_begin(s, LAM_K_PHI);
-      HIPCHK(s, launch_phi2d(k, s->ty_phi, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
-                             last && k.n_T > 0, s->st));
-      timing_end(s, ev);
+      EvPair ev = timing_slot(s, LAM_K_PHI);
+      const int do_T = last && k.n_T > 0;
+      if (d3)
+        HIPCHK(s, launch_phi3d(k, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2], do_T, s->st,
+                               ev.a, ev.b));
+      else
+        HIPCHK(s, launch_phi2d(k, s->ty_phi, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
+                               do_T, s->st, ev.a, ev.b));
       src = dst;
       remaining -= sub;
     }
@@ -364,9 +382,16 @@ int lam_observables(lam_sim* s, lam_obs* o) {
   if (!s || !o) return fail(s, LAM_EINVAL, "bad arguments");
   if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
   const int cur = (int)(s->step & 1);
-  int nblk = lb2d_blocks(s->k, s->ty_lb);
-  HIPCHK(s, launch_lb2d(s->k, s->ty_lb, MODE_OBS, s->g[cur], nullptr, s->phi[cur], s->T[cur],
-                        nullptr, nullptr, s->partials, s->st));
+  int nblk;
+  if (s->p.dim == 3) {
+    nblk = blocks3d(s->k);
+    HIPCHK(s, launch_lb3d(s->k, MODE_OBS, s->g[cur], nullptr, s->phi[cur], s->T[cur], nullptr,
+                          nullptr, s->partials, s->st));
+  } else {
+    nblk = lb2d_blocks(s->k, s->ty_lb);
+    HIPCHK(s, launch_lb2d(s->k, s->ty_lb, MODE_OBS, s->g[cur], nullptr, s->phi[cur], s->T[cur],
+                          nullptr, nullptr, s->partials, s->st));
+  }
   HIPCHK(s, launch_finalize(s->partials, nblk, s->result, s->st));
   double r[R_N];
   HIPCHK(s, hipMemcpyAsync(r, s->result, sizeof(r), hipMemcpyDeviceToHost, s->st));
@@ -410,7 +435,10 @@ int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T)
   if (d_phi)
     HIPCHK(s, hipMemcpyAsync(d_phi, s->phi[cur], sizeof(float) * s->N, hipMemcpyDeviceToDevice,
                              s->st));
-  if (d_u || d_n)
+  if ((d_u || d_n) && s->p.dim == 3)
+    HIPCHK(s, launch_lb3d(s->k, MODE_FIELDS, s->g[cur], nullptr, s->phi[cur], s->T[cur],
+                          d_u ? d_u : s->u, d_n, nullptr, s->st));
+  else if (d_u || d_n)
     HIPCHK(s, launch_lb2d(s->k, s->ty_lb, MODE_FIELDS, s->g[cur], nullptr, s->phi[cur],
                           s->T[cur], d_u ? d_u : s->u, d_n, nullptr, s->st));
   if (d_T) {

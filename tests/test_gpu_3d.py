@@ -1,0 +1,91 @@
+"""GPU parity of the D3Q19 path (z-marching kernels) against the FP64 oracle, through the C-ABI.
+Same tolerances as the 2D tests (see test_gpu_parity.py)."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import Oracle
+from tests._helpers import gpu_fields, rel_l2, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def params3(nx=24, ny=16, nz=20, **kw):
+    return S.model_params("c3_256cube_xi0.1", nx=nx, ny=ny, nz=nz, **kw)
+
+
+def test_force_and_velocity_at_start_3d(gpu):
+    for ff in (0, 1):
+        p = params3(force_form=ff)
+        phi0 = S.phi0((20, 16, 24), seed=3)
+        o, g = run_pair(gpu, p, phi0, 0)
+        fo, fg = o.fields(), gpu_fields(g)
+        scale = np.abs(fo["u"]).max()
+        assert scale > 1e-6
+        assert np.abs(fg["u"] - fo["u"]).max() < 2e-5 * scale, ff
+        assert np.abs(fg["n"] - fo["n"]).max() < 1e-6
+
+
+@pytest.mark.parametrize("shape,walls", [((20, 16, 24), 1), ((37, 12, 40), 1), ((16, 24, 8), 0)])
+def test_parity_3d(gpu, shape, walls):
+    """Several z chunks and ragged x/y tiles; walls on and fully periodic."""
+    nz, ny, nx = shape
+    p = params3(nx=nx, ny=ny, nz=nz, walls=walls, Tw=0.9, T0=1.5 if walls else 0.95)
+    phi0 = S.phi0(shape, seed=7)
+    o, g = run_pair(gpu, p, phi0, 40)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+    assert rel_l2(fg["u"], fo["u"]) <= 1e-4
+    assert np.abs(fg["T"] - fo["T"]).max() < 1e-5
+
+
+def test_parity_3d_without_hydrodynamics(gpu):
+    """The paper's 3D runs solve phi and T only (Section 3, Fig. 3)."""
+    p = S.model_params("paper_3d_nohydro", nx=16, ny=16, nz=48)
+    phi0 = S.phi0((48, 16, 16), seed=2, amplitude=0.01)
+    o, g = run_pair(gpu, p, phi0, 200)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+    assert np.abs(fg["u"]).max() == 0.0
+
+
+def test_observables_and_conservation_3d(gpu):
+    p = params3()
+    phi0 = S.phi0((20, 16, 24), seed=4)
+    o, g = run_pair(gpu, p, phi0, 0)
+    a0 = g.observables()
+    o.step(60)
+    g.step(60)
+    a, b = o.observables(), g.observables()
+    N = phi0.size
+    assert abs(a["mass_dev"] - b["mass_dev"]) / N < 1e-6
+    assert abs(a["phi_sum"] - b["phi_sum"]) / N < 1e-6
+    assert abs(b["phi_sum"] - a0["phi_sum"]) / N < 1e-6
+    assert np.abs(np.array(a["mom"]) - np.array(b["mom"])).max() / N < 1e-7
+    assert b["max_u"] == pytest.approx(a["max_u"], rel=1e-4)
+    assert b["free_energy"] == pytest.approx(a["free_energy"], rel=1e-5)
+
+
+def test_checkpoint_and_roll_3d(gpu):
+    import torch
+    p = params3()
+    phi0 = S.phi0((20, 16, 24), seed=5)
+    t = lambda a: torch.tensor(a, dtype=torch.float32)  # noqa: E731
+    ref = gpu.Sim(p).init_fields(t(phi0)).step(21)
+    a = gpu.Sim(p).init_fields(t(phi0)).step(10)
+    b = gpu.Sim(p).set_state(a.get_state()).step(11)
+    assert np.array_equal(gpu_fields(ref)["phi"], gpu_fields(b)["phi"])
+    c = gpu.Sim(p).init_fields(t(np.roll(phi0, (3, 5), axis=(1, 2)))).step(21)
+    assert np.array_equal(np.roll(gpu_fields(ref)["phi"], (3, 5), axis=(1, 2)), gpu_fields(c)["phi"])
+
+
+def test_full_size_3d_one_step(gpu):
+    """The 256^3 workload in the launch configuration of the benchmark line, one step, every
+    site compared with the oracle."""
+    p = S.model_params("c3_256cube_xi0.1")
+    phi0 = S.initial_phi("c3_256cube_xi0.1")
+    o, g = run_pair(gpu, p, phi0, 1)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-6
+    assert rel_l2(fg["u"], fo["u"]) <= 1e-4
+    assert np.abs(fg["n"] - fo["n"]).max() < 1e-6

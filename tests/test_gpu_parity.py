@@ -282,3 +282,12 @@ def test_full_size_conservation_long(gpu):
     N = phi0.size
     assert abs(b["mass_dev"] - a["mass_dev"]) / N < 1e-6
     assert abs(b["phi_sum"] - a["phi_sum"]) / N < 1e-6
+
+
+def test_full_size_4096_one_step(gpu):
+    """The 4096^2 lattice (working set above the last-level cache), one step, site by site."""
+    p, phi0 = workload("m1_4096sq")
+    o, g = run_pair(gpu, p, phi0, 1)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-6
+    assert rel_l2(fg["u"], fo["u"]) <= 1e-4
