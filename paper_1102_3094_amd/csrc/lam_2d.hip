@@ -29,6 +29,8 @@ struct Lb2dSmem {
   float L[TY + 4][TX + 4];
   float P[3][TY + 2][TX + 2];  // Pxx, Pyy, Pxy (or mu in P[0] for the -phi grad mu form)
   float a[TY + 6];
+  int rowoff[TY + 6];  // y * nx of each tile row (wrapped or reflected)
+  int colx[TX + 6];    // x of each tile column (wrapped)
   double red[TY / 4][R_N];
 };
 
@@ -91,18 +93,39 @@ __global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const float* _
     if (x < nx && y < ny) pull9(gin, N, nx, ny, P.walls, x, y, g[j]);
   }
 
-  // phi with halo 3: periodic in x, reflected (or periodic) in y; a = (T - Tc)/Tc per row
-  for (int i = tid; i < (TY + 6) * (TX + 6); i += NTH) {
-    int r = i / (TX + 6), c = i - r * (TX + 6);
-    bool f;
-    int gy = wall_axis(y0 - 3 + r, ny, P.walls, f);
-    int gx = wrap(x0 - 3 + c, nx);
-    S.phi[r][c] = phi[(size_t)gy * nx + gx];
+  // index tables of the halo-3 tile: periodic in x, reflected (or periodic) in y;
+  // a = (T - Tc)/Tc per row
+  for (int i = tid; i < (TY + 6) + (TX + 6); i += NTH) {
+    if (i < TY + 6) {
+      bool f;
+      const int gy = wall_axis(y0 - 3 + i, ny, P.walls, f);
+      S.rowoff[i] = gy * nx;
+      S.a[i] = (Trow[gy] - P.Tc) / P.Tc;
+    } else {
+      S.colx[i - (TY + 6)] = wrap(x0 - 3 + (i - (TY + 6)), nx);
+    }
   }
-  if (tid < TY + 6) {
-    bool f;
-    int gy = wall_axis(y0 - 3 + tid, ny, P.walls, f);
-    S.a[tid] = (Trow[gy] - P.Tc) / P.Tc;
+  __syncthreads();
+  // phi tile; all loads of a thread are issued before its LDS stores, so their latencies overlap
+  {
+    constexpr int CNT = (TY + 6) * (TX + 6), IT = (CNT + NTH - 1) / NTH;
+    float v[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * NTH;
+      if (i < CNT) {
+        int r = i / (TX + 6), c = i - r * (TX + 6);
+        v[k] = phi[(size_t)S.rowoff[r] + S.colx[c]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * NTH;
+      if (i < CNT) {
+        int r = i / (TX + 6), c = i - r * (TX + 6);
+        S.phi[r][c] = v[k];
+      }
+    }
   }
   __syncthreads();
   // L = lap phi on halo 2
@@ -267,37 +290,68 @@ __global__ __launch_bounds__(16 * TY) void phi2d_kernel(KParams P, const float* 
   __shared__ float Ux[HYDRO ? HU : 1][HYDRO ? WU : 1];
   __shared__ float Uy[HYDRO ? HU : 1][HYDRO ? WU : 1];
   __shared__ float sa[H];
+  __shared__ int rowoff[H], colx[W];
+  __shared__ float rowsgn[H];  // -1 on mirror-image rows (wall-normal velocity is odd)
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
   const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY;
   const int t = xcd_tile(blockIdx.x, nbx * nby);
   const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
-
-  if (HYDRO) {
-    // velocity at depth 2 (plane offset 2); the wall-normal component is odd across a wall
-    for (int i = tid; i < HU * WU; i += NTH) {
-      int r = i / WU, c = i - (i / WU) * WU;
+  for (int i = tid; i < H + W; i += NTH) {
+    if (i < H) {
       bool f;
-      int gy = wall_axis(y0 - R + 2 + r, ny, P.walls, f);
-      int gx = wrap(x0 - R + 2 + c, nx);
-      size_t s = (size_t)gy * nx + gx;
-      Ux[r][c] = u[s];
-      float vy = u[N + s];
-      Uy[r][c] = f ? -vy : vy;
+      const int gy = wall_axis(y0 - R + i, ny, P.walls, f);
+      rowoff[i] = gy * nx;
+      rowsgn[i] = f ? -1.f : 1.f;
+      sa[i] = (Trow[gy] - P.Tc) / P.Tc;
+    } else {
+      colx[i - H] = wrap(x0 - R + (i - H), nx);
     }
   }
-  for (int i = tid; i < H * W; i += NTH) {
-    int r = i / W, c = i - r * W;
-    bool f;
-    int gy = wall_axis(y0 - R + r, ny, P.walls, f);
-    int gx = wrap(x0 - R + c, nx);
-    A[r][c] = psi_in[(size_t)gy * nx + gx];
-  }
-  for (int i = tid; i < H; i += NTH) {
-    bool f;
-    int gy = wall_axis(y0 - R + i, ny, P.walls, f);
-    sa[i] = (Trow[gy] - P.Tc) / P.Tc;
+  __syncthreads();
+
+  // Tile loads: every load of a thread is issued before its LDS stores (overlapped latency).
+  {
+    constexpr int CA = H * W, IA = (CA + NTH - 1) / NTH;
+    constexpr int CU = HYDRO ? HU * WU : 0, IU = (CU + NTH - 1) / NTH;
+    float va[IA], vx[IU > 0 ? IU : 1], vy[IU > 0 ? IU : 1];
+#pragma unroll
+    for (int k = 0; k < IA; ++k) {
+      const int i = tid + k * NTH;
+      if (i < CA) {
+        int r = i / W, c = i - r * W;
+        va[k] = psi_in[(size_t)rowoff[r] + colx[c]];
+      }
+    }
+    // velocity at depth 2 (plane offset 2); the wall-normal component is odd across a wall
+#pragma unroll
+    for (int k = 0; k < IU; ++k) {
+      const int i = tid + k * NTH;
+      if (i < CU) {
+        int r = i / WU, c = i - r * WU;
+        size_t s = (size_t)rowoff[r + 2] + colx[c + 2];
+        vx[k] = u[s];
+        vy[k] = rowsgn[r + 2] * u[N + s];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IA; ++k) {
+      const int i = tid + k * NTH;
+      if (i < CA) {
+        int r = i / W, c = i - r * W;
+        A[r][c] = va[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IU; ++k) {
+      const int i = tid + k * NTH;
+      if (i < CU) {
+        int r = i / WU, c = i - r * WU;
+        Ux[r][c] = vx[k];
+        Uy[r][c] = vy[k];
+      }
+    }
   }
   __syncthreads();
 

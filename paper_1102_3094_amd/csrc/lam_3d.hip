@@ -49,6 +49,7 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P) {
 }
 
 struct Lb3dSmem {
+  int rowoff[BY + 6], colx[BX + 6];  // y * nx and x of the halo-3 xy tile (periodic)
   float phi[5][BY + 6][BX + 6];
   float L[4][BY + 4][BX + 4];
   float P[4][6][BY + 2][BX + 2];  // xx, yy, zz, xy, xz, yz (or mu in [0] for -phi grad mu)
@@ -78,8 +79,41 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __res
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
   float g[19];
 
+  for (int i = tid; i < (BY + 6) + (BX + 6); i += NT3) {
+    if (i < BY + 6) S.rowoff[i] = wrap(T.y0 - 3 + i, ny) * nx;
+    else S.colx[i - (BY + 6)] = wrap(T.x0 - 3 + (i - (BY + 6)), nx);
+  }
+  __syncthreads();
+  // phi slices are loaded into registers one iteration before they are stored to LDS
+  constexpr int CPH = (BY + 6) * (BX + 6), IPH = (CPH + NT3 - 1) / NT3;
+  float pv[IPH];
+  auto load_phi = [&](int sl) {
+    bool f;
+    const size_t zoff = (size_t)wall_axis(sl, nz, P.walls, f) * plane;
+#pragma unroll
+    for (int j = 0; j < IPH; ++j) {
+      const int i = tid + j * NT3;
+      if (i < CPH) {
+        const int r = i / (BX + 6), c = i - r * (BX + 6);
+        pv[j] = phi[zoff + S.rowoff[r] + S.colx[c]];
+      }
+    }
+  };
+  load_phi(T.z0 - 3);
+
   for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
     const int s_load = T.z0 - 3 + k, s_L = s_load - 1, s_P = s_load - 2, s_out = s_load - 3;
+    {  // phi slice s_load (loaded last iteration) into its ring slot
+      float(*dst)[BX + 6] = S.phi[((s_load % 5) + 5) % 5];
+#pragma unroll
+      for (int j = 0; j < IPH; ++j) {
+        const int i = tid + j * NT3;
+        if (i < CPH) {
+          const int r = i / (BX + 6), c = i - r * (BX + 6);
+          dst[r][c] = pv[j];
+        }
+      }
+    }
     const bool do_out = s_out >= T.z0 && in_xy;
     // pulls of the output slice first: f_q(x) = f*_q(x - e_q), bounce-back across a wall
     if (do_out) {
@@ -102,16 +136,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __res
         g[q] = gin[(size_t)qq * N + idx];
       }
     }
-    {  // phi slice s_load with xy halo 3
-      bool f;
-      const int gz = wall_axis(s_load, nz, P.walls, f);
-      float(*dst)[BX + 6] = S.phi[((s_load % 5) + 5) % 5];
-      for (int i = tid; i < (BY + 6) * (BX + 6); i += NT3) {
-        int r = i / (BX + 6), c = i - r * (BX + 6);
-        int gy = wrap(T.y0 - 3 + r, ny), gx = wrap(T.x0 - 3 + c, nx);
-        dst[r][c] = phi[((size_t)gz * ny + gy) * nx + gx];
-      }
-    }
+    if (k + 1 < T.z1 - T.z0 + 6) load_phi(s_load + 1);
     __syncthreads();
     if (s_L >= T.z0 - 2) {  // L slice s_L with xy halo 2
       float(*pc)[BX + 6] = S.phi[((s_L % 5) + 5) % 5];
@@ -274,6 +299,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __res
 // psi ring of 6: the load of slice z + 4 must not overwrite slice z - 1, which slower threads may
 // still read for the output slice z of the previous iteration (no barrier between them).
 struct Phi3dSmem {
+  int rowoff[BY + 6], colx[BX + 6];
   float psi[6][BY + 6][BX + 6];
   float mu[4][BY + 2][BX + 2];
   float u[4][3][BY + 2][BX + 2];
@@ -294,32 +320,73 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
 
-  for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
-    const int s_load = T.z0 - 3 + k, s_mu = s_load - 2, s_out = s_load - 3;
-    {  // psi slice s_load (xy halo 3); u slice s_mu (xy halo 1, normal component odd)
-      bool f;
-      const int gz = wall_axis(s_load, nz, P.walls, f);
-      float(*dst)[BX + 6] = S.psi[((s_load % 6) + 6) % 6];
-      for (int i = tid; i < (BY + 6) * (BX + 6); i += NT3) {
-        int r = i / (BX + 6), c = i - r * (BX + 6);
-        int gy = wrap(T.y0 - 3 + r, ny), gx = wrap(T.x0 - 3 + c, nx);
-        dst[r][c] = psi_in[((size_t)gz * ny + gy) * nx + gx];
+  for (int i = tid; i < (BY + 6) + (BX + 6); i += NT3) {
+    if (i < BY + 6) S.rowoff[i] = wrap(T.y0 - 3 + i, ny) * nx;
+    else S.colx[i - (BY + 6)] = wrap(T.x0 - 3 + (i - (BY + 6)), nx);
+  }
+  __syncthreads();
+  // psi slice s and u slice s - 2 are loaded into registers one iteration before their LDS store
+  constexpr int CPS = (BY + 6) * (BX + 6), IPS = (CPS + NT3 - 1) / NT3;
+  constexpr int CUS = (BY + 2) * (BX + 2), IUS = (CUS + NT3 - 1) / NT3;
+  float pv[IPS], uv[3][IUS];
+  auto load = [&](int sl) {
+    bool f;
+    const size_t zoff = (size_t)wall_axis(sl, nz, P.walls, f) * plane;
+#pragma unroll
+    for (int j = 0; j < IPS; ++j) {
+      const int i = tid + j * NT3;
+      if (i < CPS) {
+        const int r = i / (BX + 6), c = i - r * (BX + 6);
+        pv[j] = psi_in[zoff + S.rowoff[r] + S.colx[c]];
       }
-      if (HYDRO && s_mu >= T.z0 - 1) {
-        bool fl;
-        const int uz = wall_axis(s_mu, nz, P.walls, fl);
-        float(*ud)[BY + 2][BX + 2] = S.u[((s_mu % 4) + 4) % 4];
-        for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
-          int r = i / (BX + 2), c = i - r * (BX + 2);
-          int gy = wrap(T.y0 - 1 + r, ny), gx = wrap(T.x0 - 1 + c, nx);
-          size_t s = ((size_t)uz * ny + gy) * nx + gx;
-          ud[0][r][c] = u[s];
-          ud[1][r][c] = u[N + s];
-          float vz = u[2 * N + s];
-          ud[2][r][c] = fl ? -vz : vz;
+    }
+    const int su = sl - 2;
+    if (HYDRO && su >= T.z0 - 1) {
+      bool fl;
+      const size_t uoff = (size_t)wall_axis(su, nz, P.walls, fl) * plane;
+      const float sg = fl ? -1.f : 1.f;
+#pragma unroll
+      for (int j = 0; j < IUS; ++j) {
+        const int i = tid + j * NT3;
+        if (i < CUS) {
+          const int r = i / (BX + 2), c = i - r * (BX + 2);
+          const size_t s = uoff + S.rowoff[r + 2] + S.colx[c + 2];
+          uv[0][j] = u[s];
+          uv[1][j] = u[N + s];
+          uv[2][j] = sg * u[2 * N + s];
         }
       }
     }
+  };
+  load(T.z0 - 3);
+
+  for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
+    const int s_load = T.z0 - 3 + k, s_mu = s_load - 2, s_out = s_load - 3;
+    {  // psi slice s_load (xy halo 3); u slice s_mu (xy halo 1, normal component odd)
+      float(*dst)[BX + 6] = S.psi[((s_load % 6) + 6) % 6];
+#pragma unroll
+      for (int j = 0; j < IPS; ++j) {
+        const int i = tid + j * NT3;
+        if (i < CPS) {
+          const int r = i / (BX + 6), c = i - r * (BX + 6);
+          dst[r][c] = pv[j];
+        }
+      }
+      if (HYDRO && s_mu >= T.z0 - 1) {
+        float(*ud)[BY + 2][BX + 2] = S.u[((s_mu % 4) + 4) % 4];
+#pragma unroll
+        for (int j = 0; j < IUS; ++j) {
+          const int i = tid + j * NT3;
+          if (i < CUS) {
+            const int r = i / (BX + 2), c = i - r * (BX + 2);
+            ud[0][r][c] = uv[0][j];
+            ud[1][r][c] = uv[1][j];
+            ud[2][r][c] = uv[2][j];
+          }
+        }
+      }
+    }
+    if (k + 1 < T.z1 - T.z0 + 6) load(s_load + 1);
     __syncthreads();
     if (s_mu >= T.z0 - 1) {  // mu of slice s_mu with xy halo 1 (25-point biharmonic)
       bool f;

@@ -44,7 +44,7 @@ def test_one_step_all_fields(gpu):
     assert np.abs(fg["T"] - fo["T"]).max() < 1e-6
 
 
-@pytest.mark.parametrize("steps", [1000])
+@pytest.mark.parametrize("steps", [1000, 2000])
 def test_parity_1000_steps_lamellar(gpu, steps):
     """The spec bar on the 64x64 wall geometry with the milder wall temperature (0.9 Tc)
     that keeps the coupled run bounded: rel-L2(phi) <= 1e-5 after 1000 steps; mass and sum(phi)
@@ -56,7 +56,10 @@ def test_parity_1000_steps_lamellar(gpu, steps):
     g.step(steps)
     fo, fg = o.fields(), gpu_fields(g)
     assert np.abs(fo["phi"]).max() > 0.5  # lamellae have formed near the walls
-    assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+    # 1e-5 at 1000 steps; FP32 rounding accumulates about linearly (measured ~1e-8 per step), so
+    # longer horizons get 1e-5 per 1000 steps plus a 50% margin
+    tol = 1e-5 if steps <= 1000 else 1.5e-5 * steps / 1000
+    assert rel_l2(fg["phi"], fo["phi"]) <= tol
     assert rel_l2(fg["u"], fo["u"]) <= 1e-4
     ob = g.observables()
     N = phi0.size
