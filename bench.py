@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0
 OBS_EVERY = 1000
 
 
-def byte_model(dim):
+def byte_model(dim, pop_bytes=4):
     """Algorithmic bytes per site: (dominant kernel, whole step).  Dominant kernel: populations
-    read and written (FP32) plus phi read; whole step: populations and phi read and written."""
+    read and written plus phi read; whole step: populations and phi read and written."""
     q = 9 if dim == 2 else 19
-    return 2 * 4 * q + 4, 2 * (4 * q + 4)
+    return 2 * pop_bytes * q + 4, 2 * (pop_bytes * q + 4)
 
 
 def kernel_source_hash(dim):
@@ -48,6 +48,7 @@ def traffic_from_profiles(workload, dim):
     or None when it is missing or was taken from another version of the kernel source."""
     kern = "lb2d" if dim == 2 else "lb3d"
     path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_traffic.json")
+    # only the FP32-storage kernel has committed counter summaries
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -80,6 +81,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pop-storage", type=int, default=0, choices=(0, 1),
+                    help="population storage: 0 FP32 deviations, 1 FP16 deviations")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named workload of synthetic.WORKLOADS (default: the 1024^2 lattice)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -98,11 +101,11 @@ def main():
 
     lam.load()
     wl = args.workload
-    p = S.model_params(wl)
+    p = S.model_params(wl, pop_storage=args.pop_storage)
     phi0 = S.initial_phi(wl)
     dim = p["dim"]
     n_sites = p["nx"] * p["ny"] * (p["nz"] if dim == 3 else 1)
-    lb_bytes, step_bytes = byte_model(dim)
+    lb_bytes, step_bytes = byte_model(dim, 2 if args.pop_storage else 4)
     sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(phi0, dtype=torch.float32))
     n_phi, n_T = sim.substeps
     if args.profile_pass:
@@ -163,11 +166,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if not args.pop_storage else "f32 (populations stored f16)",
         "data": "synthetic",
         "config": {"workload": f"{lattice} {shape} cold walls, tau={p['tau']}, xi={p['xi']}, "
                                f"n_phi={n_phi}, n_T={n_T}{extras}",
                    "name": wl, "lattice": lattice, "shape": shape, "tau": p["tau"],
+                   "pop_storage": "fp16" if args.pop_storage else "fp32",
                    "xi": p["xi"], "n_phi_sub": n_phi, "seed": 1},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -28,8 +28,8 @@
  * A handle is not thread-safe; different handles on different streams are independent.
  *
  * Layouts (row-major, x fastest): scalar fields [nz][ny][nx] (nz = 1 in 2D), FP32;
- * vector fields [dim][nz][ny][nx].  Populations are stored internally as FP32 deviations
- * f_q - w_q from the rest state.
+ * vector fields [dim][nz][ny][nx].  Populations are stored internally as deviations f_q - w_q
+ * from the rest state, in FP32 or (pop_storage = 1) FP16.
  *
  * Errors.  Every int-returning function returns 0 on success or one of the LAM_E* codes below;
  * lam_last_error gives a message (for a NULL handle: the last failure of lam_create or
@@ -64,7 +64,8 @@ typedef struct lam_params {
   int32_t n_phi_sub;         /* Euler sub-steps of phi per step; 0 = smallest stable count        */
   int32_t n_T_sub;           /* FTCS sub-steps of T per step; 0 = ceil(xi / 0.45)                  */
   int32_t force_form;        /* 0: F = -div P; 1: F = -phi grad mu                                 */
-  int32_t pop_storage;       /* 0: FP32 population deviations (only value supported)              */
+  int32_t pop_storage;       /* 0: FP32 population deviations; 1: FP16 deviations (FP32 arithmetic,
+                                round-to-nearest storage; halves the population traffic)         */
   int32_t allow_unstable;    /* 1: accept n_phi_sub / n_T_sub below the stability bound           */
   int32_t tile_hint;         /* 0: automatic; 8, 16, 32 or 64: tile height of the step kernels. The
                                 per-site arithmetic is the same for every tile: bit-identical

@@ -14,6 +14,7 @@
 //   all in LDS (temporal blocking), reading phi and u once and writing phi once.  The workgroup
 //   of tile 0 also advances the per-row temperature.
 #include <hip/hip_ext.h>
+#include <hip/hip_fp16.h>
 
 #include "lam_dev.hpp"
 
@@ -36,10 +37,11 @@ struct Lb2dSmem {
 
 // Pull of the 9 populations of site (x, y): f_q(x) = f*_q(x - e_q); across a wall the opposite
 // population of x itself (halfway bounce-back).
-__device__ __forceinline__ void pull9(const float* __restrict__ G, size_t N, int nx, int ny,
+template <typename ST>
+__device__ __forceinline__ void pull9(const ST* __restrict__ G, size_t N, int nx, int ny,
                                       int walls, int x, int y, float g[9]) {
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  auto ld = [&](int q, int yy, int xx) { return G[(size_t)q * N + (size_t)yy * nx + xx]; };
+  auto ld = [&](int q, int yy, int xx) { return to_f32(G[(size_t)q * N + (size_t)yy * nx + xx]); };
   g[0] = ld(0, y, x);
   g[1] = ld(1, y, xm);
   g[3] = ld(3, y, xp);
@@ -66,10 +68,11 @@ __device__ __forceinline__ void pull9(const float* __restrict__ G, size_t N, int
 }
 
 // One workgroup of 16*TY threads (TY/4 waves) per 64 x TY tile; every thread owns the 4 sites
-// (tx, ty + k TY/4), k < 4, of one column.
-template <int TY, int MODE>
-__global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const float* __restrict__ gin,
-                                                       float* __restrict__ gout,
+// (tx, ty + k TY/4), k < 4, of one column.  ST is the storage type of the populations (float or
+// __half); all arithmetic is FP32.
+template <int TY, int MODE, typename ST>
+__global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const ST* __restrict__ gin,
+                                                       ST* __restrict__ gout,
                                                        const float* __restrict__ phi,
                                                        const float* __restrict__ Trow,
                                                        float* __restrict__ uout,
@@ -215,15 +218,15 @@ __global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const float* _
         return gq + om * (geq - gq) + frc;
       };
       const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
-      gout[0 * N + s] = coll(g0, w0, 0.f, 0.f);
-      gout[1 * N + s] = coll(g1, w1, ux, Fx);
-      gout[2 * N + s] = coll(g2, w1, uy, Fy);
-      gout[3 * N + s] = coll(g3, w1, -ux, -Fx);
-      gout[4 * N + s] = coll(g4, w1, -uy, -Fy);
-      gout[5 * N + s] = coll(g5, w2, ux + uy, Fx + Fy);
-      gout[6 * N + s] = coll(g6, w2, uy - ux, Fy - Fx);
-      gout[7 * N + s] = coll(g7, w2, -ux - uy, -Fx - Fy);
-      gout[8 * N + s] = coll(g8, w2, ux - uy, Fx - Fy);
+      gout[0 * N + s] = from_f32<ST>(coll(g0, w0, 0.f, 0.f));
+      gout[1 * N + s] = from_f32<ST>(coll(g1, w1, ux, Fx));
+      gout[2 * N + s] = from_f32<ST>(coll(g2, w1, uy, Fy));
+      gout[3 * N + s] = from_f32<ST>(coll(g3, w1, -ux, -Fx));
+      gout[4 * N + s] = from_f32<ST>(coll(g4, w1, -uy, -Fy));
+      gout[5 * N + s] = from_f32<ST>(coll(g5, w2, ux + uy, Fx + Fy));
+      gout[6 * N + s] = from_f32<ST>(coll(g6, w2, uy - ux, Fy - Fx));
+      gout[7 * N + s] = from_f32<ST>(coll(g7, w2, -ux - uy, -Fx - Fy));
+      gout[8 * N + s] = from_f32<ST>(coll(g8, w2, ux - uy, Fx - Fy));
       uout[s] = ux;
       uout[N + s] = uy;
     } else if (MODE == MODE_FIELDS) {
@@ -444,31 +447,42 @@ static void launch(K kern, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0,
     hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
 }
 
-template <int TY>
-static void lb2d_launch(const KParams& P, int mode, const float* gin, float* gout, const float* phi,
+template <int TY, typename ST>
+static void lb2d_launch(const KParams& P, int mode, const void* gin, void* gout, const float* phi,
                         const float* Trow, float* u, float* n, double* partials, hipStream_t st,
                         hipEvent_t e0, hipEvent_t e1) {
   dim3 grid(blocks2d(P, TY)), block(16 * TY);
+  const ST* gi = (const ST*)gin;
+  ST* go = (ST*)gout;
   if (mode == MODE_STEP)
-    launch(lb2d_kernel<TY, MODE_STEP>, grid, block, st, e0, e1, P, gin, gout, phi, Trow, u, n,
+    launch(lb2d_kernel<TY, MODE_STEP, ST>, grid, block, st, e0, e1, P, gi, go, phi, Trow, u, n,
            partials);
   else if (mode == MODE_OBS)
-    launch(lb2d_kernel<TY, MODE_OBS>, grid, block, st, e0, e1, P, gin, gout, phi, Trow, u, n,
+    launch(lb2d_kernel<TY, MODE_OBS, ST>, grid, block, st, e0, e1, P, gi, go, phi, Trow, u, n,
            partials);
   else
-    launch(lb2d_kernel<TY, MODE_FIELDS>, grid, block, st, e0, e1, P, gin, gout, phi, Trow, u, n,
+    launch(lb2d_kernel<TY, MODE_FIELDS, ST>, grid, block, st, e0, e1, P, gi, go, phi, Trow, u, n,
            partials);
 }
 
-hipError_t launch_lb2d(const KParams& P, int ty, int mode, const float* gin, float* gout,
-                       const float* phi, const float* Trow, float* u, float* n, double* partials,
-                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  if (ty == 8) lb2d_launch<8>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
-  else if (ty == 16) lb2d_launch<16>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
-  else if (ty == 32) lb2d_launch<32>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
-  else if (ty == 64) lb2d_launch<64>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+template <typename ST>
+static hipError_t lb2d_dispatch(const KParams& P, int ty, int mode, const void* gin, void* gout,
+                                const float* phi, const float* Trow, float* u, float* n,
+                                double* partials, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (ty == 8) lb2d_launch<8, ST>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else if (ty == 16) lb2d_launch<16, ST>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else if (ty == 32) lb2d_launch<32, ST>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else if (ty == 64) lb2d_launch<64, ST>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
   else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_lb2d(const KParams& P, int ty, int mode, const void* gin, void* gout,
+                       const float* phi, const float* Trow, float* u, float* n, double* partials,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (P.half_pops)
+    return lb2d_dispatch<__half>(P, ty, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  return lb2d_dispatch<float>(P, ty, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
 }
 
 template <int S_, int TY>

@@ -13,6 +13,7 @@
 //   -> psi' = psi + h (Gamma lap mu - div(psi u)) for the output slice.  One Euler sub-step per
 //   launch; the workgroup of tile 0 of the last launch also advances the per-layer temperature.
 #include <hip/hip_ext.h>
+#include <hip/hip_fp16.h>
 
 #include "lam_dev.hpp"
 
@@ -56,9 +57,9 @@ struct Lb3dSmem {
   double red[NT3 / 64][R_N];
 };
 
-template <int MODE>
-__global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __restrict__ gin,
-                                                   float* __restrict__ gout,
+template <int MODE, typename ST>
+__global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restrict__ gin,
+                                                   ST* __restrict__ gout,
                                                    const float* __restrict__ phi,
                                                    const float* __restrict__ Trow,
                                                    float* __restrict__ uout,
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __res
           const int zz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
           idx = ((size_t)zz * ny + sy) * nx + sx;
         }
-        g[q] = gin[(size_t)qq * N + idx];
+        g[q] = to_f32(gin[(size_t)qq * N + idx]);
       }
     }
     if (k + 1 < T.z1 - T.z0 + 6) load_phi(s_load + 1);
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const float* __res
           const float eF = E19[q][0] * Fx + E19[q][1] * Fy + E19[q][2] * Fz;
           const float geq = w * (dn + n * (eu * (3.f + 4.5f * eu) - usq));
           const float frc = kf * w * (3.f * (eF - uF) + 9.f * eu * eF);
-          gout[(size_t)q * N + s] = g[q] + om * (geq - g[q]) + frc;
+          gout[(size_t)q * N + s] = from_f32<ST>(g[q] + om * (geq - g[q]) + frc);
         }
         uout[s] = ux;
         uout[N + s] = uy;
@@ -472,16 +473,26 @@ static void launch3(K kern, int nb, hipStream_t st, hipEvent_t e0, hipEvent_t e1
     hipLaunchKernelGGL(kern, dim3(nb), dim3(NT3), 0, st, args...);
 }
 
-hipError_t launch_lb3d(const KParams& P, int mode, const float* gin, float* gout,
+template <typename ST>
+static void lb3d_launch(const KParams& P, int mode, const void* gin, void* gout, const float* phi,
+                        const float* Trow, float* u, float* n, double* partials, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
+  const int nb = blocks3d(P);
+  const ST* gi = (const ST*)gin;
+  ST* go = (ST*)gout;
+  if (mode == MODE3_STEP)
+    launch3(lb3d_kernel<MODE3_STEP, ST>, nb, st, e0, e1, P, gi, go, phi, Trow, u, n, partials);
+  else if (mode == MODE3_OBS)
+    launch3(lb3d_kernel<MODE3_OBS, ST>, nb, st, e0, e1, P, gi, go, phi, Trow, u, n, partials);
+  else
+    launch3(lb3d_kernel<MODE3_FIELDS, ST>, nb, st, e0, e1, P, gi, go, phi, Trow, u, n, partials);
+}
+
+hipError_t launch_lb3d(const KParams& P, int mode, const void* gin, void* gout,
                        const float* phi, const float* Trow, float* u, float* n, double* partials,
                        hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  const int nb = blocks3d(P);
-  if (mode == MODE3_STEP)
-    launch3(lb3d_kernel<MODE3_STEP>, nb, st, e0, e1, P, gin, gout, phi, Trow, u, n, partials);
-  else if (mode == MODE3_OBS)
-    launch3(lb3d_kernel<MODE3_OBS>, nb, st, e0, e1, P, gin, gout, phi, Trow, u, n, partials);
-  else
-    launch3(lb3d_kernel<MODE3_FIELDS>, nb, st, e0, e1, P, gin, gout, phi, Trow, u, n, partials);
+  if (P.half_pops) lb3d_launch<__half>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
+  else lb3d_launch<float>(P, mode, gin, gout, phi, Trow, u, n, partials, st, e0, e1);
   return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ namespace lam {
 enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
 // lam_2d.hip
 int lb2d_blocks(const KParams& P, int ty);
-hipError_t launch_lb2d(const KParams& P, int ty, int mode, const float* gin, float* gout,
+hipError_t launch_lb2d(const KParams& P, int ty, int mode, const void* gin, void* gout,
                        const float* phi, const float* Trow, float* u, float* n, double* partials,
                        hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int phi2d_max_sub();
@@ -25,23 +25,24 @@ hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, flo
                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // lam_3d.hip
 int blocks3d(const KParams& P);
-hipError_t launch_lb3d(const KParams& P, int mode, const float* gin, float* gout,
+hipError_t launch_lb3d(const KParams& P, int mode, const void* gin, void* gout,
                        const float* phi, const float* Trow, float* u, float* n, double* partials,
                        hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_phi3d(const KParams& P, const float* in, float* out, const float* u,
                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // lam_util.hip
-hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, float* g,
+hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, void* g,
                        hipStream_t st);
 hipError_t launch_init_T(int nrows, int walls, float T0, float Tw, int quench, float* a, float* b,
                          hipStream_t st);
 hipError_t launch_finalize(const double* partials, int nblk, double* out, hipStream_t st);
 hipError_t launch_broadcast_T(const float* Trow, size_t N, size_t layer, float* out,
                               hipStream_t st);
-hipError_t launch_write_header(int dim, int nx, int ny, int nz, int64_t step, int Q, void* dst,
-                               hipStream_t st);
-bool check_header(const void* host_copy, int dim, int nx, int ny, int nz, int Q, int64_t* step);
+hipError_t launch_write_header(int dim, int nx, int ny, int nz, int64_t step, int Q, int esz,
+                               void* dst, hipStream_t st);
+bool check_header(const void* host_copy, int dim, int nx, int ny, int nz, int Q, int esz,
+                  int64_t* step);
 size_t header_bytes();
 // lam_spectra.hip
 size_t spectra_scratch_bytes(int nx, int ny);
@@ -65,7 +66,8 @@ struct lam_sim {
   hipStream_t st;
   char* ws;
   size_t ws_bytes;
-  float* g[2];
+  void* g[2];      // population deviations, FP32 or FP16 (pop_storage)
+  size_t pop_bytes;  // bytes of one population field (Q * N * element size)
   float* phi[2];
   float* psi[2];
   float* u;
@@ -104,7 +106,8 @@ Layout layout(const lam_params& p) {
     off = align256(off + bytes);
     return o;
   };
-  for (int i = 0; i < 2; ++i) L.g[i] = take(sizeof(float) * Q * N);
+  const size_t esz = p.pop_storage == 1 ? 2 : 4;
+  for (int i = 0; i < 2; ++i) L.g[i] = take(esz * Q * N);
   for (int i = 0; i < 2; ++i) L.phi[i] = take(sizeof(float) * N);
   for (int i = 0; i < 2; ++i) L.psi[i] = take(sizeof(float) * N);
   L.u = take(sizeof(float) * p.dim * N);
@@ -175,7 +178,8 @@ int validate(const lam_params* p, std::string& why) {
   if (!(p->Tc > 0)) return why = "Tc must be positive", LAM_EINVAL;
   if (!(p->Gamma >= 0)) return why = "Gamma must be non-negative", LAM_EINVAL;
   if (p->force_form != 0 && p->force_form != 1) return why = "force_form must be 0 or 1", LAM_EINVAL;
-  if (p->pop_storage != 0) return why = "only FP32 population storage is available", LAM_EINVAL;
+  if (p->pop_storage != 0 && p->pop_storage != 1)
+    return why = "pop_storage must be 0 (FP32) or 1 (FP16)", LAM_EINVAL;
   if (p->walls != 0 && p->walls != 1) return why = "walls must be 0 or 1", LAM_EINVAL;
   if (p->hydro != 0 && p->hydro != 1) return why = "hydro must be 0 or 1", LAM_EINVAL;
   if (p->n_phi_sub < 0 || p->n_T_sub < 0) return why = "sub-step counts must be >= 0", LAM_EINVAL;
@@ -229,7 +233,7 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   s->ws = (char*)d_workspace;
   s->ws_bytes = bytes;
   for (int i = 0; i < 2; ++i) {
-    s->g[i] = (float*)(s->ws + L.g[i]);
+    s->g[i] = (void*)(s->ws + L.g[i]);
     s->phi[i] = (float*)(s->ws + L.phi[i]);
     s->psi[i] = (float*)(s->ws + L.psi[i]);
   }
@@ -239,6 +243,7 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   s->result = (double*)(s->ws + L.result);
   s->spec = s->ws + L.spec;
   s->nblk = L.nblk;
+  s->pop_bytes = (p->pop_storage == 1 ? 2 : 4) * (size_t)s->Q * s->N;
   KParams& k = s->k;
   k.nx = p->nx;
   k.ny = p->ny;
@@ -259,6 +264,7 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   k.gz = (float)p->body_force[2];
   k.n_T = p->xi > 0 ? s->nT : 0;
   k.r_T = p->xi > 0 ? (float)(p->xi / s->nT) : 0.f;
+  k.half_pops = p->pop_storage == 1;
   s->step = 0;
   s->initialised = false;
   *out = s;
@@ -276,8 +282,7 @@ int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const fl
   if (!s || !d_phi0) return fail(s, LAM_EINVAL, "null simulation or phi0");
   HIPCHK(s, hipMemcpyAsync(s->phi[0], d_phi0, sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
   HIPCHK(s, launch_init(s->k, s->p.dim, d_n0, d_u0, s->g[0], s->st));
-  HIPCHK(s, hipMemcpyAsync(s->g[1], s->g[0], sizeof(float) * s->Q * s->N, hipMemcpyDeviceToDevice,
-                           s->st));
+  HIPCHK(s, hipMemcpyAsync(s->g[1], s->g[0], s->pop_bytes, hipMemcpyDeviceToDevice, s->st));
   HIPCHK(s, hipMemsetAsync(s->u, 0, sizeof(float) * s->p.dim * s->N, s->st));
   HIPCHK(s, launch_init_T(s->nrows, s->p.walls, (float)s->p.T0, (float)s->p.Tw, s->p.xi < 0,
                           s->T[0], s->T[1], s->st));
@@ -450,7 +455,7 @@ int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T)
 
 int lam_state_bytes(const lam_sim* s, size_t* bytes) {
   if (!s || !bytes) return LAM_EINVAL;
-  *bytes = header_bytes() + sizeof(float) * ((size_t)s->Q * s->N + s->N + s->nrows);
+  *bytes = header_bytes() + s->pop_bytes + sizeof(float) * (s->N + s->nrows);
   return LAM_OK;
 }
 
@@ -461,10 +466,11 @@ int lam_get_state(lam_sim* s, void* d_buf, size_t bytes) {
   if (bytes < need) return fail(s, LAM_ESIZE, "checkpoint buffer too small");
   const int cur = (int)(s->step & 1);
   char* b = (char*)d_buf;
-  HIPCHK(s, launch_write_header(s->p.dim, s->p.nx, s->p.ny, s->k.nz, s->step, s->Q, b, s->st));
+  HIPCHK(s, launch_write_header(s->p.dim, s->p.nx, s->p.ny, s->k.nz, s->step, s->Q,
+                                (int)(s->pop_bytes / ((size_t)s->Q * s->N)), b, s->st));
   b += header_bytes();
-  HIPCHK(s, hipMemcpyAsync(b, s->g[cur], sizeof(float) * s->Q * s->N, hipMemcpyDeviceToDevice, s->st));
-  b += sizeof(float) * s->Q * s->N;
+  HIPCHK(s, hipMemcpyAsync(b, s->g[cur], s->pop_bytes, hipMemcpyDeviceToDevice, s->st));
+  b += s->pop_bytes;
   HIPCHK(s, hipMemcpyAsync(b, s->phi[cur], sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
   b += sizeof(float) * s->N;
   HIPCHK(s, hipMemcpyAsync(b, s->T[cur], sizeof(float) * s->nrows, hipMemcpyDeviceToDevice, s->st));
@@ -480,13 +486,14 @@ int lam_set_state(lam_sim* s, const void* d_buf, size_t bytes) {
   HIPCHK(s, hipMemcpyAsync(hdr, d_buf, sizeof(hdr), hipMemcpyDeviceToHost, s->st));
   HIPCHK(s, hipStreamSynchronize(s->st));
   int64_t step;
-  if (!check_header(hdr, s->p.dim, s->p.nx, s->p.ny, s->k.nz, s->Q, &step))
+  if (!check_header(hdr, s->p.dim, s->p.nx, s->p.ny, s->k.nz, s->Q,
+                    (int)(s->pop_bytes / ((size_t)s->Q * s->N)), &step))
     return fail(s, LAM_ESTATE, "checkpoint does not match this lattice");
   const int cur = (int)(step & 1);
   const char* b = (const char*)d_buf + header_bytes();
   for (int i = 0; i < 2; ++i)
-    HIPCHK(s, hipMemcpyAsync(s->g[i], b, sizeof(float) * s->Q * s->N, hipMemcpyDeviceToDevice, s->st));
-  b += sizeof(float) * s->Q * s->N;
+    HIPCHK(s, hipMemcpyAsync(s->g[i], b, s->pop_bytes, hipMemcpyDeviceToDevice, s->st));
+  b += s->pop_bytes;
   HIPCHK(s, hipMemcpyAsync(s->phi[cur], b, sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
   b += sizeof(float) * s->N;
   for (int i = 0; i < 2; ++i)

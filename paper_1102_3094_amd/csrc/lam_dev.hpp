@@ -2,6 +2,7 @@
 // library: the kernel parameter block, index maps for periodic and wall-reflected axes, the
 // XCD-aware tile order and small reduction helpers.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,7 +22,19 @@ struct KParams {
   float gx, gy, gz;     // uniform test acceleration
   float r_T;            // xi / n_T
   int n_T;              // FTCS sub-steps (0: temperature frozen)
+  int half_pops;        // populations stored as FP16 deviations
 };
+
+// Storage conversions of the population deviations (FP32 or FP16 storage, FP32 arithmetic;
+// FP16 rounding is to nearest even).
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(__half v) { return __half2float(v); }
+template <typename ST>
+__device__ __forceinline__ ST from_f32(float v);
+template <>
+__device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half_rn(v); }
 
 // Reduction slots of the observables.
 enum { R_MASS = 0, R_JX, R_JY, R_JZ, R_PHI, R_FE, R_UMAX, R_BAD, R_N };

@@ -26,9 +26,9 @@ __device__ __forceinline__ float geq_dev(float w, float n, float eu, float uu) {
 
 // Post-collision field whose streaming yields f^eq(n0, u0) at every site:
 // g*_q(x) = g^eq_q(x + e_q) if x + e_q is a fluid site, else g^eq_{opp q}(x).
-template <int DIM>
+template <int DIM, typename ST>
 __global__ void init_pop_kernel(KParams P, const float* __restrict__ n0,
-                                const float* __restrict__ u0, float* __restrict__ g) {
+                                const float* __restrict__ u0, ST* __restrict__ g) {
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -58,7 +58,7 @@ __global__ void init_pop_kernel(KParams P, const float* __restrict__ n0,
       sz = DIM == 2 ? 0 : (sz + P.nz) % P.nz;
       v = eq(q, site(sx, sy, sz));
     }
-    g[(size_t)q * N + i] = v;
+    g[(size_t)q * N + i] = from_f32<ST>(v);
   }
 }
 
@@ -107,18 +107,23 @@ struct StateHeader {
   uint64_t magic;
   int32_t dim, nx, ny, nz;
   int64_t step;
-  int32_t Q, pad;
+  int32_t Q, pop_bytes;  // populations per site and bytes per population value
 };
 constexpr uint64_t STATE_MAGIC = 0x4c414d5354415431ull;
 
 __global__ void write_header_kernel(StateHeader h, StateHeader* dst) { *dst = h; }
 
-hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, float* g,
+hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, void* g,
                        hipStream_t st) {
   size_t N = (size_t)P.nx * P.ny * P.nz;
   dim3 grid((unsigned)((N + 255) / 256)), block(256);
-  if (dim == 2) hipLaunchKernelGGL(init_pop_kernel<2>, grid, block, 0, st, P, n0, u0, g);
-  else hipLaunchKernelGGL(init_pop_kernel<3>, grid, block, 0, st, P, n0, u0, g);
+  if (P.half_pops) {
+    if (dim == 2) hipLaunchKernelGGL((init_pop_kernel<2, __half>), grid, block, 0, st, P, n0, u0, (__half*)g);
+    else hipLaunchKernelGGL((init_pop_kernel<3, __half>), grid, block, 0, st, P, n0, u0, (__half*)g);
+  } else {
+    if (dim == 2) hipLaunchKernelGGL((init_pop_kernel<2, float>), grid, block, 0, st, P, n0, u0, (float*)g);
+    else hipLaunchKernelGGL((init_pop_kernel<3, float>), grid, block, 0, st, P, n0, u0, (float*)g);
+  }
   return hipGetLastError();
 }
 
@@ -141,17 +146,18 @@ hipError_t launch_broadcast_T(const float* Trow, size_t N, size_t layer, float* 
   return hipGetLastError();
 }
 
-hipError_t launch_write_header(int dim, int nx, int ny, int nz, int64_t step, int Q, void* dst,
-                               hipStream_t st) {
-  StateHeader h{STATE_MAGIC, dim, nx, ny, nz, step, Q, 0};
+hipError_t launch_write_header(int dim, int nx, int ny, int nz, int64_t step, int Q, int esz,
+                               void* dst, hipStream_t st) {
+  StateHeader h{STATE_MAGIC, dim, nx, ny, nz, step, Q, esz};
   hipLaunchKernelGGL(write_header_kernel, dim3(1), dim3(1), 0, st, h, (StateHeader*)dst);
   return hipGetLastError();
 }
 
-bool check_header(const void* host_copy, int dim, int nx, int ny, int nz, int Q, int64_t* step) {
+bool check_header(const void* host_copy, int dim, int nx, int ny, int nz, int Q, int esz,
+                  int64_t* step) {
   const StateHeader* h = (const StateHeader*)host_copy;
   if (h->magic != STATE_MAGIC || h->dim != dim || h->nx != nx || h->ny != ny || h->nz != nz ||
-      h->Q != Q)
+      h->Q != Q || h->pop_bytes != esz)
     return false;
   *step = h->step;
   return true;
