@@ -75,6 +75,36 @@ def cpu_baseline(params, phi0, budget_s=12.0):
             "sample": f"{steps} steps of the {shape} workload ({dt:.1f} s, FP64, OpenMP over sites)"}
 
 
+def bench_ensemble(args):
+    """64 independent lattices (sides 128-512, xi and tau swept) in one launch per kernel,
+    autotuned tile height, step pairs replayed from a HIP graph."""
+    import torch
+    import paper_1102_3094_amd as lam
+    import synthetic as S
+    members, phis = S.ensemble_members(seed=1, count=64, pop_storage=1)
+    ens = lam.Ensemble(members)
+    tile = ens.tune(10)
+    ens.init_fields(phis)
+    ens.step(args.warmup)
+    ens.synchronize()
+    t0 = time.perf_counter()
+    ens.step(args.steps)
+    ens.synchronize()
+    dt = time.perf_counter() - t0
+    sites = ens.sites
+    mlups = sites * args.steps / dt / 1e6
+    _, step_bytes = byte_model(2, 2)
+    out = {"metric": "MLUPS (ensemble, all members)", "value": round(mlups, 1), "unit": "MLUPS",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 (populations stored f16)", "data": "synthetic",
+           "config": {"workload": "64 D2Q9 lattices, sides log-uniform 128-512, xi log-uniform "
+                                  "1e-3..1, tau uniform 0.55..3.0, cold walls, seed 1",
+                      "sites": sites, "tile_height": tile},
+           "step_effective_roofline_frac": round(mlups * 1e6 * step_bytes / 8e12, 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +113,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pop-storage", type=int, default=0, choices=(0, 1),
                     help="population storage: 0 FP32 deviations, 1 FP16 deviations")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="the batched ensemble instead: 64 uneven 2D lattices, FP16 populations")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named workload of synthetic.WORKLOADS (default: the 1024^2 lattice)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -100,6 +132,8 @@ def main():
     import synthetic as S
 
     lam.load()
+    if args.ensemble:
+        return bench_ensemble(args)
     wl = args.workload
     p = S.model_params(wl, pop_storage=args.pop_storage)
     phi0 = S.initial_phi(wl)

@@ -151,6 +151,31 @@ int lam_kernel_times(lam_sim* s, double* h_ms, int64_t* h_launches, int32_t nk);
 const char* lam_last_error(const lam_sim* s);
 void lam_destroy(lam_sim* s);
 
+/* Ensembles: independent 2D simulations of different sizes and parameters (for example sweeps in
+ * xi and viscosity, Section 3) advanced together.  Every time step is one launch of the LB kernel
+ * and one launch of the phi kernel over the tiles of all members (workgroups map to
+ * (member, tile) through a tile table), so small lattices fill the GPU together; with a non-NULL
+ * stream, pairs of steps are captured once in a HIP graph and replayed.  Each member computes
+ * exactly what it computes alone (bit for bit, at the same tile height).
+ * Requirements: all members 2D with the same hydro flag, pop_storage and phi sub-step count.
+ * Memory: one caller workspace of lam_ensemble_workspace_bytes() bytes holds every member. */
+typedef struct lam_ensemble lam_ensemble;
+int lam_ensemble_workspace_bytes(const lam_params* members, int32_t count, size_t* bytes);
+int lam_ensemble_create(const lam_params* members, int32_t count, void* d_workspace, size_t bytes,
+                        void* hip_stream, lam_ensemble** out);
+/* The member simulation i (owned by the ensemble): lam_observables, lam_get_fields,
+ * lam_structure_factor, lam_orientation and checkpoints work on it; do not lam_step it alone. */
+int lam_ensemble_member(lam_ensemble* e, int32_t i, lam_sim** out);
+/* d_phi0: host array of count device pointers to each member's initial phi. */
+int lam_ensemble_init_fields(lam_ensemble* e, const float* const* d_phi0);
+int lam_ensemble_step(lam_ensemble* e, int64_t nsteps);
+/* Autotuner: times `steps` steps at each tile height (16, 32, 64), keeps the fastest and
+ * returns it.  It advances the members' state: call it before lam_ensemble_init_fields. */
+int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height);
+int lam_ensemble_sites(const lam_ensemble* e, int64_t* sites);
+const char* lam_ensemble_last_error(const lam_ensemble* e);
+void lam_ensemble_destroy(lam_ensemble* e);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,7 +40,10 @@ class lam_obs(C.Structure):
 EXPORTS = ("lam_workspace_bytes", "lam_create", "lam_substeps", "lam_init_fields", "lam_step",
            "lam_observables", "lam_structure_factor", "lam_orientation", "lam_get_fields",
            "lam_state_bytes", "lam_get_state", "lam_set_state", "lam_set_timing",
-           "lam_kernel_times", "lam_last_error", "lam_destroy")
+           "lam_kernel_times", "lam_last_error", "lam_destroy",
+           "lam_ensemble_workspace_bytes", "lam_ensemble_create", "lam_ensemble_member",
+           "lam_ensemble_init_fields", "lam_ensemble_step", "lam_ensemble_tune",
+           "lam_ensemble_sites", "lam_ensemble_last_error", "lam_ensemble_destroy")
 LAM_K_LB, LAM_K_PHI, LAM_NK = 0, 1, 2
 
 _lib = None
@@ -74,6 +77,17 @@ def load():
     L.lam_last_error.restype = C.c_char_p
     L.lam_destroy.argtypes = [vp]
     L.lam_destroy.restype = None
+    L.lam_ensemble_workspace_bytes.argtypes = [pp, C.c_int32, C.POINTER(C.c_size_t)]
+    L.lam_ensemble_create.argtypes = [pp, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lam_ensemble_member.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+    L.lam_ensemble_init_fields.argtypes = [vp, C.POINTER(vp)]
+    L.lam_ensemble_step.argtypes = [vp, C.c_int64]
+    L.lam_ensemble_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+    L.lam_ensemble_sites.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.lam_ensemble_last_error.argtypes = [vp]
+    L.lam_ensemble_last_error.restype = C.c_char_p
+    L.lam_ensemble_destroy.argtypes = [vp]
+    L.lam_ensemble_destroy.restype = None
     _lib = L
     return L
 
@@ -115,9 +129,25 @@ def workspace_bytes(params: dict) -> int:
 class Sim:
     """One simulation on one GPU.  Fields are torch tensors shaped (ny, nx) or (nz, ny, nx)."""
 
+    @classmethod
+    def _view(cls, handle, params: dict, device, stream):
+        """A member of an ensemble: the ensemble owns the handle and the memory."""
+        import torch
+        self = cls.__new__(cls)
+        self.params = dict(params)
+        self.device = torch.device(device)
+        self.dim = int(params["dim"])
+        self.shape = (params["ny"], params["nx"])
+        self.N = int(params["ny"]) * int(params["nx"])
+        self.stream = stream
+        self._h = handle
+        self._owned = False
+        return self
+
     def __init__(self, params: dict, device="cuda:0", stream=None):
         import torch
         L = load()
+        self._owned = True
         self.params = dict(params)
         self.device = torch.device(device)
         self.dim = int(params["dim"])
@@ -138,9 +168,9 @@ class Sim:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
+        if h is not None and _lib is not None and getattr(self, "_owned", True):
             _lib.lam_destroy(h)
-            self._h = None
+        self._h = None
 
     def _chk(self, rc):
         _check(rc, self._h)
@@ -232,6 +262,74 @@ class Sim:
         n = (C.c_int64 * LAM_NK)()
         self._chk(load().lam_kernel_times(self._h, ms, n, LAM_NK))
         return {"lb": (ms[LAM_K_LB], n[LAM_K_LB]), "phi": (ms[LAM_K_PHI], n[LAM_K_PHI])}
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def _check_ens(rc: int, handle=None):
+    if rc != LAM_OK:
+        raise LamError(rc, load().lam_ensemble_last_error(handle).decode(errors="replace"))
+
+
+class Ensemble:
+    """Independent 2D simulations advanced together (one launch per kernel for all members).
+    Runs on its own non-default stream so that step pairs are replayed from a HIP graph."""
+
+    def __init__(self, members, device="cuda:0", stream=None):
+        import torch
+        L = load()
+        self.members = [dict(m) for m in members]
+        self.device = torch.device(device)
+        arr = (lam_params * len(members))(*[make_params(m) for m in members])
+        self._arr = arr
+        n = C.c_size_t()
+        _check_ens(L.lam_ensemble_workspace_bytes(arr, len(members), C.byref(n)))
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.workspace = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check_ens(L.lam_ensemble_create(arr, len(members), C.c_void_p(self.workspace.data_ptr()),
+                                         n.value, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.sims = []
+        for i, m in enumerate(self.members):
+            sh = C.c_void_p()
+            _check_ens(L.lam_ensemble_member(h, i, C.byref(sh)), h)
+            self.sims.append(Sim._view(sh, m, self.device, self.stream))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            for s in getattr(self, "sims", []):
+                s._h = None
+            _lib.lam_ensemble_destroy(h)
+        self._h = None
+
+    @property
+    def sites(self) -> int:
+        n = C.c_int64()
+        _check_ens(load().lam_ensemble_sites(self._h, C.byref(n)), self._h)
+        return n.value
+
+    def init_fields(self, phi0s):
+        import torch
+        ts = [torch.as_tensor(p, dtype=torch.float32, device=self.device).contiguous()
+              for p in phi0s]
+        self._keep = ts
+        ptrs = (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+        torch.cuda.current_stream(self.device).synchronize()
+        _check_ens(load().lam_ensemble_init_fields(self._h, ptrs), self._h)
+        return self
+
+    def step(self, n: int = 1):
+        _check_ens(load().lam_ensemble_step(self._h, int(n)), self._h)
+        return self
+
+    def tune(self, steps: int = 20) -> int:
+        th = C.c_int32()
+        _check_ens(load().lam_ensemble_tune(self._h, int(steps), C.byref(th)), self._h)
+        return th.value
 
     def synchronize(self):
         self.stream.synchronize()

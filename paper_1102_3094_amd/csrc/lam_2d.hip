@@ -71,21 +71,16 @@ __device__ __forceinline__ void pull9(const ST* __restrict__ G, size_t N, int nx
 // (tx, ty + k TY/4), k < 4, of one column.  ST is the storage type of the populations (float or
 // __half); all arithmetic is FP32.
 template <int TY, int MODE, typename ST>
-__global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const ST* __restrict__ gin,
-                                                       ST* __restrict__ gout,
-                                                       const float* __restrict__ phi,
-                                                       const float* __restrict__ Trow,
-                                                       float* __restrict__ uout,
-                                                       float* __restrict__ nout,
-                                                       double* __restrict__ partials) {
+__device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict__ gin,
+                                          ST* __restrict__ gout, const float* __restrict__ phi,
+                                          const float* __restrict__ Trow,
+                                          float* __restrict__ uout, float* __restrict__ nout,
+                                          double* __restrict__ partials, const int x0,
+                                          const int y0, Lb2dSmem<TY>& S) {
   constexpr int NTH = 16 * TY, NW = TY / 4;
-  __shared__ Lb2dSmem<TY> S;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
-  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY;
-  const int t = xcd_tile(blockIdx.x, nbx * nby);
-  const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
   const int tx = tid & 63, ty = tid >> 6;
 
   // issue the population pulls first so that their latency overlaps the stencil phases
@@ -266,6 +261,36 @@ __global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const ST* __re
   }
 }
 
+template <int TY, int MODE, typename ST>
+__global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const ST* __restrict__ gin,
+                                                       ST* __restrict__ gout,
+                                                       const float* __restrict__ phi,
+                                                       const float* __restrict__ Trow,
+                                                       float* __restrict__ uout,
+                                                       float* __restrict__ nout,
+                                                       double* __restrict__ partials) {
+  __shared__ Lb2dSmem<TY> S;
+  const int nbx = (P.nx + TX - 1) / TX, nby = (P.ny + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, nbx * nby);
+  lb2d_tile<TY, MODE, ST>(P, gin, gout, phi, Trow, uout, nout, partials, (t % nbx) * TX,
+                          (t / nbx) * TY, S);
+}
+
+// Ensemble: workgroup b takes tile xcd_tile(b, ntiles) of the concatenated tile lists of all
+// members; the member's tiles are then processed exactly as in a single simulation.
+template <int TY, typename ST>
+__global__ __launch_bounds__(16 * TY) void lb2d_ens_kernel(const EnsMember* __restrict__ mem,
+                                                           const int* __restrict__ tile_member,
+                                                           int ntiles, int cur) {
+  __shared__ Lb2dSmem<TY> S;
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const EnsMember& M = mem[tile_member[t]];
+  const KParams P = M.P;
+  const int lt = t - M.tile0, nbx = (P.nx + TX - 1) / TX;
+  lb2d_tile<TY, MODE_STEP, ST>(P, (const ST*)M.g[cur], (ST*)M.g[cur ^ 1], M.phi[cur], M.T[cur],
+                               M.u, nullptr, nullptr, (lt % nbx) * TX, (lt / nbx) * TY, S);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Order-parameter sub-steps.  Cell (r, c) of every LDS plane is the site (y0 - R + r, x0 - R + c);
 // a plane is valid at depth d when rows d .. H-1-d and columns d .. W-1-d hold data.
@@ -277,30 +302,44 @@ struct Phi2dDims {
 };
 
 template <int S_, int TY, bool HYDRO>
-__global__ __launch_bounds__(16 * TY) void phi2d_kernel(KParams P, const float* __restrict__ psi_in,
-                                                        float* __restrict__ psi_out,
-                                                        const float* __restrict__ u,
-                                                        const float* __restrict__ Trow,
-                                                        float* __restrict__ Tnext,
-                                                        float* __restrict__ Tscr, int do_T) {
+struct Phi2dSmem {
+  using D = Phi2dDims<S_, TY>;
+  static constexpr int H = D::H, W = D::W, HU = H - 4, WU = W - 4;
+  float A[H][W];
+  float B[H][W];
+  float Cm[HU][WU];
+  float Ux[HYDRO ? HU : 1][HYDRO ? WU : 1];
+  float Uy[HYDRO ? HU : 1][HYDRO ? WU : 1];
+  float sa[H];
+  int rowoff[H], colx[W];
+  float rowsgn[H];  // -1 on mirror-image rows (wall-normal velocity is odd)
+};
+
+// t is the tile's index within its simulation (the workgroup of tile 0 advances T).
+template <int S_, int TY, bool HYDRO>
+__device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __restrict__ psi_in,
+                                           float* __restrict__ psi_out,
+                                           const float* __restrict__ u,
+                                           const float* __restrict__ Trow,
+                                           float* __restrict__ Tnext, float* __restrict__ Tscr,
+                                           const int do_T, const int t, const int x0,
+                                           const int y0, Phi2dSmem<S_, TY, HYDRO>& Sm) {
   using D = Phi2dDims<S_, TY>;
   constexpr int R = D::R, H = D::H, W = D::W;
   constexpr int NTH = 16 * TY;
   constexpr int HU = H - 4, WU = W - 4;  // planes used from depth 2 on (mu, velocity)
-  __shared__ float A[H][W];
-  __shared__ float B[H][W];
-  __shared__ float Cm[HU][WU];
-  __shared__ float Ux[HYDRO ? HU : 1][HYDRO ? WU : 1];
-  __shared__ float Uy[HYDRO ? HU : 1][HYDRO ? WU : 1];
-  __shared__ float sa[H];
-  __shared__ int rowoff[H], colx[W];
-  __shared__ float rowsgn[H];  // -1 on mirror-image rows (wall-normal velocity is odd)
+  auto& A = Sm.A;
+  auto& B = Sm.B;
+  auto& Cm = Sm.Cm;
+  auto& Ux = Sm.Ux;
+  auto& Uy = Sm.Uy;
+  auto& sa = Sm.sa;
+  auto& rowoff = Sm.rowoff;
+  auto& colx = Sm.colx;
+  auto& rowsgn = Sm.rowsgn;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
-  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY;
-  const int t = xcd_tile(blockIdx.x, nbx * nby);
-  const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
   for (int i = tid; i < H + W; i += NTH) {
     if (i < H) {
       bool f;
@@ -427,6 +466,38 @@ __global__ __launch_bounds__(16 * TY) void phi2d_kernel(KParams P, const float* 
   }
 }
 
+template <int S_, int TY, bool HYDRO>
+__global__ __launch_bounds__(16 * TY) void phi2d_kernel(KParams P, const float* __restrict__ psi_in,
+                                                        float* __restrict__ psi_out,
+                                                        const float* __restrict__ u,
+                                                        const float* __restrict__ Trow,
+                                                        float* __restrict__ Tnext,
+                                                        float* __restrict__ Tscr, int do_T) {
+  __shared__ Phi2dSmem<S_, TY, HYDRO> Sm;
+  const int nbx = (P.nx + TX - 1) / TX, nby = (P.ny + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, nbx * nby);
+  phi2d_tile<S_, TY, HYDRO>(P, psi_in, psi_out, u, Trow, Tnext, Tscr, do_T, t, (t % nbx) * TX,
+                            (t / nbx) * TY, Sm);
+}
+
+// Ensemble: one launch over the tiles of all members; pass > 0 selects the member's phi scratch
+// buffers for chained launches (more sub-steps than one launch fuses).
+template <int S_, int TY, bool HYDRO>
+__global__ __launch_bounds__(16 * TY) void phi2d_ens_kernel(const EnsMember* __restrict__ mem,
+                                                            const int* __restrict__ tile_member,
+                                                            int ntiles, int cur, int pass,
+                                                            int last) {
+  __shared__ Phi2dSmem<S_, TY, HYDRO> Sm;
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const EnsMember& M = mem[tile_member[t]];
+  const KParams P = M.P;
+  const int lt = t - M.tile0, nbx = (P.nx + TX - 1) / TX;
+  const float* in = pass == 0 ? M.phi[cur] : M.psi[(pass - 1) & 1];
+  float* out = last ? M.phi[cur ^ 1] : M.psi[pass & 1];
+  phi2d_tile<S_, TY, HYDRO>(P, in, out, M.u, M.T[cur], M.T[cur ^ 1], M.T[2],
+                            last && P.n_T > 0, lt, (lt % nbx) * TX, (lt / nbx) * TY, Sm);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Host launchers.  Tile heights 8, 16, 32 and 64 are compiled; the per-site arithmetic does not
 // depend on the tile, so every choice gives bit-identical fields.
@@ -516,6 +587,44 @@ hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, flo
     else PHI_CASE(2, 64);
   }
 #undef PHI_CASE
+  return hipGetLastError();
+}
+
+// Ensemble launchers: one LB launch and ceil(n_phi / 2) phi launches per step, all members.
+template <int TY>
+static void ens_step_ty(const EnsMember* mem, const int* tile_member, int ntiles, int cur,
+                        int half, int hydro, int nphi, hipStream_t st) {
+  dim3 grid(ntiles), block(16 * TY);
+  if (hydro) {
+    if (half) hipLaunchKernelGGL((lb2d_ens_kernel<TY, __half>), grid, block, 0, st, mem, tile_member, ntiles, cur);
+    else hipLaunchKernelGGL((lb2d_ens_kernel<TY, float>), grid, block, 0, st, mem, tile_member, ntiles, cur);
+  }
+  int remaining = nphi, pass = 0;
+  while (remaining > 0) {
+    const int sub = remaining >= 2 ? 2 : 1;
+    const int last = remaining == sub;
+#define ENS_PHI(S_, H_)                                                                          \
+  hipLaunchKernelGGL((phi2d_ens_kernel<S_, TY, H_>), grid, block, 0, st, mem, tile_member, ntiles, \
+                     cur, pass, last)
+    if (sub == 2) {
+      if (hydro) ENS_PHI(2, true);
+      else ENS_PHI(2, false);
+    } else {
+      if (hydro) ENS_PHI(1, true);
+      else ENS_PHI(1, false);
+    }
+#undef ENS_PHI
+    remaining -= sub;
+    ++pass;
+  }
+}
+
+hipError_t launch_ens_step(const EnsMember* mem, const int* tile_member, int ntiles, int ty,
+                           int cur, int half, int hydro, int nphi, hipStream_t st) {
+  if (ty == 16) ens_step_ty<16>(mem, tile_member, ntiles, cur, half, hydro, nphi, st);
+  else if (ty == 32) ens_step_ty<32>(mem, tile_member, ntiles, cur, half, hydro, nphi, st);
+  else if (ty == 64) ens_step_ty<64>(mem, tile_member, ntiles, cur, half, hydro, nphi, st);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

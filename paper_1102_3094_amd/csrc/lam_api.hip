@@ -31,6 +31,8 @@ hipError_t launch_lb3d(const KParams& P, int mode, const void* gin, void* gout,
 hipError_t launch_phi3d(const KParams& P, const float* in, float* out, const float* u,
                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_ens_step(const EnsMember* mem, const int* tile_member, int ntiles, int ty,
+                           int cur, int half, int hydro, int nphi, hipStream_t st);
 // lam_util.hip
 hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, void* g,
                        hipStream_t st);
@@ -511,6 +513,266 @@ void lam_destroy(lam_sim* s) {
   if (!s) return;
   for (hipEvent_t e : s->ev) hipEventDestroy(e);
   delete s;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Ensembles.
+struct lam_ensemble {
+  std::vector<lam_sim*> sims;
+  std::vector<EnsMember> host_members;
+  std::vector<int> host_tiles;
+  EnsMember* d_members = nullptr;
+  int* d_tile_member = nullptr;
+  int ntiles = 0, ty = 32, nphi = 1, hydro = 1, half = 0;
+  hipStream_t st = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int64_t sites = 0;
+  std::string err;
+};
+
+namespace {
+
+int efail(lam_ensemble* e, int code, const std::string& msg) {
+  if (e) e->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+struct EnsLayout {
+  std::vector<size_t> off, bytes;
+  size_t members, tiles, total;
+};
+
+int ens_layout(const lam_params* m, int count, EnsLayout& L, std::string& why) {
+  if (!m || count < 1) return why = "need at least one member", LAM_EINVAL;
+  size_t off = 0, maxtiles = 0;
+  for (int i = 0; i < count; ++i) {
+    int rc = validate(&m[i], why);
+    if (rc) return why = "member " + std::to_string(i) + ": " + why, rc;
+    if (m[i].dim != 2) return why = "ensemble members must be 2D", LAM_EINVAL;
+    if (m[i].hydro != m[0].hydro || m[i].pop_storage != m[0].pop_storage)
+      return why = "members differ in hydro or pop_storage", LAM_EINVAL;
+    int n0 = m[0].n_phi_sub > 0 ? m[0].n_phi_sub : auto_nphi(m[0]);
+    int ni = m[i].n_phi_sub > 0 ? m[i].n_phi_sub : auto_nphi(m[i]);
+    if (n0 != ni) return why = "members need different phi sub-step counts", LAM_EINVAL;
+    size_t b = layout(m[i]).total;
+    L.off.push_back(off);
+    L.bytes.push_back(b);
+    off = align256(off + b);
+    maxtiles += (size_t)((m[i].nx + 63) / 64) * ((m[i].ny + 15) / 16);
+  }
+  L.members = off;
+  off = align256(off + sizeof(EnsMember) * count);
+  L.tiles = off;
+  off = align256(off + sizeof(int) * maxtiles);
+  L.total = off;
+  return LAM_OK;
+}
+
+int ens_build_tiles(lam_ensemble* e, int ty) {
+  e->host_tiles.clear();
+  int t = 0;
+  for (size_t i = 0; i < e->sims.size(); ++i) {
+    const KParams& k = e->sims[i]->k;
+    int n = ((k.nx + 63) / 64) * ((k.ny + ty - 1) / ty);
+    e->host_members[i].tile0 = t;
+    for (int j = 0; j < n; ++j) e->host_tiles.push_back((int)i);
+    t += n;
+  }
+  e->ntiles = t;
+  e->ty = ty;
+  hipError_t r = hipMemcpy(e->d_members, e->host_members.data(),
+                           sizeof(EnsMember) * e->host_members.size(), hipMemcpyHostToDevice);
+  if (r == hipSuccess)
+    r = hipMemcpy(e->d_tile_member, e->host_tiles.data(), sizeof(int) * e->host_tiles.size(),
+                  hipMemcpyHostToDevice);
+  if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("tile table: ") + hipGetErrorString(r));
+  if (e->graph) {
+    hipGraphExecDestroy(e->graph);
+    e->graph = nullptr;
+  }
+  return LAM_OK;
+}
+
+hipError_t ens_one_step(lam_ensemble* e, int cur) {
+  return launch_ens_step(e->d_members, e->d_tile_member, e->ntiles, e->ty, cur, e->half, e->hydro,
+                         e->nphi, e->st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lam_ensemble_workspace_bytes(const lam_params* members, int32_t count, size_t* bytes) {
+  EnsLayout L;
+  std::string why;
+  int rc = ens_layout(members, count, L, why);
+  if (rc) return efail(nullptr, rc, why);
+  if (!bytes) return efail(nullptr, LAM_EINVAL, "null output");
+  *bytes = L.total;
+  return LAM_OK;
+}
+
+int lam_ensemble_create(const lam_params* members, int32_t count, void* d_workspace, size_t bytes,
+                        void* hip_stream, lam_ensemble** out) {
+  if (!out) return efail(nullptr, LAM_EINVAL, "null output handle");
+  *out = nullptr;
+  EnsLayout L;
+  std::string why;
+  int rc = ens_layout(members, count, L, why);
+  if (rc) return efail(nullptr, rc, why);
+  if (!d_workspace || bytes < L.total)
+    return efail(nullptr, LAM_ESIZE, "workspace smaller than lam_ensemble_workspace_bytes()");
+  if (((uintptr_t)d_workspace) & 255) return efail(nullptr, LAM_EINVAL, "workspace not 256-byte aligned");
+  lam_ensemble* e = new lam_ensemble();
+  e->st = (hipStream_t)hip_stream;
+  char* ws = (char*)d_workspace;
+  for (int i = 0; i < count; ++i) {
+    lam_sim* s = nullptr;
+    rc = lam_create(&members[i], ws + L.off[i], L.bytes[i], hip_stream, &s);
+    if (rc) {
+      lam_ensemble_destroy(e);
+      return efail(nullptr, rc, "member " + std::to_string(i) + ": " + g_create_error);
+    }
+    e->sims.push_back(s);
+    EnsMember m{};
+    m.P = s->k;
+    m.g[0] = s->g[0];
+    m.g[1] = s->g[1];
+    m.phi[0] = s->phi[0];
+    m.phi[1] = s->phi[1];
+    m.psi[0] = s->psi[0];
+    m.psi[1] = s->psi[1];
+    m.u = s->u;
+    for (int k = 0; k < 3; ++k) m.T[k] = s->T[k];
+    e->host_members.push_back(m);
+    e->sites += (int64_t)s->N;
+  }
+  e->nphi = e->sims[0]->nphi;
+  e->hydro = members[0].hydro;
+  e->half = members[0].pop_storage == 1;
+  e->d_members = (EnsMember*)(ws + L.members);
+  e->d_tile_member = (int*)(ws + L.tiles);
+  rc = ens_build_tiles(e, 32);
+  if (rc) {
+    std::string msg = e->err;
+    lam_ensemble_destroy(e);
+    return efail(nullptr, rc, msg);
+  }
+  *out = e;
+  return LAM_OK;
+}
+
+int lam_ensemble_member(lam_ensemble* e, int32_t i, lam_sim** out) {
+  if (!e || !out || i < 0 || i >= (int)e->sims.size()) return efail(e, LAM_EINVAL, "bad member index");
+  *out = e->sims[i];
+  return LAM_OK;
+}
+
+int lam_ensemble_init_fields(lam_ensemble* e, const float* const* d_phi0) {
+  if (!e || !d_phi0) return efail(e, LAM_EINVAL, "bad arguments");
+  for (size_t i = 0; i < e->sims.size(); ++i) {
+    int rc = lam_init_fields(e->sims[i], d_phi0[i], nullptr, nullptr);
+    if (rc) return efail(e, rc, "member " + std::to_string(i) + ": " + e->sims[i]->err);
+  }
+  return LAM_OK;
+}
+
+int lam_ensemble_step(lam_ensemble* e, int64_t nsteps) {
+  if (!e || nsteps < 0) return efail(e, LAM_EINVAL, "bad arguments");
+  const int64_t step0 = e->sims[0]->step;
+  for (lam_sim* s : e->sims) {
+    if (!s->initialised) return efail(e, LAM_EINVAL, "member fields not initialised");
+    if (s->step != step0) return efail(e, LAM_EINVAL, "members were stepped separately");
+  }
+  int64_t done = 0, step = step0;
+  auto direct = [&]() -> int {
+    hipError_t r = ens_one_step(e, (int)(step & 1));
+    if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("ensemble step: ") + hipGetErrorString(r));
+    ++step;
+    ++done;
+    return LAM_OK;
+  };
+  if ((step & 1) && done < nsteps) {
+    int rc = direct();
+    if (rc) return rc;
+  }
+  if (e->st && nsteps - done >= 2) {
+    if (!e->graph) {  // capture one pair of steps (parity 0 then 1) once
+      hipGraph_t g;
+      hipError_t r = hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal);
+      if (r == hipSuccess) r = ens_one_step(e, 0);
+      if (r == hipSuccess) r = ens_one_step(e, 1);
+      hipError_t r2 = hipStreamEndCapture(e->st, &g);
+      if (r == hipSuccess) r = r2;
+      if (r == hipSuccess) r = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+      if (r2 == hipSuccess) hipGraphDestroy(g);
+      if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("graph capture: ") + hipGetErrorString(r));
+    }
+    while (nsteps - done >= 2) {
+      hipError_t r = hipGraphLaunch(e->graph, e->st);
+      if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("graph launch: ") + hipGetErrorString(r));
+      step += 2;
+      done += 2;
+    }
+  }
+  while (done < nsteps) {
+    int rc = direct();
+    if (rc) return rc;
+  }
+  for (lam_sim* s : e->sims) s->step = step;
+  return LAM_OK;
+}
+
+int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height) {
+  if (!e || steps < 1) return efail(e, LAM_EINVAL, "bad arguments");
+  for (lam_sim* s : e->sims) s->initialised = true;  // timing does not depend on the values
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return efail(e, LAM_EHIP, "event creation");
+  const int cand[3] = {16, 32, 64};
+  int best = 32;
+  float best_ms = 1e30f;
+  for (int c : cand) {
+    int rc = ens_build_tiles(e, c);
+    if (rc) return rc;
+    if ((rc = lam_ensemble_step(e, 2))) return rc;
+    hipEventRecord(a, e->st);
+    if ((rc = lam_ensemble_step(e, steps))) return rc;
+    hipEventRecord(b, e->st);
+    hipEventSynchronize(b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  int rc = ens_build_tiles(e, best);
+  if (rc) return rc;
+  if (tile_height) *tile_height = best;
+  return LAM_OK;
+}
+
+int lam_ensemble_sites(const lam_ensemble* e, int64_t* sites) {
+  if (!e || !sites) return LAM_EINVAL;
+  *sites = e->sites;
+  return LAM_OK;
+}
+
+const char* lam_ensemble_last_error(const lam_ensemble* e) {
+  return e ? e->err.c_str() : g_create_error.c_str();
+}
+
+void lam_ensemble_destroy(lam_ensemble* e) {
+  if (!e) return;
+  if (e->graph) hipGraphExecDestroy(e->graph);
+  for (lam_sim* s : e->sims) lam_destroy(s);
+  delete e;
 }
 
 }  // extern "C"

@@ -36,6 +36,20 @@ __device__ __forceinline__ float from_f32<float>(float v) { return v; }
 template <>
 __device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half_rn(v); }
 
+// One member of an ensemble as the ensemble kernels see it: its parameters, its device buffers
+// (populations by step parity, phi by step parity, phi scratch, u, T by parity + scratch) and the
+// index of its first tile in the concatenated tile list.
+struct EnsMember {
+  KParams P;
+  void* g[2];
+  float* phi[2];
+  float* psi[2];
+  float* u;
+  float* T[3];
+  int tile0;
+  int pad_;
+};
+
 // Reduction slots of the observables.
 enum { R_MASS = 0, R_JX, R_JY, R_JZ, R_PHI, R_FE, R_UMAX, R_BAD, R_N };
 

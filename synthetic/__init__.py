@@ -93,7 +93,7 @@ def model_params(name_or_dict, **overrides) -> dict:
     w.update(overrides)
     return {k: w[k] for k in MODEL_KEYS if k in w} | {
         k: w[k] for k in ("n_phi_sub", "n_T_sub", "force_form", "body_force", "pop_storage",
-                          "allow_unstable") if k in w}
+                          "allow_unstable", "tile_hint") if k in w}
 
 
 def shape_of(p: dict):
@@ -105,3 +105,25 @@ def initial_phi(name_or_dict, seed=None, **overrides) -> np.ndarray:
     w.update(overrides)
     return phi0(shape_of(w), seed=w.get("seed", 1) if seed is None else seed,
                 amplitude=w.get("amplitude", 0.05))
+
+
+def ensemble_members(seed: int = 1, count: int = 64, pop_storage: int = 1):
+    """The batched-ensemble workload: `count` independent 2D runs with cold walls; side lengths
+    log-uniform in [128, 512] (rounded), xi log-uniform in [1e-3, 1], tau uniform in
+    [0.55, 3.0]; free-energy coefficients and temperatures as the 64^2 workload; populations
+    stored in FP16 by default.  Draws come from three separate SplitMix64 streams of `seed`.
+    Returns (parameter dicts, initial phi arrays)."""
+    import math
+    u_side = uniform01(seed, count, offset=1 << 40)
+    u_xi = uniform01(seed, count, offset=2 << 40)
+    u_tau = uniform01(seed, count, offset=3 << 40)
+    members, phis = [], []
+    for i in range(count):
+        side = int(round(math.exp(math.log(128) + u_side[i] * (math.log(512) - math.log(128)))))
+        xi = math.exp(math.log(1e-3) + u_xi[i] * (math.log(1.0) - math.log(1e-3)))
+        tau = 0.55 + u_tau[i] * (3.0 - 0.55)
+        p = dict(dim=2, nx=side, ny=side, nz=1, walls=1, hydro=1, tau=tau, xi=xi,
+                 pop_storage=pop_storage, **_BJ)
+        members.append(p)
+        phis.append(phi0((side, side), seed=seed * 1000 + i))
+    return members, phis

@@ -95,3 +95,18 @@ def test_substep_rule_host(L):
         L.lam_substeps(h, C.byref(a), C.byref(b))
         L.lam_destroy(h)
         assert a.value == want and b.value == 1
+
+
+def test_ensemble_validation(L):
+    a = S.model_params("c1_64sq")
+    b = S.model_params("c1_64sq", nx=100, tau=0.7)
+    arr = (lam.lam_params * 2)(lam.make_params(a), lam.make_params(b))
+    n = C.c_size_t()
+    assert L.lam_ensemble_workspace_bytes(arr, 2, C.byref(n)) == 0 and n.value > 0
+    c = S.model_params("c1_64sq", kappa=-0.03, c=0.03, T0=0.0075, Tw=0.0045, Tc=0.005)
+    arr = (lam.lam_params * 2)(lam.make_params(a), lam.make_params(c))
+    assert L.lam_ensemble_workspace_bytes(arr, 2, C.byref(n)) == lam.LAM_EINVAL
+    assert b"sub-step" in L.lam_ensemble_last_error(None)
+    d = S.model_params("c3_256cube_xi0.1", nx=16, ny=16, nz=16)
+    arr = (lam.lam_params * 2)(lam.make_params(a), lam.make_params(d))
+    assert L.lam_ensemble_workspace_bytes(arr, 2, C.byref(n)) == lam.LAM_EINVAL
