@@ -50,26 +50,27 @@ def phi0(shape, seed: int = 1, amplitude: float = 0.05) -> np.ndarray:
 
 # Model parameters of the workloads.  tau: BGK relaxation time; Gamma: mobility; b, kappa, c:
 # Brazovskii free-energy coefficients; Tc, T0, Tw: critical, initial and wall temperatures;
-# xi: thermal conductivity (a negative value stands for an infinitely fast quench).
-_BJ = dict(Gamma=0.1, b=0.1, kappa=-0.006, c=0.0375, Tc=1.0, T0=1.5, Tw=0.7)
+# xi: thermal conductivity (a negative value stands for an infinitely fast quench).  _DEEP_QUENCH:
+# the coefficients of the 64^2, 1024^2, 256^3 and ensemble workloads (walls at 0.7 Tc).
+_DEEP_QUENCH = dict(Gamma=0.1, b=0.1, kappa=-0.006, c=0.0375, Tc=1.0, T0=1.5, Tw=0.7)
 
 WORKLOADS = {
     # 64x64 D2Q9, periodic x, cold walls at y=0 and y=63: the parity workload.
     "c1_64sq": dict(dim=2, nx=64, ny=64, nz=1, walls=1, hydro=1, tau=1.0, xi=0.05, steps=2000,
-                    seed=1, **_BJ),
+                    seed=1, **_DEEP_QUENCH),
     # 1024x1024 D2Q9 at two viscosities: the throughput workload (S(k) and orientation every 1k).
     "c2_1024sq_tau0.6": dict(dim=2, nx=1024, ny=1024, nz=1, walls=1, hydro=1, tau=0.6, xi=0.01,
-                             steps=50000, seed=1, **_BJ),
+                             steps=50000, seed=1, **_DEEP_QUENCH),
     "c2_1024sq_tau2.0": dict(dim=2, nx=1024, ny=1024, nz=1, walls=1, hydro=1, tau=2.0, xi=0.01,
-                             steps=50000, seed=1, **_BJ),
+                             steps=50000, seed=1, **_DEEP_QUENCH),
     # 256^3 D3Q19, periodic x and y, cold walls at z=0 and z=255.
     "c3_256cube_xi0.001": dict(dim=3, nx=256, ny=256, nz=256, walls=1, hydro=1, tau=1.0,
-                               xi=0.001, steps=20000, seed=1, **_BJ),
+                               xi=0.001, steps=20000, seed=1, **_DEEP_QUENCH),
     "c3_256cube_xi0.1": dict(dim=3, nx=256, ny=256, nz=256, walls=1, hydro=1, tau=1.0, xi=0.1,
-                             steps=20000, seed=1, **_BJ),
+                             steps=20000, seed=1, **_DEEP_QUENCH),
     # 4096x4096 D2Q9: a working set well above the last-level cache, for the HBM figure.
     "m1_4096sq": dict(dim=2, nx=4096, ny=4096, nz=1, walls=1, hydro=1, tau=0.6, xi=0.01,
-                      steps=2000, seed=1, **_BJ),
+                      steps=2000, seed=1, **_DEEP_QUENCH),
     # The paper's own parameter set (Section 3): 256x256, b=0.1, kappa=-c=-0.03, Tc=0.005,
     # Gamma=0.1, walls at 0.9 Tc, initial noise in [-0.01, 0.01]; tau=5 gives eta=1.5 (Fig. 2).
     "paper_2d_tau5": dict(dim=2, nx=256, ny=256, nz=1, walls=1, hydro=1, tau=5.0, xi=1e-3,
@@ -123,7 +124,22 @@ def ensemble_members(seed: int = 1, count: int = 64, pop_storage: int = 1):
         xi = math.exp(math.log(1e-3) + u_xi[i] * (math.log(1.0) - math.log(1e-3)))
         tau = 0.55 + u_tau[i] * (3.0 - 0.55)
         p = dict(dim=2, nx=side, ny=side, nz=1, walls=1, hydro=1, tau=tau, xi=xi,
-                 pop_storage=pop_storage, **_BJ)
+                 pop_storage=pop_storage, **_DEEP_QUENCH)
         members.append(p)
         phis.append(phi0((side, side), seed=seed * 1000 + i))
     return members, phis
+
+
+def he_uniform(seed: int, shapes, head=None) -> np.ndarray:
+    """Initial parameter vector of a stack of 3x3 convolutions: for each (C_in, C_out) in `shapes`
+    the 9 C_out C_in weights are uniform in [-s, s], s = sqrt(6 / (9 C_in)) (He et al., 2015,
+    uniform variant), followed by C_out zero biases; `head` = (C_in, C_out) of a final 1x1 layer,
+    whose weights and biases start at zero.  Layer k draws from offset k << 32 of `seed`."""
+    parts = []
+    for k, (ci, co) in enumerate(shapes):
+        s = np.sqrt(6.0 / (9 * ci))
+        parts.append(s * (2.0 * uniform01(seed, 9 * ci * co, offset=k << 32) - 1.0))
+        parts.append(np.zeros(co))
+    if head is not None:
+        parts.append(np.zeros(head[0] * head[1] + head[1]))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)

@@ -1,0 +1,167 @@
+"""Pins of the surrogate oracle (U-Net forward and backward, FP64) against what mathematics fixes:
+brute-force sums, adjoint identities, finite differences, translation equivariance, and the
+bfloat16 rounding of a library routine."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle import surrogate as U
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def test_conv3x3_brute_force():
+    """Cross-correlation over the 3x3 taps, periodic in x and zero outside the walls, summed in
+    plain Python loops."""
+    H, W, ci, co = 4, 5, 2, 3
+    r = rng(1)
+    x = r.normal(size=(H, W, ci))
+    Wt = r.normal(size=(9, co, ci))
+    b = r.normal(size=co)
+    got = U.conv3x3(x, Wt, b)
+    for y, xx, o in itertools.product(range(H), range(W), range(co)):
+        s = b[o]
+        for dy, dx, c in itertools.product((-1, 0, 1), (-1, 0, 1), range(ci)):
+            yy = y + dy
+            if 0 <= yy < H:
+                s += Wt[3 * (dy + 1) + dx + 1, o, c] * x[yy, (xx + dx) % W, c]
+        assert got[y, xx, o] == pytest.approx(s, abs=1e-12)
+
+
+def test_conv_adjoints():
+    """<conv(x), g> = <x, input_grad(g)> = <W, weight_grad(x, g)>: the two gradients are the
+    adjoints of the bilinear map, whatever the shapes."""
+    r = rng(2)
+    for H, W, ci, co in [(6, 7, 3, 4), (8, 8, 5, 2), (1, 3, 1, 1)]:
+        x = r.normal(size=(H, W, ci))
+        Wt = r.normal(size=(9, co, ci))
+        g = r.normal(size=(H, W, co))
+        lhs = np.sum(U.conv3x3(x, Wt, np.zeros(co)) * g)
+        assert np.sum(x * U.conv3x3_input_grad(g, Wt)) == pytest.approx(lhs, rel=1e-12)
+        dW, db = U.conv3x3_weight_grad(x, g)
+        assert np.sum(Wt * dW) == pytest.approx(lhs, rel=1e-12)
+        assert np.allclose(db, g.sum(axis=(0, 1)))
+
+
+def test_pool_up_adjoint():
+    r = rng(3)
+    x = r.normal(size=(8, 6, 3))
+    y = r.normal(size=(4, 3, 3))
+    assert np.sum(U.pool(x) * y) == pytest.approx(np.sum(x * U.up(y) / 4.0), rel=1e-13)
+    assert U.pool(U.up(y)) == pytest.approx(y, abs=1e-15)
+
+
+def test_silu_derivative():
+    z = np.linspace(-8, 8, 33)
+    h = 1e-6
+    fd = (U.silu(z + h) - U.silu(z - h)) / (2 * h)
+    assert np.abs(fd - U.dsilu(z)).max() < 1e-9
+    assert U.silu(np.array([0.0]))[0] == 0.0 and U.dsilu(np.array([0.0]))[0] == 0.5
+
+
+def test_bf16_rounding_matches_torch():
+    """Round to nearest even, as torch's float32 -> bfloat16 conversion does."""
+    r = rng(4)
+    x = np.concatenate([r.normal(size=1000) * 10.0 ** r.integers(-6, 6, size=1000),
+                        [1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -1.0 - 2.0 ** -8, 0.0]])
+    x = x.astype(np.float32).astype(np.float64)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(U.bf16(x), ref)
+    assert U.bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0            # tie -> even
+    assert U.bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+
+
+def small_net(seed=5, widths=(4, 6, 8), H=8, W=12):
+    shapes = [(ci, co) for _, ci, co in U.layers(widths)]
+    theta = S.he_uniform(seed, shapes, head=(widths[0], U.OUT_CH))
+    r = rng(seed)
+    theta[-(U.OUT_CH * widths[0] + U.OUT_CH):] = r.normal(size=U.OUT_CH * widths[0] + U.OUT_CH)
+    for name, (Wt, b) in U.split(theta, widths).items():
+        b[...] = 0.1 * r.normal(size=b.shape)
+    x = r.normal(size=(H, W, U.IN_CH))
+    t = r.normal(size=(H, W, U.OUT_CH))
+    return theta, x, t, widths
+
+
+def test_parameter_layout():
+    widths = (32, 64, 128, 256)
+    assert U.param_count(widths) == 1947523
+    th = np.arange(U.param_count(widths), dtype=np.float64)
+    P = U.split(th, widths)
+    assert P["e1a"][0].shape == (9, 32, 5) and P["d3a"][0].shape == (9, 128, 384)
+    assert P["e1a"][0][0, 0, 0] == 0 and P["e1a"][1][0] == 9 * 32 * 5
+    assert P["head"][1][-1] == th[-1]
+
+
+def test_gradient_finite_differences():
+    """Central differences of the loss against the analytic gradient, for a random sample of
+    parameters of every layer and for input sites next to the walls and the x seam."""
+    theta, x, t, widths = small_net()
+    out, cache = U.forward(theta, x, widths)
+    grad, gx = U.backward(theta, cache, out, t, widths)
+    r = rng(6)
+    h = 1e-6
+    o = 0
+    idx = []
+    for name, ci, co in U.layers(widths):
+        n = 9 * ci * co + co
+        idx += list(o + r.choice(n, size=4, replace=False)) + [o + n - 1]
+        o += n
+    idx += list(range(o, theta.size))
+    for i in idx:
+        tp = theta.copy()
+        tp[i] += h
+        tm = theta.copy()
+        tm[i] -= h
+        fd = (U.loss(U.forward(tp, x, widths)[0], t) - U.loss(U.forward(tm, x, widths)[0], t)) / (2 * h)
+        assert fd == pytest.approx(grad[i], rel=1e-5, abs=1e-9), i
+    for (yy, xx, c) in [(0, 0, 0), (7, 11, 4), (0, 5, 2), (3, 0, 1), (7, 6, 3)]:
+        xp = x.copy()
+        xp[yy, xx, c] += h
+        xm = x.copy()
+        xm[yy, xx, c] -= h
+        fd = (U.loss(U.forward(theta, xp, widths)[0], t) - U.loss(U.forward(theta, xm, widths)[0], t)) / (2 * h)
+        assert fd == pytest.approx(gx[yy, xx, c], rel=1e-5, abs=1e-9)
+
+
+def test_x_translation_equivariance():
+    """The lattice is periodic in x; shifting the input by a multiple of 2^(L-1) columns (the
+    pooling stride) shifts the output."""
+    theta, x, t, widths = small_net(W=16)
+    a = U.forward(theta, x, widths)[0]
+    b = U.forward(theta, np.roll(x, 4, axis=1), widths)[0]
+    assert np.allclose(np.roll(a, 4, axis=1), b, atol=1e-12)
+
+
+def test_bf16_emulation_is_close():
+    """q=True rounds at the device's storage points; the result stays within a few bf16 ulps of
+    the FP64 network."""
+    theta, x, t, widths = small_net()
+    a = U.forward(theta, x, widths)[0]
+    b = U.forward(theta, x, widths, q=True)[0]
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 3e-2
+    ga = U.backward(theta, U.forward(theta, x, widths)[1], a, t, widths)[0]
+    gb = U.backward(theta, U.forward(theta, x, widths, q=True)[1], b, t, widths, q=True)[0]
+    assert np.linalg.norm(ga - gb) / np.linalg.norm(ga) < 5e-2
+
+
+def test_adam_first_step():
+    """After one step from zero moments, the bias-corrected update is lr g / (|g| + eps)."""
+    r = rng(7)
+    th = r.normal(size=50)
+    g = r.normal(size=50)
+    new, m, v = U.adam(th, np.zeros(50), np.zeros(50), g, 1, lr=1e-3)
+    assert np.allclose(th - new, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-10)
+
+
+def test_he_uniform_bounds():
+    th = S.he_uniform(3, [(5, 32), (32, 32)], head=(32, 3))
+    assert th.size == 9 * 5 * 32 + 32 + 9 * 32 * 32 + 32 + 32 * 3 + 3
+    w0 = th[:9 * 5 * 32]
+    assert np.abs(w0).max() <= np.sqrt(6 / 45) and np.abs(w0).max() > 0.9 * np.sqrt(6 / 45)
+    assert np.all(th[-(32 * 3 + 3):] == 0)
