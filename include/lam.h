@@ -130,6 +130,16 @@ int lam_orientation(lam_sim* s, double* h_hist, int32_t nbins, double* Q, double
  * u [dim][N] (force-shifted velocity of eq. moment), n [N], T [N]. Asynchronous. */
 int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T);
 
+/* Re-anchoring after an external update of the fields (for example the learned surrogate of
+ * lam_surrogate.h): phi is replaced by d_phi [N] and the populations by the same equilibrium
+ * start as lam_init_fields (density d_n, velocity d_u [dim][N]; NULL gives 1 and 0), while the
+ * temperature and the step count are kept.  Asynchronous. */
+int lam_set_fields(lam_sim* s, const float* d_phi, const float* d_u, const float* d_n);
+
+/* Advance only the temperature by nsteps time steps (the FTCS sub-steps lam_step applies to T,
+ * Section 2) and the step count; phi and the populations are unchanged.  Asynchronous. */
+int lam_advance_temperature(lam_sim* s, int64_t nsteps);
+
 /* Checkpoint: the complete state (populations, phi, T, step) in lam_state_bytes() bytes of
  * caller device memory.  lam_set_state returns LAM_ESTATE for a checkpoint of another lattice. */
 int lam_state_bytes(const lam_sim* s, size_t* bytes);

@@ -1,0 +1,96 @@
+/* lam_surrogate.h -- C-ABI of the learned surrogate of the lamellar-fluid update (gfx950).
+ *
+ * A U-Net maps the fields (phi, u_x, u_y, T, a = (T - Tc)/Tc) of a 2D lattice with walls normal
+ * to y to the increments of (phi, u_x, u_y) over a fixed number of lattice steps.  The paper has
+ * no network: this is an accelerator around its method (Section 2 defines the fields, Section 3
+ * the geometry: periodic in x, walls at y = 0 and y = H - 1).  The plain solver (lam.h) stays the
+ * reference that re-anchors the state and judges the error.
+ *
+ * Network: L levels of widths base * 2^l; each encoder level has two 3x3 convolutions with SiLU,
+ * levels are joined by 2x2 average pooling; each decoder level upsamples 2x (nearest), prepends
+ * the upsampled channels to the encoder output of the level and applies two 3x3 convolutions
+ * with SiLU; a 1x1 head gives 3 outputs.  Convolutions are cross-correlations, periodic in x,
+ * zero-padded across the walls.  Weights and activations are stored in bfloat16, sums are FP32
+ * on the matrix cores; master weights, gradients and Adam moments are FP32.
+ *
+ * Parameter vector (FP32, lsn_param_count entries): for each 3x3 layer in the order e1a, e1, e2a,
+ * e2, ..., eLa, eL, d(L-1)a, d(L-1), ..., d1a, d1 the weights [9][C_out][C_in] (tap = 3 (dy+1) +
+ * (dx+1)) then the biases [C_out]; then the head weights [3][base] and biases [3].  C_in of e1a
+ * is 5; C_in of d(l)a is width(l+1) + width(l).
+ *
+ * Fields are planar FP32 in device memory: [4][H][W] = phi, u_x, u_y, T (x fastest), the layout
+ * lam_get_fields writes.  Network inputs are (field - shift) * scale per channel, channel 4 from
+ * a; outputs are normalised increments: field += out * out_scale.
+ *
+ * Ownership: the caller owns every device buffer (one workspace of lsn_workspace_bytes); the
+ * library allocates no device memory.  All work is queued on the caller's HIP stream; functions
+ * that return host values synchronise it.  Calls on one network are not thread-safe.
+ * Errors: return codes as lam.h (LAM_EINVAL bad sizes or arguments, LAM_EHIP a HIP error,
+ * LAM_ESIZE workspace too small, LAM_ENONFINITE non-finite loss); lsn_last_error gives text. */
+#ifndef LAM_SURROGATE_H
+#define LAM_SURROGATE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsn_net lsn_net;
+
+typedef struct {
+  int32_t height, width;  /* lattice; height % (4 * 2^(levels-1)) == 0, width % (32 * 2^(levels-1)) == 0 */
+  int32_t levels;         /* 1 .. 5 */
+  int32_t base_width;     /* channels of level 1: 32 or 64 */
+  int32_t training;       /* 1: keep activations, gradients and Adam moments */
+  float Tc;               /* critical temperature, for a = (T - Tc)/Tc */
+  float in_shift[5], in_scale[5];  /* input normalisation of phi, u_x, u_y, T, a */
+  float out_scale[3];              /* increments of phi, u_x, u_y per unit output */
+} lsn_config;
+
+int lsn_param_count(const lsn_config* cfg, int64_t* count);
+int lsn_workspace_bytes(const lsn_config* cfg, size_t* bytes);
+int lsn_create(const lsn_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+               lsn_net** out);
+
+/* Parameters in and out (FP32 device vectors of lsn_param_count entries).  Setting them resets
+ * the Adam moments and step count. */
+int lsn_set_params(lsn_net* net, const float* d_params);
+int lsn_get_params(lsn_net* net, float* d_params);
+
+/* Network output for the fields d_fields [4][H][W]: d_out [3][H][W] FP32 (normalised increments). */
+int lsn_forward(lsn_net* net, const float* d_fields, float* d_out);
+
+/* One surrogate step in place on d_fields [4][H][W]: phi, u_x, u_y += out * out_scale, then phi
+ * is shifted by a constant so that its sum over the lattice is unchanged (the exact conservation
+ * law of the method, eq. massdiff).  T is left alone. */
+int lsn_advance(lsn_net* net, float* d_fields);
+
+/* Training target from two snapshots [4][H][W] taken the surrogate's step count apart:
+ * d_target [3][H][W] = (later - earlier) / out_scale for phi, u_x, u_y. */
+int lsn_make_target(lsn_net* net, const float* d_earlier, const float* d_later, float* d_target);
+
+/* Loss and gradient (training networks only): loss = mean over the 3 H W outputs of
+ * (out - target)^2; its gradient with respect to the parameters is ADDED to the gradient buffer
+ * (cleared by lsn_zero_grad, read by lsn_get_grads).  h_loss (nullable) receives the loss and
+ * the call synchronises; LAM_ENONFINITE if it is not finite. */
+int lsn_zero_grad(lsn_net* net);
+int lsn_loss_backward(lsn_net* net, const float* d_fields, const float* d_target, double* h_loss);
+int lsn_get_grads(lsn_net* net, float* d_grads);
+
+/* One Adam step (Kingma & Ba, 2015, with bias correction) on the accumulated gradient scaled by
+ * grad_scale (for example 1/batch), then the bfloat16 weight copies are refreshed. */
+int lsn_adam(lsn_net* net, float lr, float beta1, float beta2, float eps, float grad_scale);
+
+/* Kernel timing: with timing enabled, the next forward's kernels are bracketed by HIP events
+ * and lsn_forward_time returns its duration in ms (synchronises). */
+int lsn_set_timing(lsn_net* net, int32_t enable);
+int lsn_forward_time(lsn_net* net, float* ms);
+
+const char* lsn_last_error(const lsn_net* net);
+void lsn_destroy(lsn_net* net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -40,7 +40,8 @@ class lam_obs(C.Structure):
 EXPORTS = ("lam_workspace_bytes", "lam_create", "lam_substeps", "lam_init_fields", "lam_step",
            "lam_observables", "lam_structure_factor", "lam_orientation", "lam_get_fields",
            "lam_state_bytes", "lam_get_state", "lam_set_state", "lam_set_timing",
-           "lam_kernel_times", "lam_last_error", "lam_destroy",
+           "lam_kernel_times", "lam_last_error", "lam_destroy", "lam_set_fields",
+           "lam_advance_temperature",
            "lam_ensemble_workspace_bytes", "lam_ensemble_create", "lam_ensemble_member",
            "lam_ensemble_init_fields", "lam_ensemble_step", "lam_ensemble_tune",
            "lam_ensemble_sites", "lam_ensemble_last_error", "lam_ensemble_destroy")
@@ -74,6 +75,8 @@ def load():
     L.lam_set_timing.argtypes = [vp, C.c_int32]
     L.lam_kernel_times.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.lam_last_error.argtypes = [vp]
+    L.lam_set_fields.argtypes = [vp, vp, vp, vp]
+    L.lam_advance_temperature.argtypes = [vp, C.c_int64]
     L.lam_last_error.restype = C.c_char_p
     L.lam_destroy.argtypes = [vp]
     L.lam_destroy.restype = None
@@ -201,6 +204,29 @@ class Sim:
     def step(self, n: int = 1):
         self._chk(load().lam_step(self._h, int(n)))
         return self
+
+    def set_fields(self, phi, u=None, n=None):
+        """Replace phi and restart the populations from the equilibrium of (n, u); T and the
+        step count are kept."""
+        phi = self._dev(phi, self.N)
+        u = self._dev(u, self.dim * self.N)
+        n = self._dev(n, self.N)
+        self._keep_set = (phi, u, n)
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        self._chk(load().lam_set_fields(self._h, ptr(phi), ptr(u), ptr(n)))
+        return self
+
+    def advance_temperature(self, n: int):
+        self._chk(load().lam_advance_temperature(self._h, int(n)))
+        return self
+
+    def fields_into(self, buf):
+        """phi, u_x, u_y, T of a 2D run into the planar FP32 device buffer buf [4][ny][nx]."""
+        assert self.dim == 2 and buf.is_contiguous() and buf.numel() == 4 * self.N
+        p = buf.data_ptr()
+        self._chk(load().lam_get_fields(self._h, C.c_void_p(p), C.c_void_p(p + 4 * self.N), None,
+                                        C.c_void_p(p + 12 * self.N)))
+        return buf
 
     def observables(self, raise_nonfinite: bool = False) -> dict:
         o = lam_obs()

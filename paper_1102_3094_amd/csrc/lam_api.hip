@@ -39,6 +39,8 @@ hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* 
 hipError_t launch_init_T(int nrows, int walls, float T0, float Tw, int quench, float* a, float* b,
                          hipStream_t st);
 hipError_t launch_finalize(const double* partials, int nblk, double* out, hipStream_t st);
+hipError_t launch_temperature(int nrows, int walls, float r_T, int n_T, int64_t nsteps,
+                              const float* Tin, float* Tout, hipStream_t st);
 hipError_t launch_broadcast_T(const float* Trow, size_t N, size_t layer, float* out,
                               hipStream_t st);
 hipError_t launch_write_header(int dim, int nx, int ny, int nz, int64_t step, int Q, int esz,
@@ -290,6 +292,37 @@ int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const fl
                           s->T[0], s->T[1], s->st));
   s->step = 0;
   s->initialised = true;
+  return LAM_OK;
+}
+
+int lam_set_fields(lam_sim* s, const float* d_phi, const float* d_u, const float* d_n) {
+  if (!s || !d_phi) return fail(s, LAM_EINVAL, "null simulation or phi");
+  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+  const int cur = (int)(s->step & 1);
+  HIPCHK(s, hipMemcpyAsync(s->phi[cur], d_phi, sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(s, launch_init(s->k, s->p.dim, d_n, d_u, s->g[cur], s->st));
+  return LAM_OK;
+}
+
+int lam_advance_temperature(lam_sim* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return fail(s, LAM_EINVAL, "bad arguments");
+  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+  if (nsteps == 0) return LAM_OK;
+  if (s->nrows > 8192) return fail(s, LAM_EINVAL, "more than 8192 layers along the wall axis");
+  const int cur = (int)(s->step & 1), nxt = (int)((s->step + nsteps) & 1);
+  const float* src = s->T[cur];
+  if (s->k.n_T > 0) {
+    HIPCHK(s, launch_temperature(s->nrows, s->p.walls, s->k.r_T, s->k.n_T, nsteps, src, s->T[2], s->st));
+    src = s->T[2];
+  }
+  if (src != s->T[nxt])
+    HIPCHK(s, hipMemcpyAsync(s->T[nxt], src, sizeof(float) * s->nrows, hipMemcpyDeviceToDevice, s->st));
+  // phi lives in the buffer of the current parity; move it with the step count
+  if (cur != nxt)
+    HIPCHK(s, hipMemcpyAsync(s->phi[nxt], s->phi[cur], sizeof(float) * s->N, hipMemcpyDeviceToDevice, s->st));
+  if (cur != nxt)
+    HIPCHK(s, hipMemcpyAsync(s->g[nxt], s->g[cur], s->pop_bytes, hipMemcpyDeviceToDevice, s->st));
+  s->step += nsteps;
   return LAM_OK;
 }
 

@@ -73,6 +73,42 @@ __global__ void init_T_kernel(int nrows, int walls, float T0, float Tw, int quen
   T1buf[j] = v;
 }
 
+// Temperature only: nsteps x n_T FTCS sub-steps of the per-layer profile (the same update as
+// the tail of the phi kernels), wall layers held; one workgroup, profile in LDS.
+__global__ __launch_bounds__(256) void temperature_kernel(int nrows, int walls, float r_T, int n_T,
+                                                          int64_t nsteps, const float* __restrict__ Tin,
+                                                          float* __restrict__ Tout) {
+  extern __shared__ float sT[];
+  float* a = sT;
+  float* b = sT + nrows;
+  for (int j = threadIdx.x; j < nrows; j += blockDim.x) a[j] = Tin[j];
+  __syncthreads();
+  for (int64_t t = 0; t < nsteps; ++t)
+    for (int m = 0; m < n_T; ++m) {
+      for (int j = threadIdx.x; j < nrows; j += blockDim.x) {
+        float v = a[j];
+        const bool wall = walls && (j == 0 || j == nrows - 1);
+        if (!wall) {
+          const float lo = a[j == 0 ? nrows - 1 : j - 1], hi = a[j == nrows - 1 ? 0 : j + 1];
+          v = v + r_T * ((lo + hi) - 2.f * v);
+        }
+        b[j] = v;
+      }
+      __syncthreads();
+      float* tmp = a;
+      a = b;
+      b = tmp;
+    }
+  for (int j = threadIdx.x; j < nrows; j += blockDim.x) Tout[j] = a[j];
+}
+
+hipError_t launch_temperature(int nrows, int walls, float r_T, int n_T, int64_t nsteps,
+                              const float* Tin, float* Tout, hipStream_t st) {
+  hipLaunchKernelGGL(temperature_kernel, dim3(1), dim3(256), 2 * nrows * sizeof(float), st, nrows,
+                     walls, r_T, n_T, nsteps, Tin, Tout);
+  return hipGetLastError();
+}
+
 // Sum block partials in a fixed order (deterministic), one workgroup of 256 threads.
 __global__ void finalize_kernel(const double* __restrict__ partials, int nblk, int nslot,
                                 double* __restrict__ out) {

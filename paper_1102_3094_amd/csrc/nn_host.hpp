@@ -1,0 +1,65 @@
+// nn_host.hpp -- argument blocks and launchers of the U-Net surrogate kernels (nn_kernels.hip),
+// shared with the host implementation of the surrogate's C-ABI (nn_api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lam {
+namespace nn {
+
+typedef uint16_t bf16_t;  // bfloat16 bit pattern
+
+enum { CONV_FWD = 0, CONV_BWD_SILU = 1, CONV_BWD_PLAIN = 2 };
+
+struct ConvArgs {
+  const bf16_t* in;     // input (offset to its first channel), pixel stride in_ld
+  int in_ld;
+  const bf16_t* w;      // [9][Cout][Cin]
+  const float* bias;    // CONV_FWD: [Cout]
+  bf16_t* out;          // output (offset to its first channel), pixel stride out_ld
+  int out_ld;
+  bf16_t* zout;         // CONV_FWD, optional: pre-activation [pixels][Cout]
+  const bf16_t* zprev;  // CONV_BWD_SILU: pre-activation [pixels][Cout]; the result is multiplied by silu'
+  int H, W, Cin, Cout;
+  int tiles_x, nco;     // set by the launcher
+};
+
+struct PackArgs {
+  float shift[5], scale[5];
+  float Tc;
+};
+
+hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st);
+void wgrad_shape(int H, int W, int Cin, int Cout, size_t max_floats, int* nsplit, int* cps);
+hipError_t launch_wgrad(const bf16_t* x, int x_ld, const bf16_t* g, int H, int W, int Cin, int Cout,
+                        int Cin_dst, float* part, size_t max_floats, float* grad_w, hipStream_t st);
+int bias_blocks(size_t npix);
+hipError_t launch_bias_grad(const bf16_t* g, size_t npix, int C, double* part, float* grad_b,
+                            hipStream_t st);
+hipError_t launch_pack(const float* f, size_t npix, const PackArgs& pa, bf16_t* x, hipStream_t st);
+hipError_t launch_pool(const bf16_t* in, int in_ld, int H, int W, int C, bf16_t* out, hipStream_t st);
+hipError_t launch_up(const bf16_t* in, int h, int w, int C, bf16_t* out, int out_ld, hipStream_t st);
+hipError_t launch_up_bwd_silu(const bf16_t* gcat, int cat_ld, int h, int w, int C, const bf16_t* z,
+                              bf16_t* gz, hipStream_t st);
+hipError_t launch_pool_bwd_silu(const bf16_t* gskip, int skip_ld, const bf16_t* gpool, int H, int W,
+                                int C, const bf16_t* z, bf16_t* gz, hipStream_t st);
+hipError_t launch_head_fwd(const bf16_t* d, int C, size_t npix, const float* Wh, float* out,
+                           hipStream_t st);
+int loss_blocks(size_t npix);
+hipError_t launch_loss_grad(const float* out, const float* t, size_t npix, float* gout, double* part,
+                            hipStream_t st);
+hipError_t launch_head_bwd(const bf16_t* d, int C, size_t npix, const float* gout, const float* Wh,
+                           const bf16_t* z, bf16_t* gz, double* part, float* grad_head,
+                           hipStream_t st);
+hipError_t launch_refresh(const float* W, int Cout, int Cin, int Cin_pad, bf16_t* wf, bf16_t* wd,
+                          hipStream_t st);
+hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, float gscale, hipStream_t st);
+hipError_t launch_make_target(const float* e, const float* l, size_t npix, const float* s, float* t,
+                              hipStream_t st);
+hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s, double* part,
+                        hipStream_t st);
+
+}  // namespace nn
+}  // namespace lam

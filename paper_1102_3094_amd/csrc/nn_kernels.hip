@@ -1,0 +1,792 @@
+// nn_kernels.hip -- gfx950 kernels of the U-Net surrogate: 3x3 convolutions (forward and input
+// gradient) and their weight gradients on the BF16 matrix cores (v_mfma_f32_32x32x16_bf16), plus
+// the memory-bound pieces (input packing, pooling, upsampling, head, loss, reductions, Adam).
+//
+// Activations are NHWC bfloat16 (channel fastest) with a pixel stride `ld` that may exceed the
+// channel count, so that a tensor can live inside a concatenation buffer.  A 3x3 layer is an
+// implicit GEMM: M = pixels, N = output channels, K = 9 taps x input channels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "lam_dev.hpp"
+#include "nn_host.hpp"
+
+namespace lam {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float((uint32_t)v << 16); }
+// Round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float sigm(float z) { return 1.f / (1.f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  float s = sigm(z);
+  return s * (1.f + z * (1.f - s));
+}
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+constexpr int PSTR = 40;  // LDS elements per pixel (or weight row) of a 32-channel chunk: 8 pad
+
+// Workgroup = 4 waves; tile = (4 RW) rows x 32 columns x (32 NJ) output channels; wave w owns
+// rows w RW .. w RW + RW - 1.  Per 32-channel chunk of the input: the (4 RW + 2) x 34 input
+// patch and the 9 x 32 NJ x 32 weights are staged in LDS (the next chunk is loaded into
+// registers while the matrix cores work on the current one).  For each column offset dx and
+// 16-channel half, the wave reads RW + 2 input rows once and reuses them for the three row
+// offsets dy.
+template <int MODE, int RW, int NJ>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+  constexpr int PR = 4 * RW + 2, PC = 34;
+  constexpr int NPV = PR * PC * 4, NWV = 9 * 32 * NJ * 4;  // 16-byte vectors per chunk
+  constexpr int LP = (NPV + 255) / 256, LW = (NWV + 255) / 256;
+  __shared__ __align__(16) bf16_t sp[PR * PC * PSTR];
+  __shared__ __align__(16) bf16_t sw[9 * 32 * NJ * PSTR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 31, kh = lane >> 5;
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int cob = L % a.nco, tile = L / a.nco;
+  const int x0 = (tile % a.tiles_x) * 32, y0 = (tile / a.tiles_x) * 4 * RW, co0 = cob * 32 * NJ;
+  const int H = a.H, W = a.W;
+
+  u32x4 rp[LP], rw[LW];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int i = 0; i < LP; ++i) {
+      const int idx = tid + i * 256;
+      rp[i] = u32x4{0, 0, 0, 0};
+      if (idx < NPV) {
+        const int pr = idx / (PC * 4), rem = idx % (PC * 4), col = rem >> 2, part = rem & 3;
+        const int y = y0 - 1 + pr;
+        int x = x0 - 1 + col;
+        x = x < 0 ? x + W : (x >= W ? x - W : x);
+        if (y >= 0 && y < H)
+          rp[i] = *(const u32x4*)(a.in + ((size_t)y * W + x) * a.in_ld + c0 + part * 8);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LW; ++i) {
+      const int idx = tid + i * 256;
+      if (idx < NWV) {
+        const int tap = idx / (32 * NJ * 4), rem = idx % (32 * NJ * 4), co = rem >> 2, part = rem & 3;
+        rw[i] = *(const u32x4*)(a.w + ((size_t)tap * a.Cout + co0 + co) * a.Cin + c0 + part * 8);
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < LP; ++i) {
+      const int idx = tid + i * 256;
+      if (idx < NPV) {
+        const int pr = idx / (PC * 4), rem = idx % (PC * 4), col = rem >> 2, part = rem & 3;
+        *(u32x4*)(sp + (pr * PC + col) * PSTR + part * 8) = rp[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LW; ++i) {
+      const int idx = tid + i * 256;
+      if (idx < NWV) {
+        const int tap = idx / (32 * NJ * 4), rem = idx % (32 * NJ * 4), co = rem >> 2, part = rem & 3;
+        *(u32x4*)(sw + (tap * 32 * NJ + co) * PSTR + part * 8) = rw[i];
+      }
+    }
+  };
+
+  f32x16 acc[RW][NJ];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[r][j][q] = 0.f;
+
+  load(0);
+  for (int c0 = 0; c0 < a.Cin; c0 += 32) {
+    __syncthreads();
+    stage();
+    __syncthreads();
+    if (c0 + 32 < a.Cin) load(c0 + 32);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        bf16x8 A[RW + 2];
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r)
+          A[r] = as_bf(*(const u32x4*)(sp + ((wave * RW + r) * PC + m + dx) * PSTR + kk * 16 + kh * 8));
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int tap = dy * 3 + dx;
+          bf16x8 B[NJ];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            B[j] = as_bf(*(const u32x4*)(sw + (tap * 32 * NJ + j * 32 + m) * PSTR + kk * 16 + kh * 8));
+#pragma unroll
+          for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+              acc[r][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[r + dy], B[j], acc[r][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // D layout of the 32x32 MFMA: lane holds column m (output channel) and rows
+  // 8 (q / 4) + 4 kh + (q % 4), q = 0..15 (pixel within the 32-column row).
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int y = y0 + wave * RW + r;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int co = co0 + j * 32 + m;
+      const float bco = MODE == CONV_FWD ? a.bias[co] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int x = x0 + 8 * (q >> 2) + 4 * kh + (q & 3);
+        const size_t p = (size_t)y * W + x;
+        const float v = acc[r][j][q];
+        if (MODE == CONV_FWD) {
+          const float z = v + bco;
+          a.out[p * a.out_ld + co] = f2bf(z * sigm(z));
+          if (a.zout) a.zout[p * a.Cout + co] = f2bf(z);
+        } else if (MODE == CONV_BWD_SILU) {
+          a.out[p * a.out_ld + co] = f2bf(v * dsilu(bf2f(a.zprev[p * a.Cout + co])));
+        } else {
+          a.out[p * a.out_ld + co] = f2bf(v);
+        }
+      }
+    }
+  }
+}
+
+// Weight gradient of a 3x3 layer: dW[tap][co][ci] = sum_p g[p][co] X[p + off(tap)][ci], an MFMA
+// GEMM with K = pixels.  Workgroup = 3 waves (wave = row offset dy); block (32 MJ output channels)
+// x (32 input channels) x a range of pixel chunks (4 rows x 32 columns each).  Both operands
+// need 8 consecutive pixels of one channel per lane, so each chunk is transposed into LDS
+// (channel-major): g once, X three times (one copy per column offset dx, so that every MFMA
+// operand read is 16-byte aligned).  Partial sums go to part[split][9][Cout][Cin] (FP32).
+struct WgradArgs {
+  const bf16_t* x;  // layer input (offset to its first channel), pixel stride x_ld
+  int x_ld;
+  const bf16_t* g;  // gradient w.r.t. the pre-activation, [pixels][Cout]
+  float* part;
+  int H, W, Cin, Cout;
+  int nco, nci, nsplit, nchunks, cps;  // blocks, splits, chunks, chunks per split
+};
+
+constexpr int GST = 4 * 32 + 8;   // LDS stride per channel of the g chunk (elements)
+constexpr int XST = 6 * 32 + 8;   // LDS stride per channel of one shifted X chunk
+
+template <int MJ>
+__global__ __launch_bounds__(192) void wgrad_kernel(WgradArgs a) {
+  __shared__ __align__(16) bf16_t sg[32 * MJ * GST];
+  __shared__ __align__(16) bf16_t sx[3 * 32 * XST];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // wave = dy index
+  const int m = lane & 31, kh = lane >> 5;
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int split = L % a.nsplit, blk = L / a.nsplit;
+  const int cib = blk % a.nci, cob = blk / a.nci;
+  const int ci0 = cib * 32, co0 = cob * 32 * MJ;
+  const int H = a.H, W = a.W, tiles_x = W / 32;
+
+  f32x16 acc[3][MJ];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < MJ; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[d][j][q] = 0.f;
+
+  const int c_begin = split * a.cps;
+  const int c_end = min(a.nchunks, c_begin + a.cps);
+  for (int ch = c_begin; ch < c_end; ++ch) {
+    const int x0 = (ch % tiles_x) * 32, y0 = (ch / tiles_x) * 4;
+    __syncthreads();
+    // g chunk: tasks (channel pair, row, group of 8 pixels) -> two 16-byte LDS rows.
+    for (int t = tid; t < 16 * MJ * 4 * 4; t += 192) {
+      const int cp = t % (16 * MJ), rg = t / (16 * MJ), r = rg >> 2, grp = rg & 3;
+      uint32_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        v[k] = *(const uint32_t*)(a.g + ((size_t)(y0 + r) * W + x0 + grp * 8 + k) * a.Cout + co0 + 2 * cp);
+      u32x4 lo, hi;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        lo[k] = (v[2 * k] & 0xFFFFu) | (v[2 * k + 1] << 16);
+        hi[k] = (v[2 * k] >> 16) | (v[2 * k + 1] & 0xFFFF0000u);
+      }
+      *(u32x4*)(sg + (2 * cp) * GST + r * 32 + grp * 8) = lo;
+      *(u32x4*)(sg + (2 * cp + 1) * GST + r * 32 + grp * 8) = hi;
+    }
+    // X chunk, three column shifts: tasks (channel pair, dx, patch row, group).
+    for (int t = tid; t < 16 * 3 * 6 * 4; t += 192) {
+      const int cp = t % 16, rest = t / 16, grp = rest & 3, pr = (rest >> 2) % 6, dx = (rest >> 2) / 6;
+      const int y = y0 - 1 + pr;
+      uint32_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        int x = x0 + grp * 8 + k + dx - 1;
+        x = x < 0 ? x + W : (x >= W ? x - W : x);
+        v[k] = (y >= 0 && y < H) ? *(const uint32_t*)(a.x + ((size_t)y * W + x) * a.x_ld + ci0 + 2 * cp) : 0u;
+      }
+      u32x4 lo, hi;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        lo[k] = (v[2 * k] & 0xFFFFu) | (v[2 * k + 1] << 16);
+        hi[k] = (v[2 * k] >> 16) | (v[2 * k + 1] & 0xFFFF0000u);
+      }
+      bf16_t* base = sx + dx * 32 * XST + pr * 32 + grp * 8;
+      *(u32x4*)(base + (2 * cp) * XST) = lo;
+      *(u32x4*)(base + (2 * cp + 1) * XST) = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        bf16x8 A[MJ];
+#pragma unroll
+        for (int j = 0; j < MJ; ++j)
+          A[j] = as_bf(*(const u32x4*)(sg + (j * 32 + m) * GST + r * 32 + kk * 16 + kh * 8));
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const bf16x8 B = as_bf(*(const u32x4*)(sx + dx * 32 * XST + m * XST + (r + wave) * 32 + kk * 16 + kh * 8));
+#pragma unroll
+          for (int j = 0; j < MJ; ++j)
+            acc[dx][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[j], B, acc[dx][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // acc[dx][j] holds D[co = co0 + 32 j + row][ci = ci0 + m], row = 8 (q/4) + 4 kh + q % 4.
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) {
+    const int tap = wave * 3 + dx;
+#pragma unroll
+    for (int j = 0; j < MJ; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int co = co0 + 32 * j + 8 * (q >> 2) + 4 * kh + (q & 3);
+        a.part[(((size_t)split * 9 + tap) * a.Cout + co) * a.Cin + ci0 + m] = acc[dx][j][q];
+      }
+  }
+}
+
+// grad[i] += sum_s part[s][i'] in fixed order (deterministic); the partials are laid out
+// [9][Cout][Cin_pad], the gradient [9][Cout][Cin_dst] (Cin_dst <= Cin_pad drops zero padding).
+__global__ void reduce_splits_kernel(const float* __restrict__ part, int nsplit, int Cin_pad,
+                                     int Cin_dst, size_t n_dst, float* __restrict__ grad) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_dst) return;
+  const size_t src = (i / Cin_dst) * Cin_pad + i % Cin_dst;
+  const size_t n_src = n_dst / Cin_dst * Cin_pad;
+  float s = 0.f;
+  for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n_src + src];
+  grad[i] += s;
+}
+
+// Column sums of a [npix][C] bfloat16 tensor (C <= 256, 256 % C == 0) over pixel ranges of
+// `per` pixels: part[block][c] (FP64).
+__global__ __launch_bounds__(256) void colsum_bf16_kernel(const bf16_t* __restrict__ g, int npix,
+                                                          int C, int per, double* __restrict__ part) {
+  __shared__ double sm[256];
+  const int tid = threadIdx.x, c = tid % C, grp = tid / C, ngrp = 256 / C;
+  const int p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
+  double s = 0.0;
+  for (int p = p0 + grp; p < p1; p += ngrp) s += bf2f(g[(size_t)p * C + c]);
+  sm[tid] = s;
+  __syncthreads();
+  if (grp == 0) {
+    for (int k = 1; k < ngrp; ++k) s += sm[k * C + c];
+    part[(size_t)blockIdx.x * C + c] = s;
+  }
+}
+
+// out[i] += sum_b part[b][i] (FP64 partials into an FP32 vector), fixed order.
+__global__ void reduce_blocks_f64_kernel(const double* __restrict__ part, int nblk, int n,
+                                         float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * n + i];
+  out[i] += (float)s;
+}
+
+// Input packing: fields [4][H][W] FP32 (phi, ux, uy, T) -> [H W][32] bfloat16, channels
+// (f - shift) * scale, channel 4 from a = (T - Tc) / Tc, channels 5..31 zero.
+__global__ void pack_input_kernel(const float* __restrict__ f, size_t npix, PackArgs pa,
+                                  bf16_t* __restrict__ x) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  float v[5];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = (f[c * npix + p] - pa.shift[c]) * pa.scale[c];
+  v[4] = ((f[3 * npix + p] - pa.Tc) / pa.Tc - pa.shift[4]) * pa.scale[4];
+  u32x4 w0;
+  w0[0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+  w0[1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+  w0[2] = (uint32_t)f2bf(v[4]);
+  w0[3] = 0;
+  u32x4* dst = (u32x4*)(x + p * 32);
+  dst[0] = w0;
+  dst[1] = dst[2] = dst[3] = u32x4{0, 0, 0, 0};
+}
+
+// 2x2 average pool: in [H][W] (pixel stride in_ld) -> out [H/2][W/2][C]; one thread per output
+// pixel and group of 8 channels.
+__global__ void pool_kernel(const bf16_t* __restrict__ in, int in_ld, int H, int W, int C,
+                            bf16_t* __restrict__ out) {
+  const int h = H / 2, w = W / 2, G = C / 8;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)h * w * G) return;
+  const int g = (int)(i % G);
+  const size_t p = i / G;
+  const int y = (int)(p / w), x = (int)(p % w);
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const size_t q = (size_t)(2 * y + (d >> 1)) * W + 2 * x + (d & 1);
+    const u32x4 v = *(const u32x4*)(in + q * in_ld + g * 8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s[2 * k] += __uint_as_float(v[k] << 16);
+      s[2 * k + 1] += __uint_as_float(v[k] & 0xFFFF0000u);
+    }
+  }
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    o[k] = (uint32_t)f2bf(0.25f * s[2 * k]) | ((uint32_t)f2bf(0.25f * s[2 * k + 1]) << 16);
+  *(u32x4*)(out + p * C + g * 8) = o;
+}
+
+// Nearest 2x upsampling: in [h][w][C] -> out [2h][2w] (pixel stride out_ld, channels 0..C-1).
+__global__ void up_kernel(const bf16_t* __restrict__ in, int h, int w, int C,
+                          bf16_t* __restrict__ out, int out_ld) {
+  const int W = 2 * w, G = C / 8;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)4 * h * w * G) return;
+  const int g = (int)(i % G);
+  const size_t p = i / G;
+  const int y = (int)(p / W), x = (int)(p % W);
+  *(u32x4*)(out + p * out_ld + g * 8) = *(const u32x4*)(in + ((size_t)(y / 2) * w + x / 2) * C + g * 8);
+}
+
+// Gradient through the upsampling into a SiLU output: gz[p][c] = bf16(silu'(z[p][c]) *
+// sum over the 2x2 fine pixels of gcat[.][c]) for the coarse [h][w][C] map; gcat has pixel
+// stride cat_ld, the upsampled channels first.
+__global__ void up_bwd_silu_kernel(const bf16_t* __restrict__ gcat, int cat_ld, int h, int w, int C,
+                                   const bf16_t* __restrict__ z, bf16_t* __restrict__ gz) {
+  const int W = 2 * w, G = C / 8;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)h * w * G) return;
+  const int g = (int)(i % G);
+  const size_t p = i / G;
+  const int y = (int)(p / w), x = (int)(p % w);
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const size_t q = (size_t)(2 * y + (d >> 1)) * W + 2 * x + (d & 1);
+    const u32x4 v = *(const u32x4*)(gcat + q * cat_ld + g * 8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s[2 * k] += __uint_as_float(v[k] << 16);
+      s[2 * k + 1] += __uint_as_float(v[k] & 0xFFFF0000u);
+    }
+  }
+  const u32x4 zv = *(const u32x4*)(z + p * C + g * 8);
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float z0 = __uint_as_float(zv[k] << 16), z1 = __uint_as_float(zv[k] & 0xFFFF0000u);
+    o[k] = (uint32_t)f2bf(s[2 * k] * dsilu(z0)) | ((uint32_t)f2bf(s[2 * k + 1] * dsilu(z1)) << 16);
+  }
+  *(u32x4*)(gz + p * C + g * 8) = o;
+}
+
+// Gradient into an encoder output that feeds both the skip connection and the pool:
+// gz[p][c] = bf16(silu'(z[p][c]) (gskip[p][c] + gpool[p/2][c] / 4)) on the fine [H][W][C] map;
+// gskip has pixel stride skip_ld.
+__global__ void pool_bwd_silu_kernel(const bf16_t* __restrict__ gskip, int skip_ld,
+                                     const bf16_t* __restrict__ gpool, int H, int W, int C,
+                                     const bf16_t* __restrict__ z, bf16_t* __restrict__ gz) {
+  const int G = C / 8;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)H * W * G) return;
+  const int g = (int)(i % G);
+  const size_t p = i / G;
+  const int y = (int)(p / W), x = (int)(p % W);
+  const u32x4 a = *(const u32x4*)(gskip + p * skip_ld + g * 8);
+  const u32x4 b = *(const u32x4*)(gpool + ((size_t)(y / 2) * (W / 2) + x / 2) * C + g * 8);
+  const u32x4 zv = *(const u32x4*)(z + p * C + g * 8);
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float v0 = __uint_as_float(a[k] << 16) + 0.25f * __uint_as_float(b[k] << 16);
+    float v1 = __uint_as_float(a[k] & 0xFFFF0000u) + 0.25f * __uint_as_float(b[k] & 0xFFFF0000u);
+    v0 *= dsilu(__uint_as_float(zv[k] << 16));
+    v1 *= dsilu(__uint_as_float(zv[k] & 0xFFFF0000u));
+    o[k] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+  }
+  *(u32x4*)(gz + p * C + g * 8) = o;
+}
+
+// Head: out[c][p] = b[c] + sum_k Wh[c][k] d[p][k], FP32 planar output, C = d's channels (<= 64).
+__global__ void head_fwd_kernel(const bf16_t* __restrict__ d, int C, size_t npix,
+                                const float* __restrict__ Wh, float* __restrict__ out) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  float s0 = Wh[3 * C], s1 = Wh[3 * C + 1], s2 = Wh[3 * C + 2];
+  for (int k = 0; k < C; k += 8) {
+    const u32x4 v = *(const u32x4*)(d + p * C + k);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const float x = __uint_as_float(t & 1 ? (v[t / 2] & 0xFFFF0000u) : (v[t / 2] << 16));
+      s0 += Wh[k + t] * x;
+      s1 += Wh[C + k + t] * x;
+      s2 += Wh[2 * C + k + t] * x;
+    }
+  }
+  out[p] = s0;
+  out[npix + p] = s1;
+  out[2 * npix + p] = s2;
+}
+
+// Loss gradient: gout[c][p] = 2 (out - t) / (3 npix); per-block FP64 partial of sum (out - t)^2.
+__global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ out,
+                                                        const float* __restrict__ t, size_t npix,
+                                                        float* __restrict__ gout,
+                                                        double* __restrict__ part) {
+  __shared__ double sm[4];
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (p < npix) {
+    const float inv = 2.f / (3.f * (float)npix);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float d = out[c * npix + p] - t[c * npix + p];
+      s += (double)d * d;
+      gout[c * npix + p] = inv * d;
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+// Head weight gradient partials over pixel ranges: part[b][c C + k] = sum_p gout[c][p] d[p][k],
+// part[b][3 C + c] = sum_p gout[c][p].  Thread = (k, pixel group); C <= 64.
+__global__ __launch_bounds__(256) void head_wgrad_kernel(const bf16_t* __restrict__ d, int C,
+                                                         size_t npix, int per,
+                                                         const float* __restrict__ gout,
+                                                         double* __restrict__ part) {
+  __shared__ double sm[256][4];
+  const int tid = threadIdx.x, k = tid % C, grp = tid / C, ngrp = 256 / C;
+  const size_t p0 = (size_t)blockIdx.x * per, p1 = min(npix, p0 + per);
+  double s0 = 0, s1 = 0, s2 = 0, b0 = 0, b1 = 0, b2 = 0;
+  for (size_t p = p0 + grp; p < p1; p += ngrp) {
+    const float x = bf2f(d[p * C + k]);
+    const float g0 = gout[p], g1 = gout[npix + p], g2 = gout[2 * npix + p];
+    s0 += (double)g0 * x;
+    s1 += (double)g1 * x;
+    s2 += (double)g2 * x;
+    if (k == 0) {
+      b0 += g0;
+      b1 += g1;
+      b2 += g2;
+    }
+  }
+  sm[tid][0] = s0;
+  sm[tid][1] = s1;
+  sm[tid][2] = s2;
+  sm[tid][3] = 0;
+  __syncthreads();
+  if (grp == 0) {
+    for (int q = 1; q < ngrp; ++q) {
+      s0 += sm[q * C + k][0];
+      s1 += sm[q * C + k][1];
+      s2 += sm[q * C + k][2];
+    }
+    double* o = part + (size_t)blockIdx.x * (3 * C + 3);
+    o[k] = s0;
+    o[C + k] = s1;
+    o[2 * C + k] = s2;
+  }
+  __syncthreads();
+  if (k == 0) {
+    sm[grp][0] = b0;
+    sm[grp][1] = b1;
+    sm[grp][2] = b2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double c0 = 0, c1 = 0, c2 = 0;
+    for (int q = 0; q < ngrp; ++q) {
+      c0 += sm[q][0];
+      c1 += sm[q][1];
+      c2 += sm[q][2];
+    }
+    double* o = part + (size_t)blockIdx.x * (3 * C + 3);
+    o[3 * C] = c0;
+    o[3 * C + 1] = c1;
+    o[3 * C + 2] = c2;
+  }
+}
+
+// Gradient into the last decoder output: gz[p][k] = bf16(silu'(z[p][k]) sum_c gout[c][p] Wh[c][k]).
+__global__ void head_dgrad_kernel(const float* __restrict__ gout, size_t npix, int C,
+                                  const float* __restrict__ Wh, const bf16_t* __restrict__ z,
+                                  bf16_t* __restrict__ gz) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix * C) return;
+  const size_t p = i / C;
+  const int k = (int)(i % C);
+  const float g = gout[p] * Wh[k] + gout[npix + p] * Wh[C + k] + gout[2 * npix + p] * Wh[2 * C + k];
+  gz[i] = f2bf(g * dsilu(bf2f(z[i])));
+}
+
+// bfloat16 copies of one 3x3 layer's FP32 weights W[9][Cout][Cin]: wf[9][Cout][Cin_pad] (zero
+// beyond Cin) for the forward pass and, if wd is given, wd[8 - tap][ci][co] for the input
+// gradient (the same kernel run backwards: taps mirrored, channel roles swapped).
+__global__ void refresh_weights_kernel(const float* __restrict__ W, int Cout, int Cin, int Cin_pad,
+                                       bf16_t* __restrict__ wf, bf16_t* __restrict__ wd) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)9 * Cout * Cin_pad) return;
+  const int ci = (int)(i % Cin_pad);
+  const size_t r = i / Cin_pad;
+  const int co = (int)(r % Cout), tap = (int)(r / Cout);
+  if (ci >= Cin) {
+    wf[i] = 0;
+    return;
+  }
+  const bf16_t v = f2bf(W[((size_t)tap * Cout + co) * Cin + ci]);
+  wf[i] = v;
+  if (wd) wd[((size_t)(8 - tap) * Cin + ci) * Cout + co] = v;
+}
+
+// Adam (Kingma & Ba, 2015): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// theta -= lr (m / c1) / (sqrt(v / c2) + eps), g = grad * gscale; c1, c2 the bias corrections.
+__global__ void adam_kernel(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ grad, size_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2, float gscale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = grad[i] * gscale;
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Training target: t[c][p] = (later[c][p] - earlier[c][p]) / out_scale[c], c < 3.
+__global__ void make_target_kernel(const float* __restrict__ e, const float* __restrict__ l,
+                                   size_t npix, float s0, float s1, float s2,
+                                   float* __restrict__ t) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * npix) return;
+  const int c = (int)(i / npix);
+  const float s = c == 0 ? s0 : (c == 1 ? s1 : s2);
+  t[i] = (l[i] - e[i]) / s;
+}
+
+// Per-block FP64 sums of out[0][p] (the phi increment in units of out_scale[0]).
+__global__ __launch_bounds__(256) void sum_f32_kernel(const float* __restrict__ x, size_t n,
+                                                      double* __restrict__ part) {
+  __shared__ double sm[4];
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double s = i < n ? (double)x[i] : 0.0;
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+// One surrogate step applied in place: f[c] += out[c] s_c (c < 3), phi shifted by the mean
+// phi increment (sum of the partials / npix) so that sum phi is unchanged.
+__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, size_t npix,
+                             float s0, float s1, float s2, const double* __restrict__ part,
+                             int nblk) {
+  __shared__ float mean;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b];
+    mean = (float)(s / (double)npix);
+  }
+  __syncthreads();
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  f[p] += (out[p] - mean) * s0;
+  f[npix + p] += out[npix + p] * s1;
+  f[2 * npix + p] += out[2 * npix + p] * s2;
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+
+static unsigned nblocks(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Pick the tile shape of a 3x3 layer: rows per wave (2 or 1) and output-channel blocks (64 or
+// 32) so that the grid fills the 256 compute units when it can.
+static void conv_shape(int H, int W, int Cout, int* rw, int* nj) {
+  const int tx = W / 32;
+  *nj = Cout % 64 == 0 ? 2 : 1;
+  *rw = H % 8 == 0 ? 2 : 1;
+  auto blocks = [&]() { return (long)tx * (H / (4 * *rw)) * (Cout / (32 * *nj)); };
+  if (blocks() < 512 && *rw == 2) *rw = 1;
+  if (blocks() < 256 && *nj == 2) *nj = 1;
+}
+
+template <int MODE>
+static hipError_t conv_mode(ConvArgs a, hipStream_t st) {
+  int rw, nj;
+  conv_shape(a.H, a.W, a.Cout, &rw, &nj);
+  a.tiles_x = a.W / 32;
+  a.nco = a.Cout / (32 * nj);
+  const unsigned grid = (unsigned)((a.W / 32) * (a.H / (4 * rw)) * a.nco);
+  if (rw == 2 && nj == 2) hipLaunchKernelGGL((conv3x3_kernel<MODE, 2, 2>), grid, 256, 0, st, a);
+  else if (rw == 2) hipLaunchKernelGGL((conv3x3_kernel<MODE, 2, 1>), grid, 256, 0, st, a);
+  else if (nj == 2) hipLaunchKernelGGL((conv3x3_kernel<MODE, 1, 2>), grid, 256, 0, st, a);
+  else hipLaunchKernelGGL((conv3x3_kernel<MODE, 1, 1>), grid, 256, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st) {
+  if (mode == CONV_FWD) return conv_mode<CONV_FWD>(a, st);
+  if (mode == CONV_BWD_SILU) return conv_mode<CONV_BWD_SILU>(a, st);
+  return conv_mode<CONV_BWD_PLAIN>(a, st);
+}
+
+// Splits of the weight-gradient GEMM: about 1024 workgroups, partials within `max_floats`.
+void wgrad_shape(int H, int W, int Cin, int Cout, size_t max_floats, int* nsplit, int* cps) {
+  const int mj = Cout % 64 == 0 ? 2 : 1;
+  const int blocks = (Cout / (32 * mj)) * (Cin / 32);
+  const int nchunks = (H / 4) * (W / 32);
+  int ns = (1024 + blocks - 1) / blocks;
+  const size_t per = (size_t)9 * Cout * Cin;
+  ns = (int)std::min<size_t>((size_t)ns, std::max<size_t>(1, max_floats / per));
+  ns = std::max(1, std::min(ns, nchunks));
+  *cps = (nchunks + ns - 1) / ns;
+  *nsplit = (nchunks + *cps - 1) / *cps;
+}
+
+hipError_t launch_wgrad(const bf16_t* x, int x_ld, const bf16_t* g, int H, int W, int Cin, int Cout,
+                        int Cin_dst, float* part, size_t max_floats, float* grad_w, hipStream_t st) {
+  WgradArgs a;
+  a.x = x;
+  a.x_ld = x_ld;
+  a.g = g;
+  a.part = part;
+  a.H = H;
+  a.W = W;
+  a.Cin = Cin;
+  a.Cout = Cout;
+  const int mj = Cout % 64 == 0 ? 2 : 1;
+  a.nco = Cout / (32 * mj);
+  a.nci = Cin / 32;
+  a.nchunks = (H / 4) * (W / 32);
+  wgrad_shape(H, W, Cin, Cout, max_floats, &a.nsplit, &a.cps);
+  const unsigned grid = (unsigned)(a.nco * a.nci * a.nsplit);
+  if (mj == 2) hipLaunchKernelGGL((wgrad_kernel<2>), grid, 192, 0, st, a);
+  else hipLaunchKernelGGL((wgrad_kernel<1>), grid, 192, 0, st, a);
+  const size_t n = (size_t)9 * Cout * Cin_dst;
+  hipLaunchKernelGGL(reduce_splits_kernel, nblocks(n, 256), 256, 0, st, part, a.nsplit, Cin, Cin_dst,
+                     n, grad_w);
+  return hipGetLastError();
+}
+
+// Bias gradient: grad_b[c] += sum_p g[p][c]; `part` holds at least nblk * C doubles.
+int bias_blocks(size_t npix) { return (int)std::min<size_t>(512, (npix + 255) / 256); }
+hipError_t launch_bias_grad(const bf16_t* g, size_t npix, int C, double* part, float* grad_b,
+                            hipStream_t st) {
+  const int nb = bias_blocks(npix);
+  const int per = (int)((npix + nb - 1) / nb);
+  hipLaunchKernelGGL(colsum_bf16_kernel, nb, 256, 0, st, g, (int)npix, C, per, part);
+  hipLaunchKernelGGL(reduce_blocks_f64_kernel, nblocks(C, 256), 256, 0, st, part, nb, C, grad_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* f, size_t npix, const PackArgs& pa, bf16_t* x, hipStream_t st) {
+  hipLaunchKernelGGL(pack_input_kernel, nblocks(npix, 256), 256, 0, st, f, npix, pa, x);
+  return hipGetLastError();
+}
+hipError_t launch_pool(const bf16_t* in, int in_ld, int H, int W, int C, bf16_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(pool_kernel, nblocks((size_t)H / 2 * (W / 2) * (C / 8), 256), 256, 0, st, in,
+                     in_ld, H, W, C, out);
+  return hipGetLastError();
+}
+hipError_t launch_up(const bf16_t* in, int h, int w, int C, bf16_t* out, int out_ld, hipStream_t st) {
+  hipLaunchKernelGGL(up_kernel, nblocks((size_t)4 * h * w * (C / 8), 256), 256, 0, st, in, h, w, C,
+                     out, out_ld);
+  return hipGetLastError();
+}
+hipError_t launch_up_bwd_silu(const bf16_t* gcat, int cat_ld, int h, int w, int C, const bf16_t* z,
+                              bf16_t* gz, hipStream_t st) {
+  hipLaunchKernelGGL(up_bwd_silu_kernel, nblocks((size_t)h * w * (C / 8), 256), 256, 0, st, gcat,
+                     cat_ld, h, w, C, z, gz);
+  return hipGetLastError();
+}
+hipError_t launch_pool_bwd_silu(const bf16_t* gskip, int skip_ld, const bf16_t* gpool, int H, int W,
+                                int C, const bf16_t* z, bf16_t* gz, hipStream_t st) {
+  hipLaunchKernelGGL(pool_bwd_silu_kernel, nblocks((size_t)H * W * (C / 8), 256), 256, 0, st, gskip,
+                     skip_ld, gpool, H, W, C, z, gz);
+  return hipGetLastError();
+}
+hipError_t launch_head_fwd(const bf16_t* d, int C, size_t npix, const float* Wh, float* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(head_fwd_kernel, nblocks(npix, 256), 256, 0, st, d, C, npix, Wh, out);
+  return hipGetLastError();
+}
+int loss_blocks(size_t npix) { return (int)((npix + 255) / 256); }
+hipError_t launch_loss_grad(const float* out, const float* t, size_t npix, float* gout,
+                            double* part, hipStream_t st) {
+  hipLaunchKernelGGL(loss_grad_kernel, loss_blocks(npix), 256, 0, st, out, t, npix, gout, part);
+  return hipGetLastError();
+}
+hipError_t launch_head_bwd(const bf16_t* d, int C, size_t npix, const float* gout, const float* Wh,
+                           const bf16_t* z, bf16_t* gz, double* part, float* grad_head,
+                           hipStream_t st) {
+  const int nb = bias_blocks(npix);
+  const int per = (int)((npix + nb - 1) / nb);
+  hipLaunchKernelGGL(head_wgrad_kernel, nb, 256, 0, st, d, C, npix, per, gout, part);
+  hipLaunchKernelGGL(reduce_blocks_f64_kernel, nblocks(3 * C + 3, 256), 256, 0, st, part, nb,
+                     3 * C + 3, grad_head);
+  hipLaunchKernelGGL(head_dgrad_kernel, nblocks(npix * C, 256), 256, 0, st, gout, npix, C, Wh, z, gz);
+  return hipGetLastError();
+}
+hipError_t launch_refresh(const float* W, int Cout, int Cin, int Cin_pad, bf16_t* wf, bf16_t* wd,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(refresh_weights_kernel, nblocks((size_t)9 * Cout * Cin_pad, 256), 256, 0, st, W,
+                     Cout, Cin, Cin_pad, wf, wd);
+  return hipGetLastError();
+}
+hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, float gscale, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, nblocks(n, 256), 256, 0, st, th, m, v, g, n, lr, b1, b2, eps, c1,
+                     c2, gscale);
+  return hipGetLastError();
+}
+hipError_t launch_make_target(const float* e, const float* l, size_t npix, const float* s, float* t,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(make_target_kernel, nblocks(3 * npix, 256), 256, 0, st, e, l, npix, s[0], s[1],
+                     s[2], t);
+  return hipGetLastError();
+}
+hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s, double* part,
+                        hipStream_t st) {
+  const int nb = (int)((npix + 255) / 256);
+  hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out, npix, part);
+  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, npix, s[0], s[1], s[2], part, nb);
+  return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace lam

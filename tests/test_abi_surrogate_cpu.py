@@ -1,0 +1,85 @@
+"""Host-side checks of the surrogate C-ABI (no GPU): exported symbols against
+include/lam_surrogate.h, the configuration struct layout, configuration checks and the parameter
+count against the oracle's layer table."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+import paper_1102_3094_amd as lam
+from paper_1102_3094_amd import surrogate as sg
+from oracle import surrogate as U
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lam.LIB_PATH):
+        from paper_1102_3094_amd.build import build
+        build()
+    return sg.lib()
+
+
+def test_exports_match_header(L):
+    src = open(os.path.join(ROOT, "include", "lam_surrogate.h")).read()
+    names = sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(lsn_\w+)\s*\(", src, re.M)))
+    assert set(names) == set(sg.SURROGATE_EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+    src = open(os.path.join(ROOT, "include", "lam.h")).read()
+    for n in ("lam_set_fields", "lam_advance_temperature"):
+        assert re.search(rf"^int {n}\(", src, re.M) and hasattr(L, n)
+
+
+def test_config_layout():
+    code = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lam_surrogate.h"
+int main(){printf("%zu %zu %zu %zu\n", sizeof(lsn_config), offsetof(lsn_config, Tc),
+offsetof(lsn_config, in_scale), offsetof(lsn_config, out_scale)); return 0;}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        open(os.path.join(d, "t.c"), "w").write(code)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", os.path.join(d, "t"),
+                        os.path.join(d, "t.c")], check=True)
+        out = subprocess.run([os.path.join(d, "t")], capture_output=True, text=True).stdout.split()
+    got = [C.sizeof(sg.lsn_config), sg.lsn_config.Tc.offset, sg.lsn_config.in_scale.offset,
+           sg.lsn_config.out_scale.offset]
+    assert [int(v) for v in out] == got
+
+
+@pytest.mark.parametrize("levels,base", [(4, 32), (3, 32), (2, 64), (1, 32), (5, 32)])
+def test_param_count_matches_oracle_layers(L, levels, base):
+    widths = tuple(base << l for l in range(levels))
+    assert sg.param_count(height=64, width=512, levels=levels, base_width=base) == U.param_count(widths)
+
+
+@pytest.mark.parametrize("bad", [dict(levels=0), dict(levels=6), dict(base_width=48),
+                                 dict(height=60), dict(width=200), dict(Tc=0.0),
+                                 dict(out_scale=(1.0, 0.0, 1.0))])
+def test_bad_config_rejected(L, bad):
+    cfg = dict(height=64, width=256, levels=4, base_width=32)
+    cfg.update(bad)
+    c = sg.make_config(**cfg)
+    n = C.c_size_t()
+    assert L.lsn_workspace_bytes(C.byref(c), C.byref(n)) == lam.LAM_EINVAL
+    assert L.lsn_last_error(None)
+
+
+def test_workspace_sizes(L):
+    c = sg.make_config(512, 512, training=False)
+    n_inf = C.c_size_t()
+    assert L.lsn_workspace_bytes(C.byref(c), C.byref(n_inf)) == 0
+    c.training = 1
+    n_tr = C.c_size_t()
+    assert L.lsn_workspace_bytes(C.byref(c), C.byref(n_tr)) == 0
+    assert 50e6 < n_inf.value < n_tr.value < 2e9
+    # create refuses a short or misaligned workspace without touching the device
+    h = C.c_void_p()
+    assert L.lsn_create(C.byref(c), C.c_void_p(256), 1024, None, C.byref(h)) == lam.LAM_ESIZE
+    assert L.lsn_create(C.byref(c), C.c_void_p(8), n_tr.value, None, C.byref(h)) == lam.LAM_EINVAL

@@ -1,0 +1,180 @@
+"""GPU parity of the U-Net surrogate (BF16 matrix-core kernels, through the C-ABI) against the
+FP64 oracle with bfloat16 emulation at the device's storage points.
+
+Tolerances.  Oracle and device round the same values to bfloat16 (unit roundoff 2^-9); what
+differs is the FP32 accumulation order on the device (relative error ~1e-6 per sum), which
+flips the bfloat16 rounding of a small fraction of stored values by one ulp (2^-8 relative).
+Over the 14 layers such flips stay well below 1e-2 in relative L2 of the output and 3e-2 of
+the parameter gradient; the assertions use those bounds."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle import surrogate as U
+from tests._helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+CFG = dict(Tc=1.0, in_shift=(0.0, 0.0, 0.0, 1.0, 0.0), in_scale=(1.0, 20.0, 20.0, 2.0, 2.0),
+           out_scale=(0.05, 0.005, 0.005))
+
+
+def fields(H, W, seed=11):
+    u = S.uniform01(seed, 4 * H * W).reshape(4, H, W)
+    y = np.arange(H)[:, None]
+    x = np.arange(W)[None, :]
+    f = np.empty((4, H, W))
+    f[0] = 0.8 * np.sin(2 * np.pi * x / 16 + 0.3 * y) + 0.2 * (2 * u[0] - 1)
+    f[1] = 0.02 * (2 * u[1] - 1)
+    f[2] = 0.02 * (2 * u[2] - 1)
+    f[3] = 0.7 + 0.8 * np.minimum(y, H - 1 - y) / (H / 2) + 0.0 * x
+    return f.astype(np.float32).astype(np.float64)
+
+
+def packed(f, cfg=CFG):
+    sh, sc = cfg["in_shift"], cfg["in_scale"]
+    x = np.empty(f.shape[1:] + (5,))
+    for c in range(4):
+        x[..., c] = (f[c] - sh[c]) * sc[c]
+    x[..., 4] = ((f[3] - cfg["Tc"]) / cfg["Tc"] - sh[4]) * sc[4]
+    return x
+
+
+def params(widths, seed=3):
+    shapes = [(ci, co) for _, ci, co in U.layers(widths)]
+    th = S.he_uniform(seed, shapes, head=(widths[0], U.OUT_CH))
+    P = U.split(th, widths)
+    k = 0
+    for name, (Wt, b) in P.items():
+        r = S.uniform01(seed + 100, b.size + (Wt.size if name == "head" else 0), offset=k << 32)
+        b[...] = 0.1 * (2 * r[:b.size] - 1)
+        if name == "head":
+            Wt[...] = 0.3 * (2 * r[b.size:].reshape(Wt.shape) - 1)
+        k += 1
+    return th.astype(np.float32).astype(np.float64)
+
+
+def make(lam, H, W, levels=4, base=32, training=False):
+    from paper_1102_3094_amd.surrogate import Surrogate
+    return Surrogate(H, W, levels=levels, base_width=base, training=training, **CFG)
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("H,W,levels,base", [(64, 256, 4, 32), (32, 128, 3, 64), (16, 64, 2, 32)])
+def test_forward_parity(gpu, H, W, levels, base):
+    widths = tuple(base << l for l in range(levels))
+    th = params(widths)
+    f = fields(H, W)
+    net = make(gpu, H, W, levels, base).set_params(dev(th))
+    out = net.forward(dev(f)).cpu().double().numpy()
+    ref, _ = U.forward(th, packed(f), widths, q=True)
+    ref = np.moveaxis(ref, 2, 0)
+    err = rel_l2(out, ref)
+    print(f"forward rel-L2 vs bf16-emulating oracle: {err:.2e}")
+    assert np.abs(ref).max() > 0.1
+    assert err <= 1e-2
+    ref64, _ = U.forward(th, packed(f), widths)
+    assert rel_l2(out, np.moveaxis(ref64, 2, 0)) <= 5e-2
+
+
+def test_forward_is_deterministic(gpu):
+    widths = (32, 64, 128, 256)
+    net = make(gpu, 64, 256).set_params(dev(params(widths)))
+    f = dev(fields(64, 256))
+    a = net.forward(f).clone()
+    b = net.forward(f)
+    assert torch.equal(a, b)
+
+
+def test_gradient_parity(gpu):
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    th = params(widths)
+    f = fields(H, W)
+    tgt = 0.5 * (2 * S.uniform01(21, 3 * H * W).reshape(3, H, W) - 1)
+    net = make(gpu, H, W, training=True).set_params(dev(th))
+    net.zero_grad()
+    loss = net.loss_backward(dev(f), dev(tgt))
+    g = net.grads().cpu().double().numpy()
+    out, cache = U.forward(th, packed(f), widths, q=True)
+    ref_loss = U.loss(out, np.moveaxis(tgt, 0, 2))
+    ref, _ = U.backward(th, cache, out, np.moveaxis(tgt, 0, 2), widths, q=True)
+    print(f"loss {loss:.6e} vs {ref_loss:.6e}; gradient rel-L2 {rel_l2(g, ref):.2e}")
+    assert loss == pytest.approx(ref_loss, rel=2e-3)
+    assert rel_l2(g, ref) <= 3e-2
+    Pg, Pr = U.split(g, widths), U.split(ref, widths)
+    for name in Pr:
+        for a, b in zip(Pg[name], Pr[name]):
+            assert rel_l2(a, b) <= 6e-2, name
+    # the gradient accumulates over calls
+    net.loss_backward(dev(f), dev(tgt), want_loss=False)
+    assert np.array_equal(net.grads().cpu().double().numpy(), 2 * g)
+
+
+def test_adam_step(gpu):
+    H, W, widths = 32, 128, (32, 64, 128)
+    th = params(widths)
+    f = fields(H, W)
+    tgt = np.zeros((3, H, W))
+    net = make(gpu, H, W, levels=3, training=True).set_params(dev(th))
+    net.zero_grad()
+    net.loss_backward(dev(f), dev(tgt), want_loss=False)
+    g = net.grads().cpu().double().numpy()
+    net.adam(lr=1e-3, grad_scale=0.5)
+    new = net.params().cpu().double().numpy()
+    ref, _, _ = U.adam(th, np.zeros_like(th), np.zeros_like(th), 0.5 * g, 1, lr=1e-3)
+    assert np.abs(new - ref).max() <= 1e-6
+
+
+def test_training_reduces_loss(gpu):
+    H, W, widths = 32, 128, (32, 64, 128)
+    f = fields(H, W)
+    tgt = dev(0.3 * np.sin(np.linspace(0, 6, 3 * H * W)).reshape(3, H, W))
+    net = make(gpu, H, W, levels=3, training=True).set_params(dev(params(widths)))
+    ff = dev(f)
+    losses = []
+    for _ in range(40):
+        net.zero_grad()
+        losses.append(net.loss_backward(ff, tgt))
+        net.adam(lr=1e-3)
+    print("loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.3 * losses[0]
+
+
+def test_advance_and_target(gpu):
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    net = make(gpu, H, W).set_params(dev(params(widths)))
+    f = dev(fields(H, W))
+    out = net.forward(f).double()
+    g = f.clone()
+    net.advance(g)
+    torch.cuda.synchronize()
+    s = torch.tensor(CFG["out_scale"], dtype=torch.float64, device="cuda")[:, None, None]
+    inc = out * s
+    inc[0] -= inc[0].mean()
+    assert torch.equal(g[3], f[3])
+    assert torch.allclose(g[:3].double() - f[:3].double(), inc, atol=2e-6)
+    assert abs(g[0].double().sum() - f[0].double().sum()) < 1e-6 * H * W
+    t = net.make_target(f, g).double()
+    assert torch.allclose(t * s, g[:3].double() - f[:3].double(), atol=1e-6)
+
+
+def test_temperature_only_and_reanchor(gpu):
+    """lam_advance_temperature advances T as lam_step does; lam_set_fields replaces phi and keeps
+    T and the step count."""
+    p = S.model_params("c1_64sq", Tw=0.9, hydro=0)
+    phi0 = torch.tensor(S.initial_phi("c1_64sq"), dtype=torch.float32)
+    a = gpu.Sim(p).init_fields(phi0).step(37)
+    b = gpu.Sim(p).init_fields(phi0).advance_temperature(37)
+    ta, tb = a.fields()["T"], b.fields()["T"]
+    assert torch.allclose(ta, tb, rtol=0, atol=1e-6)
+    assert b.observables()["step"] == 37
+    new_phi = torch.flip(a.fields()["phi"], dims=[1]).contiguous()
+    b.set_fields(new_phi)
+    fb = b.fields()
+    assert torch.equal(fb["phi"], new_phi) and torch.equal(fb["T"], tb)
+    b.step(5)
+    assert not b.observables()["nonfinite"] and b.observables()["step"] == 42
