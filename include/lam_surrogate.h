@@ -32,6 +32,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "lam.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -81,6 +83,24 @@ int lsn_get_grads(lsn_net* net, float* d_grads);
 /* One Adam step (Kingma & Ba, 2015, with bias correction) on the accumulated gradient scaled by
  * grad_scale (for example 1/batch), then the bfloat16 weight copies are refreshed. */
 int lsn_adam(lsn_net* net, float lr, float beta1, float beta2, float eps, float grad_scale);
+
+/* Surrogate-accelerated run of the solver s (2D, walls normal to y, the network's lattice),
+ * `cycles` times: read phi, u and T of s into d_fields [4][H][W] (caller scratch), apply `calls`
+ * surrogate steps (lsn_advance), each standing for `steps_per_call` lattice steps during which T
+ * advances exactly (lam_advance_temperature), then re-anchor s on the result (lam_set_fields with
+ * n = 1) and run `anchor_steps` plain steps (lam_step).  The simulated time advances by
+ * cycles * (calls * steps_per_call + anchor_steps) steps.  Asynchronous on the network's stream,
+ * which must be the stream of s. */
+int lsn_rollout(lsn_net* net, lam_sim* s, float* d_fields, int32_t cycles, int32_t calls,
+                int32_t steps_per_call, int32_t anchor_steps);
+
+/* Tile-shape autotuner: runs the forward pass on d_fields once, then times each 3x3 layer's
+ * forward convolution (best of `reps` runs) with every tile shape its sizes allow and keeps the
+ * fastest.  The shapes change the speed only: every output is summed in the same order.
+ * Synchronises.  lsn_get_shapes writes the shape codes (10 x rows per wave + 32-channel output
+ * blocks) of the 3x3 layers in parameter order into codes[count]. */
+int lsn_tune(lsn_net* net, const float* d_fields, int32_t reps);
+int lsn_get_shapes(const lsn_net* net, int32_t* codes, int32_t count);
 
 /* Kernel timing: with timing enabled, the next forward's kernels are bracketed by HIP events
  * and lsn_forward_time returns its duration in ms (synchronises). */

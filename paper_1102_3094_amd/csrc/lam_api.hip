@@ -295,6 +295,20 @@ int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const fl
   return LAM_OK;
 }
 
+}  // extern "C"
+// Lattice of a simulation, for the surrogate driver in the same library (not part of the C-ABI).
+namespace lam {
+int sim_dims(const lam_sim* s, int* dim, int* nx, int* ny, int* walls) {
+  if (!s || !s->initialised) return LAM_EINVAL;
+  *dim = s->p.dim;
+  *nx = s->p.nx;
+  *ny = s->p.ny;
+  *walls = s->p.walls;
+  return LAM_OK;
+}
+}  // namespace lam
+extern "C" {
+
 int lam_set_fields(lam_sim* s, const float* d_phi, const float* d_u, const float* d_n) {
   if (!s || !d_phi) return fail(s, LAM_EINVAL, "null simulation or phi");
   if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");

@@ -13,6 +13,10 @@
 #include "lam_dev.hpp"
 #include "nn_host.hpp"
 
+namespace lam {
+int sim_dims(const lam_sim* s, int* dim, int* nx, int* ny, int* walls);
+}
+
 using namespace lam::nn;
 
 namespace {
@@ -25,6 +29,7 @@ struct Layer {
   size_t w_off, b_off;  // offsets in the parameter vector
   bf16_t* wf;           // [9][cout][cin_pad]
   bf16_t* wd;           // [9][cin][cout] (training; not for e1a)
+  int shape;            // tile shape of the forward convolution (0: default)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -53,8 +58,7 @@ struct lsn_net {
   std::vector<Layer> layers;
   float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
   bf16_t* x0 = nullptr;
-  bf16_t *ta[MAXL] = {}, *za[MAXL] = {}, *ze[MAXL] = {}, *enc_out[MAXL] = {}, *cat[MAXL] = {},
-         *pool[MAXL] = {};
+  bf16_t *ta[MAXL] = {}, *za[MAXL] = {}, *ze[MAXL] = {}, *enc_out[MAXL] = {}, *pool[MAXL] = {};
   int enc_ld[MAXL] = {};
   bf16_t *da[MAXL] = {}, *dd[MAXL] = {}, *zda[MAXL] = {}, *zdd[MAXL] = {};
   bf16_t *gA = nullptr, *gB = nullptr, *gcat[MAXL] = {}, *gp[MAXL] = {};
@@ -102,7 +106,7 @@ void build_layers(const lsn_config& c, std::vector<Layer>& ly, size_t* nparam, s
   int w[MAXL];
   for (int l = 0; l < L; ++l) w[l] = c.base_width << l;
   ly.clear();
-  auto add = [&](int cin, int cout, int cin_pad) { ly.push_back(Layer{cin, cout, cin_pad, 0, 0, nullptr, nullptr}); };
+  auto add = [&](int cin, int cout, int cin_pad) { ly.push_back(Layer{cin, cout, cin_pad, 0, 0, nullptr, nullptr, 0}); };
   for (int l = 0; l < L; ++l) {
     if (l == 0) add(5, w[0], IN_PAD);
     else add(w[l - 1], w[l], w[l - 1]);
@@ -154,11 +158,10 @@ size_t carve(lsn_net* n, char* base) {
       n->za[l] = cv.take<bf16_t>(P * w);
       n->ze[l] = cv.take<bf16_t>(P * w);
     }
+    n->enc_out[l] = cv.take<bf16_t>(P * w);
+    n->enc_ld[l] = w;
     if (l < L - 1) {
       const int cld = n->wid[l + 1] + w;
-      n->cat[l] = cv.take<bf16_t>(P * cld);
-      n->enc_out[l] = base ? n->cat[l] + n->wid[l + 1] : nullptr;
-      n->enc_ld[l] = cld;
       n->pool[l] = cv.take<bf16_t>(n->P[l + 1] * w);
       n->da[l] = cv.take<bf16_t>(P * w);
       n->dd[l] = cv.take<bf16_t>(P * w);
@@ -168,9 +171,6 @@ size_t carve(lsn_net* n, char* base) {
         n->gcat[l] = cv.take<bf16_t>(P * cld);
         n->gp[l] = cv.take<bf16_t>(n->P[l + 1] * w);
       }
-    } else {
-      n->enc_out[l] = cv.take<bf16_t>(P * w);
-      n->enc_ld[l] = w;
     }
   }
   n->out = cv.take<float>(3 * n->P[0]);
@@ -219,15 +219,63 @@ ConvArgs conv_args(const lsn_net* n, int lev, const bf16_t* in, int in_ld, int C
   return a;
 }
 
-// Forward pass of layer i (3x3, SiLU) from `in` into `out` (pixel stride out_ld).
-hipError_t fwd_layer(lsn_net* n, int i, const bf16_t* in, int in_ld, bf16_t* out, int out_ld,
-                     bf16_t* z) {
+// Buffers of forward layer i: input (and, for a decoder layer, the coarse map it upsamples),
+// output and pre-activation store.
+struct LayerIO {
+  const bf16_t *in, *in2;
+  int in_ld, in2_ld, c_split;
+  bf16_t *out, *z;
+  int out_ld;
+};
+
+LayerIO layer_io(const lsn_net* n, int i, bool keep) {
+  const int L = n->L;
+  LayerIO io{};
+  for (int l = 0; l < L; ++l) {
+    if (i == enc_a(l)) {
+      io.in = l == 0 ? n->x0 : n->pool[l - 1];
+      io.in_ld = l == 0 ? IN_PAD : n->wid[l - 1];
+      io.out = n->ta[l];
+      io.z = keep ? n->za[l] : nullptr;
+    } else if (i == enc_b(l)) {
+      io.in = n->ta[l];
+      io.in_ld = n->wid[l];
+      io.out = n->enc_out[l];
+      io.z = keep ? n->ze[l] : nullptr;
+    } else if (l < L - 1 && i == dec_a(L, l)) {
+      io.in = n->enc_out[l];
+      io.in_ld = n->wid[l];
+      io.in2 = l == L - 2 ? n->enc_out[L - 1] : n->dd[l + 1];
+      io.in2_ld = n->wid[l + 1];
+      io.c_split = n->wid[l + 1];
+      io.out = n->da[l];
+      io.z = keep ? n->zda[l] : nullptr;
+    } else if (l < L - 1 && i == dec_b(L, l)) {
+      io.in = n->da[l];
+      io.in_ld = n->wid[l];
+      io.out = n->dd[l];
+      io.z = keep ? n->zdd[l] : nullptr;
+    } else {
+      continue;
+    }
+    io.out_ld = n->wid[l];
+  }
+  return io;
+}
+
+// Forward pass of layer i (3x3, SiLU), with its tile shape `shape` (0: the layer's own).
+hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
   const Layer& q = n->layers[i];
-  ConvArgs a = conv_args(n, level_of(n, i), in, in_ld, q.cin_pad, q.wf, q.cout);
+  const LayerIO io = layer_io(n, i, keep);
+  ConvArgs a = conv_args(n, level_of(n, i), io.in, io.in_ld, q.cin_pad, q.wf, q.cout);
+  a.in2 = io.in2;
+  a.in2_ld = io.in2_ld;
+  a.c_split = io.c_split;
   a.bias = n->master + q.b_off;
-  a.out = out;
-  a.out_ld = out_ld;
-  a.zout = z;
+  a.out = io.out;
+  a.out_ld = io.out_ld;
+  a.zout = io.z;
+  a.shape = shape ? shape : q.shape;
   return launch_conv(CONV_FWD, a, n->st);
 }
 
@@ -242,38 +290,27 @@ hipError_t forward(lsn_net* n, const float* fields, bool keep) {
   pa.Tc = n->c.Tc;
   if ((e = launch_pack(fields, n->P[0], pa, n->x0, n->st))) return e;
   for (int l = 0; l < L; ++l) {
-    const bf16_t* in = l == 0 ? n->x0 : n->pool[l - 1];
-    const int in_ld = l == 0 ? IN_PAD : n->wid[l - 1];
-    if ((e = fwd_layer(n, enc_a(l), in, in_ld, n->ta[l], n->wid[l], keep ? n->za[l] : nullptr))) return e;
-    if ((e = fwd_layer(n, enc_b(l), n->ta[l], n->wid[l], n->enc_out[l], n->enc_ld[l], keep ? n->ze[l] : nullptr)))
-      return e;
+    if ((e = fwd_layer(n, enc_a(l), keep)) || (e = fwd_layer(n, enc_b(l), keep))) return e;
     if (l < L - 1 &&
-        (e = launch_pool(n->enc_out[l], n->enc_ld[l], n->H >> l, n->W >> l, n->wid[l], n->pool[l], n->st)))
+        (e = launch_pool(n->enc_out[l], n->wid[l], n->H >> l, n->W >> l, n->wid[l], n->pool[l], n->st)))
       return e;
   }
-  for (int l = L - 2; l >= 0; --l) {
-    const bf16_t* src = l == L - 2 ? n->enc_out[L - 1] : n->dd[l + 1];
-    if ((e = launch_up(src, n->H >> (l + 1), n->W >> (l + 1), n->wid[l + 1], n->cat[l], n->enc_ld[l], n->st)))
-      return e;
-    if ((e = fwd_layer(n, dec_a(L, l), n->cat[l], n->enc_ld[l], n->da[l], n->wid[l], keep ? n->zda[l] : nullptr)))
-      return e;
-    if ((e = fwd_layer(n, dec_b(L, l), n->da[l], n->wid[l], n->dd[l], n->wid[l], keep ? n->zdd[l] : nullptr)))
-      return e;
-  }
+  for (int l = L - 2; l >= 0; --l)
+    if ((e = fwd_layer(n, dec_a(L, l), keep)) || (e = fwd_layer(n, dec_b(L, l), keep))) return e;
   const bf16_t* top = L > 1 ? n->dd[0] : n->enc_out[0];
   return launch_head_fwd(top, n->wid[0], n->P[0], n->master + n->head_off, n->out, n->st);
 }
 
 // Backward of layer i given gz = gradient w.r.t. its pre-activation: weight and bias gradients,
 // then (if gin) the gradient w.r.t. its input, multiplied by silu'(zin) when zin is given.
-hipError_t bwd_layer(lsn_net* n, int i, const bf16_t* gz, const bf16_t* in, int in_ld, bf16_t* gin,
-                     int gin_ld, const bf16_t* zin) {
+hipError_t bwd_layer(lsn_net* n, int i, const bf16_t* gz, bf16_t* gin, int gin_ld, const bf16_t* zin) {
   hipError_t e;
   const Layer& q = n->layers[i];
   const int lev = level_of(n, i);
   const int H = n->H >> lev, W = n->W >> lev;
-  if ((e = launch_wgrad(in, in_ld, gz, H, W, q.cin_pad, q.cout, q.cin, n->part, WGRAD_MAX_FLOATS,
-                        n->grad + q.w_off, n->st)))
+  const LayerIO io = layer_io(n, i, true);
+  if ((e = launch_wgrad(io.in, io.in_ld, io.in2, io.in2_ld, io.c_split, gz, H, W, q.cin_pad, q.cout,
+                        q.cin, n->part, WGRAD_MAX_FLOATS, n->grad + q.w_off, n->st)))
     return e;
   if ((e = launch_bias_grad(gz, n->P[lev], q.cout, n->dpart + loss_blocks(n->P[0]) + 1,
                             n->grad + q.b_off, n->st)))
@@ -301,25 +338,23 @@ hipError_t backward(lsn_net* n, const float* target) {
   // gA: gradient w.r.t. the pre-activation of the top layer.
   for (int l = 0; l < L - 1; ++l) {
     const int w = n->wid[l];
-    if ((e = bwd_layer(n, dec_b(L, l), n->gA, n->da[l], w, n->gB, w, n->zda[l]))) return e;
-    if ((e = bwd_layer(n, dec_a(L, l), n->gB, n->cat[l], n->enc_ld[l], n->gcat[l], n->enc_ld[l], nullptr)))
-      return e;
+    const int cld = n->wid[l + 1] + w;
+    if ((e = bwd_layer(n, dec_b(L, l), n->gA, n->gB, w, n->zda[l]))) return e;
+    if ((e = bwd_layer(n, dec_a(L, l), n->gB, n->gcat[l], cld, nullptr))) return e;
     const bf16_t* zc = l + 1 < L - 1 ? n->zdd[l + 1] : n->ze[L - 1];
-    if ((e = launch_up_bwd_silu(n->gcat[l], n->enc_ld[l], n->H >> (l + 1), n->W >> (l + 1), n->wid[l + 1],
-                                zc, n->gA, n->st)))
+    if ((e = launch_up_bwd_silu(n->gcat[l], cld, n->H >> (l + 1), n->W >> (l + 1), n->wid[l + 1], zc,
+                                n->gA, n->st)))
       return e;
   }
   for (int l = L - 1; l >= 0; --l) {
     const int w = n->wid[l];
     if (l < L - 1 &&
-        (e = launch_pool_bwd_silu(n->gcat[l] + n->wid[l + 1], n->enc_ld[l], n->gp[l], n->H >> l, n->W >> l, w,
-                                  n->ze[l], n->gA, n->st)))
+        (e = launch_pool_bwd_silu(n->gcat[l] + n->wid[l + 1], n->wid[l + 1] + w, n->gp[l], n->H >> l,
+                                  n->W >> l, w, n->ze[l], n->gA, n->st)))
       return e;
-    if ((e = bwd_layer(n, enc_b(l), n->gA, n->ta[l], w, n->gB, w, n->za[l]))) return e;
-    const bf16_t* in = l == 0 ? n->x0 : n->pool[l - 1];
-    const int in_ld = l == 0 ? IN_PAD : n->wid[l - 1];
-    if ((e = bwd_layer(n, enc_a(l), n->gB, in, in_ld, l > 0 ? n->gp[l - 1] : nullptr,
-                       l > 0 ? n->wid[l - 1] : 0, nullptr)))
+    if ((e = bwd_layer(n, enc_b(l), n->gA, n->gB, w, n->za[l]))) return e;
+    if ((e = bwd_layer(n, enc_a(l), n->gB, l > 0 ? n->gp[l - 1] : nullptr, l > 0 ? n->wid[l - 1] : 0,
+                       nullptr)))
       return e;
   }
   return hipGetLastError();
@@ -496,6 +531,81 @@ int lsn_adam(lsn_net* n, float lr, float beta1, float beta2, float eps, float gr
                        grad_scale, n->st)))
     return hip_fail(n, e, "adam");
   if ((e = refresh(n))) return hip_fail(n, e, "weights");
+  return LAM_OK;
+}
+
+int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t calls,
+                int32_t steps_per_call, int32_t anchor_steps) {
+  if (!n || !s || !d_fields) return fail(n, LAM_EINVAL, "null argument");
+  if (cycles < 0 || calls < 0 || steps_per_call < 1 || anchor_steps < 0)
+    return fail(n, LAM_EINVAL, "bad rollout counts");
+  int dim, nx, ny, walls;
+  if (lam::sim_dims(s, &dim, &nx, &ny, &walls) != LAM_OK || dim != 2 || nx != n->W || ny != n->H)
+    return fail(n, LAM_EINVAL, "the simulation is not an initialised 2D run on the network's lattice");
+  const size_t N = n->P[0];
+  int r;
+  for (int c = 0; c < cycles; ++c) {
+    if ((r = lam_get_fields(s, d_fields, d_fields + N, nullptr, d_fields + 3 * N)))
+      return fail(n, r, std::string("solver: ") + lam_last_error(s));
+    for (int k = 0; k < calls; ++k) {
+      if ((r = lsn_advance(n, d_fields))) return r;
+      if ((r = lam_advance_temperature(s, steps_per_call)) ||
+          (r = lam_get_fields(s, nullptr, nullptr, nullptr, d_fields + 3 * N)))
+        return fail(n, r, std::string("solver: ") + lam_last_error(s));
+    }
+    if ((r = lam_set_fields(s, d_fields, d_fields + N, nullptr)) || (r = lam_step(s, anchor_steps)))
+      return fail(n, r, std::string("solver: ") + lam_last_error(s));
+  }
+  return LAM_OK;
+}
+
+int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
+  if (!n || !d_fields || reps < 1) return fail(n, LAM_EINVAL, "bad arguments");
+  hipError_t e;
+  hipEvent_t a, b;
+  if ((e = hipEventCreate(&a))) return hip_fail(n, e, "events");
+  if ((e = hipEventCreate(&b))) {
+    (void)hipEventDestroy(a);
+    return hip_fail(n, e, "events");
+  }
+  int rc = LAM_OK;
+  if ((e = forward(n, d_fields, false))) rc = hip_fail(n, e, "forward");
+  for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
+    const int lev = level_of(n, i);
+    int codes[8];
+    const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, codes, 8);
+    float best = 1e30f;
+    int pick = 0;
+    for (int k = 0; rc == LAM_OK && k < nc; ++k) {
+      float t = 1e30f;
+      for (int r = 0; r <= reps; ++r) {  // the first launch warms up
+        float ms = 0.f;
+        if ((e = hipEventRecord(a, n->st)) || (e = fwd_layer(n, i, false, codes[k])) ||
+            (e = hipEventRecord(b, n->st)) || (e = hipEventSynchronize(b)) ||
+            (e = hipEventElapsedTime(&ms, a, b))) {
+          rc = hip_fail(n, e, "tuning");
+          break;
+        }
+        if (r) t = std::min(t, ms);
+      }
+      if (t < best) {
+        best = t;
+        pick = codes[k];
+      }
+    }
+    n->layers[i].shape = pick;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+int lsn_get_shapes(const lsn_net* n, int32_t* codes, int32_t count) {
+  if (!n || !codes || count < (int)n->layers.size()) return LAM_EINVAL;
+  for (size_t i = 0; i < n->layers.size(); ++i)
+    codes[i] = n->layers[i].shape ? n->layers[i].shape
+                                   : conv_default_shape(n->H >> level_of(n, (int)i), n->W >> level_of(n, (int)i),
+                                                        n->layers[i].cout);
   return LAM_OK;
 }
 

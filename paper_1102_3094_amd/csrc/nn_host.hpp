@@ -15,6 +15,9 @@ enum { CONV_FWD = 0, CONV_BWD_SILU = 1, CONV_BWD_PLAIN = 2 };
 struct ConvArgs {
   const bf16_t* in;     // input (offset to its first channel), pixel stride in_ld
   int in_ld;
+  const bf16_t* in2;    // optional second input at half resolution, nearest-upsampled: it
+  int in2_ld;           // supplies input channels [0, c_split), `in` the channels from c_split
+  int c_split;
   const bf16_t* w;      // [9][Cout][Cin]
   const float* bias;    // CONV_FWD: [Cout]
   bf16_t* out;          // output (offset to its first channel), pixel stride out_ld
@@ -22,8 +25,13 @@ struct ConvArgs {
   bf16_t* zout;         // CONV_FWD, optional: pre-activation [pixels][Cout]
   const bf16_t* zprev;  // CONV_BWD_SILU: pre-activation [pixels][Cout]; the result is multiplied by silu'
   int H, W, Cin, Cout;
+  int shape;            // tile shape 10 RW + NJ (rows per wave, 32-channel output blocks); 0: default
   int tiles_x, nco;     // set by the launcher
 };
+
+// Tile shapes a 3x3 layer of these sizes can use (codes 10 RW + NJ), and the default pick.
+int conv_shapes(int H, int Cout, int* codes, int max_codes);
+int conv_default_shape(int H, int W, int Cout);
 
 struct PackArgs {
   float shift[5], scale[5];
@@ -32,8 +40,9 @@ struct PackArgs {
 
 hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st);
 void wgrad_shape(int H, int W, int Cin, int Cout, size_t max_floats, int* nsplit, int* cps);
-hipError_t launch_wgrad(const bf16_t* x, int x_ld, const bf16_t* g, int H, int W, int Cin, int Cout,
-                        int Cin_dst, float* part, size_t max_floats, float* grad_w, hipStream_t st);
+hipError_t launch_wgrad(const bf16_t* x, int x_ld, const bf16_t* x2, int x2_ld, int c_split,
+                        const bf16_t* g, int H, int W, int Cin, int Cout, int Cin_dst, float* part,
+                        size_t max_floats, float* grad_w, hipStream_t st);
 int bias_blocks(size_t npix);
 hipError_t launch_bias_grad(const bf16_t* g, size_t npix, int C, double* part, float* grad_b,
                             hipStream_t st);

@@ -67,8 +67,12 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const int y = y0 - 1 + pr;
         int x = x0 - 1 + col;
         x = x < 0 ? x + W : (x >= W ? x - W : x);
-        if (y >= 0 && y < H)
-          rp[i] = *(const u32x4*)(a.in + ((size_t)y * W + x) * a.in_ld + c0 + part * 8);
+        if (y >= 0 && y < H) {
+          if (c0 < a.c_split)
+            rp[i] = *(const u32x4*)(a.in2 + ((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * a.in2_ld + c0 + part * 8);
+          else
+            rp[i] = *(const u32x4*)(a.in + ((size_t)y * W + x) * a.in_ld + (c0 - a.c_split) + part * 8);
+        }
       }
     }
 #pragma unroll
@@ -173,8 +177,10 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 // (channel-major): g once, X three times (one copy per column offset dx, so that every MFMA
 // operand read is 16-byte aligned).  Partial sums go to part[split][9][Cout][Cin] (FP32).
 struct WgradArgs {
-  const bf16_t* x;  // layer input (offset to its first channel), pixel stride x_ld
-  int x_ld;
+  const bf16_t* x;  // layer input (offset to its first channel), pixel stride x_ld; channels
+  int x_ld;         // [0, c_split) come from x2 at half resolution (nearest upsampling)
+  const bf16_t* x2;
+  int x2_ld, c_split;
   const bf16_t* g;  // gradient w.r.t. the pre-activation, [pixels][Cout]
   float* part;
   int H, W, Cin, Cout;
@@ -234,7 +240,11 @@ __global__ __launch_bounds__(192) void wgrad_kernel(WgradArgs a) {
       for (int k = 0; k < 8; ++k) {
         int x = x0 + grp * 8 + k + dx - 1;
         x = x < 0 ? x + W : (x >= W ? x - W : x);
-        v[k] = (y >= 0 && y < H) ? *(const uint32_t*)(a.x + ((size_t)y * W + x) * a.x_ld + ci0 + 2 * cp) : 0u;
+        if (y < 0 || y >= H) v[k] = 0u;
+        else if (ci0 < a.c_split)
+          v[k] = *(const uint32_t*)(a.x2 + ((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * a.x2_ld + ci0 + 2 * cp);
+        else
+          v[k] = *(const uint32_t*)(a.x + ((size_t)y * W + x) * a.x_ld + (ci0 - a.c_split) + 2 * cp);
       }
       u32x4 lo, hi;
 #pragma unroll
@@ -634,28 +644,51 @@ __global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ ou
 
 static unsigned nblocks(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Pick the tile shape of a 3x3 layer: rows per wave (2 or 1) and output-channel blocks (64 or
-// 32) so that the grid fills the 256 compute units when it can.
-static void conv_shape(int H, int W, int Cout, int* rw, int* nj) {
+// Tile shapes: rows per wave RW in {1, 2, 4} (the tile has 4 RW rows, which must divide H) and
+// NJ in {1, 2} blocks of 32 output channels (NJ = 2 needs Cout % 64 == 0).
+int conv_shapes(int H, int Cout, int* codes, int max_codes) {
+  int n = 0;
+  for (int rw : {1, 2, 4})
+    for (int nj : {1, 2})
+      if (H % (4 * rw) == 0 && Cout % (32 * nj) == 0 && n < max_codes) codes[n++] = 10 * rw + nj;
+  return n;
+}
+
+// Default pick: the largest register tile (RW 2, NJ 2) unless the grid would leave compute
+// units idle, then smaller tiles.
+int conv_default_shape(int H, int W, int Cout) {
   const int tx = W / 32;
-  *nj = Cout % 64 == 0 ? 2 : 1;
-  *rw = H % 8 == 0 ? 2 : 1;
-  auto blocks = [&]() { return (long)tx * (H / (4 * *rw)) * (Cout / (32 * *nj)); };
-  if (blocks() < 512 && *rw == 2) *rw = 1;
-  if (blocks() < 256 && *nj == 2) *nj = 1;
+  int nj = Cout % 64 == 0 ? 2 : 1;
+  int rw = H % 8 == 0 ? 2 : 1;
+  auto blocks = [&]() { return (long)tx * (H / (4 * rw)) * (Cout / (32 * nj)); };
+  if (blocks() < 512 && rw == 2) rw = 1;
+  if (blocks() < 256 && nj == 2) nj = 1;
+  return 10 * rw + nj;
+}
+
+template <int MODE, int RW, int NJ>
+static void conv_launch(ConvArgs a, hipStream_t st) {
+  a.tiles_x = a.W / 32;
+  a.nco = a.Cout / (32 * NJ);
+  const unsigned grid = (unsigned)((a.W / 32) * (a.H / (4 * RW)) * a.nco);
+  hipLaunchKernelGGL((conv3x3_kernel<MODE, RW, NJ>), grid, 256, 0, st, a);
 }
 
 template <int MODE>
-static hipError_t conv_mode(ConvArgs a, hipStream_t st) {
-  int rw, nj;
-  conv_shape(a.H, a.W, a.Cout, &rw, &nj);
-  a.tiles_x = a.W / 32;
-  a.nco = a.Cout / (32 * nj);
-  const unsigned grid = (unsigned)((a.W / 32) * (a.H / (4 * rw)) * a.nco);
-  if (rw == 2 && nj == 2) hipLaunchKernelGGL((conv3x3_kernel<MODE, 2, 2>), grid, 256, 0, st, a);
-  else if (rw == 2) hipLaunchKernelGGL((conv3x3_kernel<MODE, 2, 1>), grid, 256, 0, st, a);
-  else if (nj == 2) hipLaunchKernelGGL((conv3x3_kernel<MODE, 1, 2>), grid, 256, 0, st, a);
-  else hipLaunchKernelGGL((conv3x3_kernel<MODE, 1, 1>), grid, 256, 0, st, a);
+static hipError_t conv_mode(const ConvArgs& a, hipStream_t st) {
+  const int code = a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout);
+  const int rw = code / 10, nj = code % 10;
+  if (a.H % (4 * rw) || a.Cout % (32 * nj) || a.W % 32 || a.Cin % 32 || a.c_split % 32)
+    return hipErrorInvalidValue;
+  switch (code) {
+    case 11: conv_launch<MODE, 1, 1>(a, st); break;
+    case 12: conv_launch<MODE, 1, 2>(a, st); break;
+    case 21: conv_launch<MODE, 2, 1>(a, st); break;
+    case 22: conv_launch<MODE, 2, 2>(a, st); break;
+    case 41: conv_launch<MODE, 4, 1>(a, st); break;
+    case 42: conv_launch<MODE, 4, 2>(a, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -678,11 +711,15 @@ void wgrad_shape(int H, int W, int Cin, int Cout, size_t max_floats, int* nsplit
   *nsplit = (nchunks + *cps - 1) / *cps;
 }
 
-hipError_t launch_wgrad(const bf16_t* x, int x_ld, const bf16_t* g, int H, int W, int Cin, int Cout,
-                        int Cin_dst, float* part, size_t max_floats, float* grad_w, hipStream_t st) {
+hipError_t launch_wgrad(const bf16_t* x, int x_ld, const bf16_t* x2, int x2_ld, int c_split,
+                        const bf16_t* g, int H, int W, int Cin, int Cout, int Cin_dst, float* part,
+                        size_t max_floats, float* grad_w, hipStream_t st) {
   WgradArgs a;
   a.x = x;
   a.x_ld = x_ld;
+  a.x2 = x2;
+  a.x2_ld = x2_ld;
+  a.c_split = c_split;
   a.g = g;
   a.part = part;
   a.H = H;

@@ -10,7 +10,8 @@ from . import LAM_OK, LamError, load
 SURROGATE_EXPORTS = ("lsn_param_count", "lsn_workspace_bytes", "lsn_create", "lsn_set_params",
                      "lsn_get_params", "lsn_forward", "lsn_advance", "lsn_make_target",
                      "lsn_zero_grad", "lsn_loss_backward", "lsn_get_grads", "lsn_adam",
-                     "lsn_set_timing", "lsn_forward_time", "lsn_last_error", "lsn_destroy")
+                     "lsn_rollout", "lsn_tune", "lsn_get_shapes", "lsn_set_timing", "lsn_forward_time", "lsn_last_error",
+                     "lsn_destroy")
 
 
 class lsn_config(C.Structure):
@@ -39,6 +40,9 @@ def lib():
     L.lsn_zero_grad.argtypes = [vp]
     L.lsn_loss_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
     L.lsn_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float]
+    L.lsn_rollout.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.lsn_tune.argtypes = [vp, vp, C.c_int32]
+    L.lsn_get_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     L.lsn_set_timing.argtypes = [vp, C.c_int32]
     L.lsn_forward_time.argtypes = [vp, C.POINTER(C.c_float)]
     L.lsn_last_error.argtypes = [vp]
@@ -172,6 +176,26 @@ class Surrogate:
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
         self._chk(lib().lsn_adam(self._h, lr, beta1, beta2, eps, grad_scale))
         return self
+
+    def rollout(self, sim, fields_scratch, cycles, calls=10, steps_per_call=100, anchor_steps=100):
+        """Surrogate-accelerated run of `sim` (a Sim on the same stream); fields_scratch is a
+        contiguous [4, H, W] FP32 device tensor."""
+        assert fields_scratch.is_contiguous() and fields_scratch.numel() == 4 * self.H * self.W
+        self._chk(lib().lsn_rollout(self._h, sim._h, C.c_void_p(fields_scratch.data_ptr()),
+                                    int(cycles), int(calls), int(steps_per_call), int(anchor_steps)))
+        return sim
+
+    def tune(self, fields, reps=3):
+        f = self._t(fields, (4, self.H, self.W))
+        self._chk(lib().lsn_tune(self._h, C.c_void_p(f.data_ptr()), int(reps)))
+        return self.shapes()
+
+    def shapes(self):
+        """Tile-shape codes of the 3x3 layers in parameter order."""
+        n = 4 * self.cfg.levels - 2
+        codes = (C.c_int32 * n)()
+        self._chk(lib().lsn_get_shapes(self._h, codes, n))
+        return list(codes)
 
     def set_timing(self, on=True):
         self._chk(lib().lsn_set_timing(self._h, int(bool(on))))

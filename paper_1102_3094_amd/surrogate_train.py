@@ -1,0 +1,172 @@
+"""Training and evaluation driver of the learned surrogate.  It only sequences calls of the two
+C-ABIs (solver runs and snapshots through lam.h; loss, gradients, Adam and rollouts through
+lam_surrogate.h); torch holds the snapshot tensors on the device.
+
+Workflow:
+  1. snapshots(): plain solver runs; fields (phi, u_x, u_y, T) every `every` steps from t_start.
+  2. normalisation(): input shifts/scales and output scales from the snapshot statistics.
+  3. train(): Adam on random consecutive snapshot pairs (target = normalised increment).
+  4. evaluate(): the same start state advanced by the plain solver and by the surrogate-
+     accelerated rollout (and by the rollout with a zero network, i.e. the method without the
+     learned part); S(k) peak position and height, phi error and wall-clock times.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+import synthetic as S
+from . import Ensemble, Sim
+from .surrogate import Surrogate
+
+
+def snapshots(members, phis, t_start, count, every=100, device="cuda:0"):
+    """[M, count + 1, 4, H, W] FP32 device tensor of fields at t_start + k * every."""
+    import torch
+    H, W = members[0]["ny"], members[0]["nx"]
+    out = torch.empty((len(members), count + 1, 4, H, W), dtype=torch.float32, device=device)
+    for m, (p, phi) in enumerate(zip(members, phis)):
+        sim = Sim(p, device=device).init_fields(torch.tensor(phi, dtype=torch.float32))
+        sim.step(t_start)
+        for k in range(count + 1):
+            if k:
+                sim.step(every)
+            sim.fields_into(out[m, k])
+        sim.stream.synchronize()
+        if sim.observables()["nonfinite"]:
+            raise RuntimeError(f"training run {m} became non-finite")
+    return out
+
+
+def normalisation(snaps, Tc, u_ref=0.01, a_ref=0.25):
+    """phi scaled to unit spread, velocities by a reference speed u_ref (a Mach-number scale:
+    the spread of u is dominated by the few active runs), T - Tc and a by a reference reduced
+    temperature a_ref (T may be uniform in every run); outputs scaled by the standard deviation
+    of each increment over the pairs."""
+    x = snaps[:, :-1]
+    d = snaps[:, 1:, :3] - snaps[:, :-1, :3]
+    sd = lambda t: max(float(t.double().std()), 1e-12)  # noqa: E731
+    in_scale = (1.0 / sd(x[:, :, 0]), 1.0 / u_ref, 1.0 / u_ref, 1.0 / (a_ref * Tc), 1.0 / a_ref)
+    in_shift = (0.0, 0.0, 0.0, Tc, 0.0)
+    out_scale = tuple(sd(d[:, :, c]) for c in range(3))
+    return dict(Tc=Tc, in_shift=in_shift, in_scale=in_scale, out_scale=out_scale)
+
+
+def mirror(f):
+    """The lattice mirrored across its mid-plane between the walls: y -> H - 1 - y, u_y -> -u_y
+    (a symmetry of the method with walls of equal temperature)."""
+    g = f.flip(-2)
+    g[2] = -g[2]
+    return g
+
+
+def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augment=True):
+    """Adam with a cosine learning-rate schedule; pairs drawn by SplitMix64 from `seed`; with
+    `augment`, every other draw uses the mirrored pair."""
+    M, K = snaps.shape[0], snaps.shape[1] - 1
+    draws = S.uniform01(seed, steps * batch)
+    flips = S.uniform01(seed + 7919, steps * batch)
+    losses = []
+    for it in range(steps):
+        net.zero_grad()
+        tot = 0.0
+        for b in range(batch):
+            j = int(draws[it * batch + b] * M * K)
+            m, k = j // K, j % K
+            a, c = snaps[m, k], snaps[m, k + 1]
+            if augment and flips[it * batch + b] < 0.5:
+                a, c = mirror(a), mirror(c)
+            tgt = net.make_target(a, c)
+            want = b == batch - 1 and (log is not None or it == steps - 1)
+            r = net.loss_backward(a, tgt, want_loss=want)
+            tot = r if r is not None else tot
+        rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / steps))
+        net.adam(lr=rate, grad_scale=1.0 / batch)
+        if want:
+            losses.append(tot)
+            if log is not None and (it % log == 0 or it == steps - 1):
+                print(f"  train step {it}: loss {tot:.4e}", flush=True)
+    return losses
+
+
+def validation_loss(net: Surrogate, snaps, pairs=32, seed=2):
+    """Mean loss over `pairs` consecutive snapshot pairs drawn from `seed` (no update: the
+    gradient buffer is cleared before and after)."""
+    M, K = snaps.shape[0], snaps.shape[1] - 1
+    draws = S.uniform01(seed, pairs)
+    tot = 0.0
+    for d in draws:
+        j = int(d * M * K)
+        m, k = j // K, j % K
+        net.zero_grad()
+        tot += net.loss_backward(snaps[m, k], net.make_target(snaps[m, k], snaps[m, k + 1]))
+    net.zero_grad()
+    return tot / pairs
+
+
+def peak(sim, nbins=None):
+    nb = nbins or sim.params["nx"] // 2
+    s = sim.structure_factor(nb)
+    return s["k_peak"], s["S_peak"]
+
+
+def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=100,
+             anchor_steps=100, zero_net: Surrogate | None = None, device="cuda:0"):
+    """Plain solver against the surrogate-accelerated rollout from the same state at step t0."""
+    import torch
+    total = cycles * (calls * steps_per_call + anchor_steps)
+    start = Sim(params, device=device).init_fields(torch.tensor(phi0, dtype=torch.float32)).step(t0)
+    state = start.get_state()
+    res = dict(t0=t0, steps=total, cycles=cycles, calls=calls, steps_per_call=steps_per_call,
+               anchor_steps=anchor_steps)
+
+    def fresh():
+        return Sim(params, device=device, stream=net.stream).set_state(state)
+
+    # plain method: per-step launches, and the same run replayed from a HIP graph (one-member
+    # ensemble); the faster of the two is the reference
+    plain = fresh()
+    plain.step(10)
+    plain = fresh()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain.step(total)
+    plain.stream.synchronize()
+    res["plain_s"] = time.perf_counter() - t
+    ens = Ensemble([dict(params, pop_storage=0, tile_hint=32)], device=device)
+    ens.sims[0].set_state(state)
+    ens.step(2)                    # captures the graph of a step pair
+    ens.sims[0].set_state(state)
+    ens.synchronize()
+    t = time.perf_counter()
+    ens.step(total)
+    ens.synchronize()
+    res["plain_graph_s"] = time.perf_counter() - t
+    res["plain_best_s"] = min(res["plain_s"], res["plain_graph_s"])
+    kp, sp = peak(plain)
+    res["plain_k_peak"], res["plain_S_peak"] = kp, sp
+    phi_ref = plain.fields()["phi"].double()
+
+    scratch = torch.empty((4, params["ny"], params["nx"]), dtype=torch.float32, device=device)
+    for name, n in (("surrogate", net), ("no_network", zero_net)):
+        if n is None:
+            continue
+        s = fresh()
+        n.rollout(s, scratch, 1, calls, steps_per_call, 0)   # warm-up of the launch path
+        s = fresh()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        n.rollout(s, scratch, cycles, calls, steps_per_call, anchor_steps)
+        s.stream.synchronize()
+        res[f"{name}_s"] = time.perf_counter() - t
+        kp, sp = peak(s)
+        phi = s.fields()["phi"].double()
+        res[f"{name}_k_peak"], res[f"{name}_S_peak"] = kp, sp
+        res[f"{name}_k_peak_err"] = abs(kp - res["plain_k_peak"]) / res["plain_k_peak"]
+        res[f"{name}_S_peak_err"] = abs(sp - res["plain_S_peak"]) / res["plain_S_peak"]
+        res[f"{name}_phi_rel_l2"] = float((phi - phi_ref).norm() / phi_ref.norm())
+        res[f"{name}_finite"] = not s.observables()["nonfinite"]
+        res[f"{name}_speedup"] = res["plain_best_s"] / res[f"{name}_s"]
+    return res

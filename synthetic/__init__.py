@@ -143,3 +143,28 @@ def he_uniform(seed: int, shapes, head=None) -> np.ndarray:
     if head is not None:
         parts.append(np.zeros(head[0] * head[1] + head[1]))
     return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
+def surrogate_members(seed: int = 7, count: int = 8, side: int = 512, Tw: float = 0.95,
+                      tau_range=(1.25, 2.0), instant: int = 0):
+    """Training runs of the learned surrogate: `count` 2D runs on a side x side lattice with cold
+    walls, xi log-uniform in [1e-3, 1] (the ensemble workload's distribution) and tau uniform in
+    `tau_range`, free-energy coefficients of the 64^2 workload with the walls at Tw.  The default
+    (walls at 0.95 Tc, tau in [1.25, 2]) is the part of the ensemble workload's range where the coupled
+    scheme stays bounded over tens of thousands of steps at this size.  The last `instant` runs
+    are quenched instantaneously (xi < 0: the whole lattice at Tw from the start).  Returns
+    (parameter dicts, initial phi arrays)."""
+    import math
+    u_xi = uniform01(seed, count, offset=2 << 40)
+    u_tau = uniform01(seed, count, offset=3 << 40)
+    members, phis = [], []
+    for i in range(count):
+        xi = math.exp(math.log(1e-3) + u_xi[i] * (math.log(1.0) - math.log(1e-3)))
+        if i >= count - instant:
+            xi = -1.0
+        tau = tau_range[0] + u_tau[i] * (tau_range[1] - tau_range[0])
+        p = dict(dim=2, nx=side, ny=side, nz=1, walls=1, hydro=1, tau=tau, xi=xi,
+                 **dict(_DEEP_QUENCH, Tw=Tw))
+        members.append(p)
+        phis.append(phi0((side, side), seed=seed * 1000 + i))
+    return members, phis

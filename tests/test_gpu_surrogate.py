@@ -178,3 +178,18 @@ def test_temperature_only_and_reanchor(gpu):
     assert torch.equal(fb["phi"], new_phi) and torch.equal(fb["T"], tb)
     b.step(5)
     assert not b.observables()["nonfinite"] and b.observables()["step"] == 42
+
+
+def test_tuned_shapes_give_identical_outputs(gpu):
+    """Every tile shape sums each output in the same order: tuning changes speed only."""
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    th = params(widths)
+    net = make(gpu, H, W).set_params(dev(th))
+    f = dev(fields(H, W))
+    before = net.forward(f).clone()
+    default = net.shapes()
+    tuned = net.tune(f, reps=1)
+    after = net.forward(f)
+    print("default shapes", default, "tuned", tuned)
+    assert len(tuned) == 14 and all(c in (11, 12, 21, 22, 41, 42) for c in tuned)
+    assert torch.equal(before, after)
