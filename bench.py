@@ -12,6 +12,12 @@ dominant kernel (fused force/stream/collide kernel; algorithmic bytes per site: 
 and written, 2 x 9 x 4 B, plus phi read, 4 B = 76 B in 2D; 2 x 19 x 4 + 4 = 156 B in 3D), and the
 FP64 CPU oracle's MLUPS on a bounded sample of the same workload.  --workload selects another
 named workload (for example the 256^3 D3Q19 lattice) for the same measurement.
+
+The same line carries the learned-surrogate leg ("surrogate"): a U-Net (BF16 matrix-core kernels)
+trained on the GPU on snapshots of plain 512^2 runs, then a surrogate-accelerated run (10 calls of
+100 lattice steps each, then re-anchoring and plain steps, 10 cycles) against the plain solver
+from the same state: wall-clock speed-up, error of the S(k) peak position and height, and the
+same for the run without the network (the method with the learned steps replaced by no change).
 """
 import argparse
 import hashlib
@@ -105,6 +111,83 @@ def bench_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512):
+    """Train the surrogate on plain runs and compare the accelerated run with the plain solver."""
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_1102_3094_amd import surrogate_train as ST
+    from paper_1102_3094_amd.surrogate import Surrogate
+    t_start, nsnap, every = 8000, 200, 100
+    mem, phis = S.surrogate_members(seed=7, count=members + 1, side=side, instant=members + 1)
+    t = time.perf_counter()
+    snaps = ST.snapshots(mem, phis, t_start, nsnap, every)
+    val, train = snaps[members:], snaps[:members]
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    print(f"surrogate: {members + 1} runs of {side}^2 snapshotted in {gen_s:.1f} s", file=sys.stderr,
+          flush=True)
+    norm = ST.normalisation(train, mem[0]["Tc"])
+    widths = [32 << l for l in range(4)]
+    shapes = [(5, 32), (32, 32)]
+    for l in range(1, 4):
+        shapes += [(widths[l - 1], widths[l]), (widths[l], widths[l])]
+    for l in range(2, -1, -1):
+        shapes += [(widths[l + 1] + widths[l], widths[l]), (widths[l], widths[l])]
+    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3)), dtype=torch.float32, device="cuda:0")
+    net = Surrogate(side, side, training=True, **norm).set_params(th)
+    val0 = ST.validation_loss(net, val)
+    t = time.perf_counter()
+    for rnd in range(4):
+        ST.train(net, train, train_steps // 4, batch=4, lr=5e-4 * 0.5 ** rnd, seed=10 + rnd)
+        torch.cuda.synchronize()
+        print(f"surrogate: training round {rnd + 1}/4 done ({time.perf_counter() - t:.1f} s)",
+              file=sys.stderr, flush=True)
+    train_s = time.perf_counter() - t
+    val1 = ST.validation_loss(net, val)
+    inf = Surrogate(side, side, **norm).set_params(net.params())
+    inf.tune(train[0, 0])
+    zero = Surrogate(side, side, **norm).set_params(torch.zeros_like(th))
+    f = train[0, 0].clone()
+    inf.set_timing(True)
+    ts = []
+    for _ in range(20):
+        inf.forward(f)
+        ts.append(inf.forward_time_ms())
+    inf.set_timing(False)
+    fwd_ms = float(np.median(ts))
+    flop = 0
+    for lev, (ci, co) in zip([0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0], shapes):
+        flop += 2 * 9 * max(ci, 32) * co * (side >> lev) ** 2
+    p = dict(mem[0], tau=1.5)
+    r = ST.evaluate(inf, p, S.phi0((side, side), seed=99), t0=15000, cycles=10, calls=10,
+                    steps_per_call=every, anchor_steps=anchor_steps, zero_net=zero)
+    tflops = flop / (fwd_ms * 1e-3) / 1e12
+    return {
+        "workload": f"D2Q9 {side}^2, walls at 0.95 Tc, instantaneous quench, tau in [1.25, 2]; "
+                    f"{members} training runs + 1 validation run (seed 7), held-out run seed 99 "
+                    f"tau 1.5 from step 15000",
+        "speedup_vs_plain": round(r["surrogate_speedup"], 3),
+        "plain_s": round(r["plain_best_s"], 5), "surrogate_s": round(r["surrogate_s"], 5),
+        "lattice_steps": r["steps"], "calls_per_cycle": r["calls"],
+        "steps_per_call": r["steps_per_call"], "anchor_steps": r["anchor_steps"],
+        "S_peak_position_err": round(r["surrogate_k_peak_err"], 4),
+        "S_peak_height_err": round(r["surrogate_S_peak_err"], 4),
+        "phi_rel_l2": round(r["surrogate_phi_rel_l2"], 4),
+        "no_network_S_peak_position_err": round(r["no_network_k_peak_err"], 4),
+        "no_network_S_peak_height_err": round(r["no_network_S_peak_err"], 4),
+        "no_network_phi_rel_l2": round(r["no_network_phi_rel_l2"], 4),
+        "finite": bool(r["surrogate_finite"]),
+        "validation_loss_untrained": round(val0, 4), "validation_loss_trained": round(val1, 4),
+        "snapshot_s": round(gen_s, 2), "train_s": round(train_s, 2), "train_steps": train_steps,
+        "forward_ms": round(fwd_ms, 4),
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 4),
+                     "kernel": "U-Net forward (14 conv3x3 implicit GEMMs, bf16)",
+                     "flop_per_call": flop},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +200,9 @@ def main():
                     help="the batched ensemble instead: 64 uneven 2D lattices, FP16 populations")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named workload of synthetic.WORKLOADS (default: the 1024^2 lattice)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-surrogate leg (training on the GPU, about a minute)")
+    ap.add_argument("--surrogate-train-steps", type=int, default=6000)
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 counter runs: a few steps of the workload, then one plain "
                          "device copy of 512 MiB whose counters calibrate the byte counts")
@@ -220,6 +306,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, phi0)
+    if not args.no_surrogate and dim == 2 and wl == WORKLOAD:
+        out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps)
     print(json.dumps(out), flush=True)
 
 
