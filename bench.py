@@ -188,6 +188,32 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512):
     }
 
 
+def surrogate_profile_pass(side=512, calls=50):
+    """For rocprofv3: the tuned 512^2 surrogate forward pass `calls` times (He-initialised
+    weights, fields of a plain run at step 2000)."""
+    import torch
+    import synthetic as S
+    import paper_1102_3094_amd as lam
+    from paper_1102_3094_amd.surrogate import Surrogate
+    from paper_1102_3094_amd import surrogate_train as ST
+    mem, phis = S.surrogate_members(seed=7, count=1, side=side, instant=1)
+    snaps = ST.snapshots(mem, phis, 2000, 1, 100)
+    widths = [32 << l for l in range(4)]
+    shapes = [(5, 32), (32, 32)]
+    for l in range(1, 4):
+        shapes += [(widths[l - 1], widths[l]), (widths[l], widths[l])]
+    for l in range(2, -1, -1):
+        shapes += [(widths[l + 1] + widths[l], widths[l]), (widths[l], widths[l])]
+    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3)), dtype=torch.float32, device="cuda:0")
+    net = Surrogate(side, side, **ST.normalisation(snaps, 1.0)).set_params(th)
+    codes = net.tune(snaps[0, 0])
+    out = torch.empty((3, side, side), dtype=torch.float32, device="cuda:0")
+    for _ in range(calls):
+        net.forward(snaps[0, 0], out)
+    torch.cuda.synchronize()
+    print(json.dumps({"surrogate_profile_pass": True, "calls": calls, "shapes": codes}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +229,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the GPU, about a minute)")
     ap.add_argument("--surrogate-train-steps", type=int, default=6000)
+    ap.add_argument("--surrogate-profile-pass", action="store_true",
+                    help="for rocprofv3: 50 tuned forward passes of the 512^2 surrogate")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 counter runs: a few steps of the workload, then one plain "
                          "device copy of 512 MiB whose counters calibrate the byte counts")
@@ -218,6 +246,8 @@ def main():
     import synthetic as S
 
     lam.load()
+    if args.surrogate_profile_pass:
+        return surrogate_profile_pass()
     if args.ensemble:
         return bench_ensemble(args)
     wl = args.workload
