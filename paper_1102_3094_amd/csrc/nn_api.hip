@@ -65,6 +65,7 @@ struct lsn_net {
   float *out = nullptr, *gout = nullptr, *part = nullptr;
   double* dpart = nullptr;
   int64_t adam_t = 0;
+  const float* fields = nullptr;  // fields of the forward pass in flight (fused input packing)
   bool timing = false, timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -263,6 +264,22 @@ LayerIO layer_io(const lsn_net* n, int i, bool keep) {
   return io;
 }
 
+PackArgs pack_args(const lsn_net* n) {
+  PackArgs pa;
+  for (int i = 0; i < 5; ++i) {
+    pa.shift[i] = n->c.in_shift[i];
+    pa.scale[i] = n->c.in_scale[i];
+  }
+  pa.Tc = n->c.Tc;
+  return pa;
+}
+
+int top_layer(const lsn_net* n) { return n->L > 1 ? dec_b(n->L, 0) : enc_b(0); }
+
+// Without kept activations the forward pass fuses the input packing into e1a, each 2x2 pool into
+// the next level's first convolution and (32-channel networks) the head into the last layer.
+bool fuses_head(const lsn_net* n, bool keep) { return !keep && n->wid[0] == 32; }
+
 // Forward pass of layer i (3x3, SiLU), with its tile shape `shape` (0: the layer's own).
 hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
   const Layer& q = n->layers[i];
@@ -276,27 +293,43 @@ hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
   a.out_ld = io.out_ld;
   a.zout = io.z;
   a.shape = shape ? shape : q.shape;
+  a.fuse = FUSE_NONE;
+  if (!keep) {
+    for (int l = 0; l < n->L; ++l)
+      if (i == enc_a(l)) {
+        if (l == 0) {
+          a.fuse = FUSE_FIELDS;
+          a.fields = n->fields;
+          a.pk = pack_args(n);
+        } else {
+          a.fuse = FUSE_POOL;
+          a.in = n->enc_out[l - 1];  // the pool is applied while staging
+          a.in_ld = n->wid[l - 1];
+        }
+      }
+    if (i == top_layer(n) && fuses_head(n, keep)) {
+      a.fuse = FUSE_HEAD;
+      a.head_w = n->master + n->head_off;
+      a.head_out = n->out;
+    }
+  }
   return launch_conv(CONV_FWD, a, n->st);
 }
 
 hipError_t forward(lsn_net* n, const float* fields, bool keep) {
   hipError_t e;
   const int L = n->L;
-  PackArgs pa;
-  for (int i = 0; i < 5; ++i) {
-    pa.shift[i] = n->c.in_shift[i];
-    pa.scale[i] = n->c.in_scale[i];
-  }
-  pa.Tc = n->c.Tc;
-  if ((e = launch_pack(fields, n->P[0], pa, n->x0, n->st))) return e;
+  n->fields = fields;
+  if (keep && (e = launch_pack(fields, n->P[0], pack_args(n), n->x0, n->st))) return e;
   for (int l = 0; l < L; ++l) {
     if ((e = fwd_layer(n, enc_a(l), keep)) || (e = fwd_layer(n, enc_b(l), keep))) return e;
-    if (l < L - 1 &&
+    if (keep && l < L - 1 &&
         (e = launch_pool(n->enc_out[l], n->wid[l], n->H >> l, n->W >> l, n->wid[l], n->pool[l], n->st)))
       return e;
   }
   for (int l = L - 2; l >= 0; --l)
     if ((e = fwd_layer(n, dec_a(L, l), keep)) || (e = fwd_layer(n, dec_b(L, l), keep))) return e;
+  if (fuses_head(n, keep)) return hipSuccess;
   const bf16_t* top = L > 1 ? n->dd[0] : n->enc_out[0];
   return launch_head_fwd(top, n->wid[0], n->P[0], n->master + n->head_off, n->out, n->st);
 }
@@ -453,7 +486,7 @@ int lsn_forward(lsn_net* n, const float* d_fields, float* d_out) {
   if (!n || !d_fields || !d_out) return fail(n, LAM_EINVAL, "null argument");
   hipError_t e;
   if (n->timing && (e = hipEventRecord(n->ev0, n->st))) return hip_fail(n, e, "event");
-  if ((e = forward(n, d_fields, false))) return hip_fail(n, e, "forward");
+  if ((e = forward(n, d_fields, n->c.training != 0))) return hip_fail(n, e, "forward");
   if (n->timing) {
     if ((e = hipEventRecord(n->ev1, n->st))) return hip_fail(n, e, "event");
     n->timed = true;
@@ -468,7 +501,7 @@ int lsn_advance(lsn_net* n, float* d_fields) {
   if (!n || !d_fields) return fail(n, LAM_EINVAL, "null argument");
   hipError_t e;
   if (n->timing && (e = hipEventRecord(n->ev0, n->st))) return hip_fail(n, e, "event");
-  if ((e = forward(n, d_fields, false))) return hip_fail(n, e, "forward");
+  if ((e = forward(n, d_fields, n->c.training != 0))) return hip_fail(n, e, "forward");
   if ((e = launch_apply(d_fields, n->out, n->P[0], n->c.out_scale, n->dpart, n->st)))
     return hip_fail(n, e, "apply");
   if (n->timing) {
@@ -569,7 +602,8 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
     return hip_fail(n, e, "events");
   }
   int rc = LAM_OK;
-  if ((e = forward(n, d_fields, false))) rc = hip_fail(n, e, "forward");
+  const bool keep = n->c.training != 0;
+  if ((e = forward(n, d_fields, keep))) rc = hip_fail(n, e, "forward");
   for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
     const int lev = level_of(n, i);
     int codes[8];
@@ -580,7 +614,7 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
       float t = 1e30f;
       for (int r = 0; r <= reps; ++r) {  // the first launch warms up
         float ms = 0.f;
-        if ((e = hipEventRecord(a, n->st)) || (e = fwd_layer(n, i, false, codes[k])) ||
+        if ((e = hipEventRecord(a, n->st)) || (e = fwd_layer(n, i, keep, codes[k])) ||
             (e = hipEventRecord(b, n->st)) || (e = hipEventSynchronize(b)) ||
             (e = hipEventElapsedTime(&ms, a, b))) {
           rc = hip_fail(n, e, "tuning");

@@ -11,6 +11,14 @@ namespace nn {
 typedef uint16_t bf16_t;  // bfloat16 bit pattern
 
 enum { CONV_FWD = 0, CONV_BWD_SILU = 1, CONV_BWD_PLAIN = 2 };
+// Forward-pass fusions (see conv3x3_kernel): none, input packed from the planar fields, input
+// pooled 2x2 from a map of twice the resolution, 1x1 head applied to the output.
+enum { FUSE_NONE = 0, FUSE_FIELDS = 1, FUSE_POOL = 2, FUSE_HEAD = 3 };
+
+struct PackArgs {
+  float shift[5], scale[5];
+  float Tc;
+};
 
 struct ConvArgs {
   const bf16_t* in;     // input (offset to its first channel), pixel stride in_ld
@@ -26,17 +34,17 @@ struct ConvArgs {
   const bf16_t* zprev;  // CONV_BWD_SILU: pre-activation [pixels][Cout]; the result is multiplied by silu'
   int H, W, Cin, Cout;
   int shape;            // tile shape 10 RW + NJ (rows per wave, 32-channel output blocks); 0: default
+  int fuse;             // FUSE_*; forward passes only
+  const float* fields;  // FUSE_FIELDS: planar FP32 [4][H][W] and its normalisation
+  PackArgs pk;
+  const float* head_w;  // FUSE_HEAD: head weights [3][32] then biases [3]; output [3][H][W]
+  float* head_out;
   int tiles_x, nco;     // set by the launcher
 };
 
 // Tile shapes a 3x3 layer of these sizes can use (codes 10 RW + NJ), and the default pick.
 int conv_shapes(int H, int Cout, int* codes, int max_codes);
 int conv_default_shape(int H, int W, int Cout);
-
-struct PackArgs {
-  float shift[5], scale[5];
-  float Tc;
-};
 
 hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st);
 void wgrad_shape(int H, int W, int Cin, int Cout, size_t max_floats, int* nsplit, int* cps);

@@ -41,8 +41,16 @@ constexpr int PSTR = 40;  // LDS elements per pixel (or weight row) of a 32-chan
 // patch and the 9 x 32 NJ x 32 weights are staged in LDS (the next chunk is loaded into
 // registers while the matrix cores work on the current one).  For each column offset dx and
 // 16-channel half, the wave reads RW + 2 input rows once and reuses them for the three row
-// offsets dy.
-template <int MODE, int RW, int NJ>
+// offsets dy.  The results leave through LDS (pixel-major rows) as 16-byte stores.
+//
+// FUSE (forward passes that keep no activations): FUSE_FIELDS builds the input from the planar
+// FP32 fields (the packing of pack_input_kernel; only channels 0..15 are non-zero, so one
+// 16-channel half is computed); FUSE_POOL reads a map of twice the resolution and averages 2x2
+// blocks while staging (the arithmetic of pool_kernel); FUSE_HEAD applies the 1x1 head to the
+// tile in LDS and writes the FP32 output instead of the activation (the arithmetic of
+// head_fwd_kernel; needs all output channels in one tile).  Each gives the same bits as the
+// separate kernels.
+template <int MODE, int RW, int NJ, int FUSE>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   constexpr int PR = 4 * RW + 2, PC = 34;
   constexpr int NPV = PR * PC * 4, NWV = 9 * 32 * NJ * 4;  // 16-byte vectors per chunk
@@ -68,10 +76,37 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         int x = x0 - 1 + col;
         x = x < 0 ? x + W : (x >= W ? x - W : x);
         if (y >= 0 && y < H) {
-          if (c0 < a.c_split)
+          if (FUSE == FUSE_FIELDS) {
+            if (part == 0) {
+              const size_t np = (size_t)H * W, q = (size_t)y * W + x;
+              float v[5];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) v[c] = (a.fields[c * np + q] - a.pk.shift[c]) * a.pk.scale[c];
+              v[4] = ((a.fields[3 * np + q] - a.pk.Tc) / a.pk.Tc - a.pk.shift[4]) * a.pk.scale[4];
+              rp[i][0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+              rp[i][1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+              rp[i][2] = (uint32_t)f2bf(v[4]);
+            }
+          } else if (FUSE == FUSE_POOL) {
+            float s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const size_t q = (size_t)(2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1);
+              const u32x4 v = *(const u32x4*)(a.in + q * a.in_ld + c0 + part * 8);
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                s8[2 * k] += __uint_as_float(v[k] << 16);
+                s8[2 * k + 1] += __uint_as_float(v[k] & 0xFFFF0000u);
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              rp[i][k] = (uint32_t)f2bf(0.25f * s8[2 * k]) | ((uint32_t)f2bf(0.25f * s8[2 * k + 1]) << 16);
+          } else if (c0 < a.c_split) {
             rp[i] = *(const u32x4*)(a.in2 + ((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * a.in2_ld + c0 + part * 8);
-          else
+          } else {
             rp[i] = *(const u32x4*)(a.in + ((size_t)y * W + x) * a.in_ld + (c0 - a.c_split) + part * 8);
+          }
         }
       }
     }
@@ -120,7 +155,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
+      for (int kk = 0; kk < (FUSE == FUSE_FIELDS ? 1 : 2); ++kk) {
         bf16x8 A[RW + 2];
 #pragma unroll
         for (int r = 0; r < RW + 2; ++r)
@@ -143,28 +178,63 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   }
 
   // D layout of the 32x32 MFMA: lane holds column m (output channel) and rows
-  // 8 (q / 4) + 4 kh + (q % 4), q = 0..15 (pixel within the 32-column row).
+  // 8 (q / 4) + 4 kh + (q % 4), q = 0..15 (pixel within the 32-column row).  Per 32-channel
+  // block j (and per stored quantity: the output, then the forward pass's pre-activation) the
+  // wave writes its values into LDS as [pixel][channel] and the workgroup stores 16-byte pieces.
+  constexpr int TP = 4 * RW * 32;  // pixels of the tile
+  static_assert(TP * PSTR <= PR * PC * PSTR, "epilogue tile exceeds the patch buffer");
+  bf16_t* so = sp;
 #pragma unroll
-  for (int r = 0; r < RW; ++r) {
-    const int y = y0 + wave * RW + r;
+  for (int j = 0; j < NJ; ++j) {
+    const int co = co0 + j * 32 + m;
+    const float bco = MODE == CONV_FWD ? a.bias[co] : 0.f;
+    const int passes = (MODE == CONV_FWD && a.zout) ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int co = co0 + j * 32 + m;
-      const float bco = MODE == CONV_FWD ? a.bias[co] : 0.f;
+      for (int r = 0; r < RW; ++r) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int x = x0 + 8 * (q >> 2) + 4 * kh + (q & 3);
-        const size_t p = (size_t)y * W + x;
-        const float v = acc[r][j][q];
-        if (MODE == CONV_FWD) {
-          const float z = v + bco;
-          a.out[p * a.out_ld + co] = f2bf(z * sigm(z));
-          if (a.zout) a.zout[p * a.Cout + co] = f2bf(z);
-        } else if (MODE == CONV_BWD_SILU) {
-          a.out[p * a.out_ld + co] = f2bf(v * dsilu(bf2f(a.zprev[p * a.Cout + co])));
-        } else {
-          a.out[p * a.out_ld + co] = f2bf(v);
+        for (int q = 0; q < 16; ++q) {
+          const int pl = (wave * RW + r) * 32 + 8 * (q >> 2) + 4 * kh + (q & 3);
+          const float v = acc[r][j][q];
+          float o;
+          if (MODE == CONV_FWD) {
+            const float z = v + bco;
+            o = pass == 0 ? z * sigm(z) : z;
+          } else if (MODE == CONV_BWD_SILU) {
+            const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
+            o = v * dsilu(bf2f(a.zprev[p * a.Cout + co]));
+          } else {
+            o = v;
+          }
+          so[pl * PSTR + m] = f2bf(o);
         }
+      }
+      __syncthreads();
+      if (FUSE == FUSE_HEAD) {
+        // 1x1 head over the Cout = 32 channels of each pixel (launched with NJ = 1 only)
+        const size_t np = (size_t)H * W;
+        for (int pl = tid; pl < TP; pl += 256) {
+          float s0 = a.head_w[96], s1 = a.head_w[97], s2 = a.head_w[98];
+#pragma unroll
+          for (int k = 0; k < 32; ++k) {
+            const float x = bf2f(so[pl * PSTR + k]);
+            s0 += a.head_w[k] * x;
+            s1 += a.head_w[32 + k] * x;
+            s2 += a.head_w[64 + k] * x;
+          }
+          const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
+          a.head_out[p] = s0;
+          a.head_out[np + p] = s1;
+          a.head_out[2 * np + p] = s2;
+        }
+        continue;
+      }
+      for (int t = tid; t < TP * 4; t += 256) {
+        const int pl = t >> 2, part = t & 3;
+        const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
+        bf16_t* dst = pass == 0 ? a.out + p * a.out_ld : a.zout + p * a.Cout;
+        *(u32x4*)(dst + co0 + j * 32 + part * 8) = *(const u32x4*)(so + pl * PSTR + part * 8);
       }
     }
   }
@@ -666,36 +736,55 @@ int conv_default_shape(int H, int W, int Cout) {
   return 10 * rw + nj;
 }
 
-template <int MODE, int RW, int NJ>
+template <int MODE, int RW, int NJ, int FUSE>
 static void conv_launch(ConvArgs a, hipStream_t st) {
   a.tiles_x = a.W / 32;
   a.nco = a.Cout / (32 * NJ);
   const unsigned grid = (unsigned)((a.W / 32) * (a.H / (4 * RW)) * a.nco);
-  hipLaunchKernelGGL((conv3x3_kernel<MODE, RW, NJ>), grid, 256, 0, st, a);
+  hipLaunchKernelGGL((conv3x3_kernel<MODE, RW, NJ, FUSE>), grid, 256, 0, st, a);
 }
 
-template <int MODE>
-static hipError_t conv_mode(const ConvArgs& a, hipStream_t st) {
-  const int code = a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout);
-  const int rw = code / 10, nj = code % 10;
-  if (a.H % (4 * rw) || a.Cout % (32 * nj) || a.W % 32 || a.Cin % 32 || a.c_split % 32)
-    return hipErrorInvalidValue;
+template <int MODE, int FUSE>
+static hipError_t conv_shape_dispatch(const ConvArgs& a, int code, hipStream_t st) {
   switch (code) {
-    case 11: conv_launch<MODE, 1, 1>(a, st); break;
-    case 12: conv_launch<MODE, 1, 2>(a, st); break;
-    case 21: conv_launch<MODE, 2, 1>(a, st); break;
-    case 22: conv_launch<MODE, 2, 2>(a, st); break;
-    case 41: conv_launch<MODE, 4, 1>(a, st); break;
-    case 42: conv_launch<MODE, 4, 2>(a, st); break;
+    case 11: conv_launch<MODE, 1, 1, FUSE>(a, st); break;
+    case 12: conv_launch<MODE, 1, 2, FUSE>(a, st); break;
+    case 21: conv_launch<MODE, 2, 1, FUSE>(a, st); break;
+    case 22: conv_launch<MODE, 2, 2, FUSE>(a, st); break;
+    case 41: conv_launch<MODE, 4, 1, FUSE>(a, st); break;
+    case 42: conv_launch<MODE, 4, 2, FUSE>(a, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int MODE>
+static hipError_t conv_mode(const ConvArgs& a, hipStream_t st) {
+  int code = a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout);
+  if (a.fuse == FUSE_HEAD) code = (code / 10) * 10 + 1;  // all 32 channels in one tile
+  const int rw = code / 10, nj = code % 10;
+  if (a.H % (4 * rw) || a.Cout % (32 * nj) || a.W % 32 || a.Cin % 32 || a.c_split % 32)
+    return hipErrorInvalidValue;
+  if (MODE != CONV_FWD && a.fuse != FUSE_NONE) return hipErrorInvalidValue;
+  if ((a.fuse == FUSE_FIELDS && a.Cin != 32) || (a.fuse == FUSE_HEAD && a.Cout != 32) ||
+      (a.fuse != FUSE_NONE && a.c_split))
+    return hipErrorInvalidValue;
+  switch (a.fuse) {
+    case FUSE_NONE: return conv_shape_dispatch<MODE, FUSE_NONE>(a, code, st);
+    case FUSE_FIELDS: return conv_shape_dispatch<MODE, FUSE_FIELDS>(a, code, st);
+    case FUSE_POOL: return conv_shape_dispatch<MODE, FUSE_POOL>(a, code, st);
+    case FUSE_HEAD: return conv_shape_dispatch<MODE, FUSE_HEAD>(a, code, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st) {
   if (mode == CONV_FWD) return conv_mode<CONV_FWD>(a, st);
-  if (mode == CONV_BWD_SILU) return conv_mode<CONV_BWD_SILU>(a, st);
-  return conv_mode<CONV_BWD_PLAIN>(a, st);
+  if (a.fuse != FUSE_NONE) return hipErrorInvalidValue;
+  if (mode == CONV_BWD_SILU) return conv_shape_dispatch<CONV_BWD_SILU, FUSE_NONE>(
+      a, a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout), st);
+  return conv_shape_dispatch<CONV_BWD_PLAIN, FUSE_NONE>(
+      a, a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout), st);
 }
 
 // Splits of the weight-gradient GEMM: about 1024 workgroups, partials within `max_floats`.

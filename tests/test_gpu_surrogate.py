@@ -193,3 +193,15 @@ def test_tuned_shapes_give_identical_outputs(gpu):
     print("default shapes", default, "tuned", tuned)
     assert len(tuned) == 14 and all(c in (11, 12, 21, 22, 41, 42) for c in tuned)
     assert torch.equal(before, after)
+
+
+@pytest.mark.parametrize("H,W,levels,base", [(64, 256, 4, 32), (32, 128, 3, 64)])
+def test_fused_inference_equals_unfused(gpu, H, W, levels, base):
+    """An inference network fuses the input packing, the pools and (32 channels) the head into
+    the convolutions; a training network runs them as separate kernels.  Same bits."""
+    widths = tuple(base << l for l in range(levels))
+    th = dev(params(widths))
+    f = dev(fields(H, W))
+    a = make(gpu, H, W, levels, base).set_params(th).forward(f)
+    b = make(gpu, H, W, levels, base, training=True).set_params(th).forward(f)
+    assert torch.equal(a, b)
