@@ -137,6 +137,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512):
     th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3)), dtype=torch.float32, device="cuda:0")
     net = Surrogate(side, side, training=True, **norm).set_params(th)
     val0 = ST.validation_loss(net, val)
+    stream = torch.cuda.Stream()  # a capturable stream: the rollout replays its step graph
     t = time.perf_counter()
     for rnd in range(4):
         ST.train(net, train, train_steps // 4, batch=4, lr=5e-4 * 0.5 ** rnd, seed=10 + rnd)
@@ -145,9 +146,9 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512):
               file=sys.stderr, flush=True)
     train_s = time.perf_counter() - t
     val1 = ST.validation_loss(net, val)
-    inf = Surrogate(side, side, **norm).set_params(net.params())
+    inf = Surrogate(side, side, stream=stream, **norm).set_params(net.params())
     inf.tune(train[0, 0])
-    zero = Surrogate(side, side, **norm).set_params(torch.zeros_like(th))
+    zero = Surrogate(side, side, stream=stream, **norm).set_params(torch.zeros_like(th))
     f = train[0, 0].clone()
     inf.set_timing(True)
     ts = []

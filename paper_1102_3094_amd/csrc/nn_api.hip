@@ -15,6 +15,7 @@
 
 namespace lam {
 int sim_dims(const lam_sim* s, int* dim, int* nx, int* ny, int* walls);
+bool sim_temperature_frozen(const lam_sim* s);
 }
 
 using namespace lam::nn;
@@ -66,6 +67,10 @@ struct lsn_net {
   double* dpart = nullptr;
   int64_t adam_t = 0;
   const float* fields = nullptr;  // fields of the forward pass in flight (fused input packing)
+  // HIP graph of one surrogate step (forward + apply) on a given fields buffer
+  hipGraphExec_t step_graph = nullptr;
+  const float* step_graph_fields = nullptr;
+  uint64_t shapes_version = 0, step_graph_version = 0;
   bool timing = false, timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -567,6 +572,45 @@ int lsn_adam(lsn_net* n, float lr, float beta1, float beta2, float eps, float gr
   return LAM_OK;
 }
 
+namespace {
+// One surrogate step on d_fields, replayed from a HIP graph when the stream can be captured (the
+// graph is rebuilt when the buffer or the tile shapes change); otherwise launched directly.  Both
+// run the same kernels on the same data.
+int advance_step(lsn_net* n, float* d_fields) {
+  if (!n->timing && !n->c.training) {
+    if (n->step_graph && (n->step_graph_fields != d_fields || n->step_graph_version != n->shapes_version)) {
+      (void)hipGraphExecDestroy(n->step_graph);
+      n->step_graph = nullptr;
+    }
+    if (!n->step_graph) {
+      hipGraph_t g;
+      hipError_t r = hipStreamBeginCapture(n->st, hipStreamCaptureModeThreadLocal);
+      if (r == hipSuccess) {
+        hipError_t r1 = forward(n, d_fields, false);
+        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->P[0], n->c.out_scale, n->dpart, n->st);
+        hipError_t r2 = hipStreamEndCapture(n->st, &g);
+        if (r1 == hipSuccess && r2 == hipSuccess) {
+          hipGraphExec_t ex;
+          if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+            n->step_graph = ex;
+            n->step_graph_fields = d_fields;
+            n->step_graph_version = n->shapes_version;
+          }
+        }
+        if (r2 == hipSuccess) (void)hipGraphDestroy(g);
+        if (r1 != hipSuccess) return hip_fail(n, r1, "capture");
+      }
+      (void)hipGetLastError();  // a stream that cannot be captured leaves the direct path
+    }
+    if (n->step_graph) {
+      hipError_t e = hipGraphLaunch(n->step_graph, n->st);
+      return e ? hip_fail(n, e, "graph launch") : LAM_OK;
+    }
+  }
+  return lsn_advance(n, d_fields);
+}
+}  // namespace
+
 int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t calls,
                 int32_t steps_per_call, int32_t anchor_steps) {
   if (!n || !s || !d_fields) return fail(n, LAM_EINVAL, "null argument");
@@ -576,14 +620,16 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
   if (lam::sim_dims(s, &dim, &nx, &ny, &walls) != LAM_OK || dim != 2 || nx != n->W || ny != n->H)
     return fail(n, LAM_EINVAL, "the simulation is not an initialised 2D run on the network's lattice");
   const size_t N = n->P[0];
+  const bool frozen = lam::sim_temperature_frozen(s);
   int r;
   for (int c = 0; c < cycles; ++c) {
     if ((r = lam_get_fields(s, d_fields, d_fields + N, nullptr, d_fields + 3 * N)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
     for (int k = 0; k < calls; ++k) {
-      if ((r = lsn_advance(n, d_fields))) return r;
-      if ((r = lam_advance_temperature(s, steps_per_call)) ||
-          (r = lam_get_fields(s, nullptr, nullptr, nullptr, d_fields + 3 * N)))
+      if ((r = advance_step(n, d_fields))) return r;
+      if ((r = lam_advance_temperature(s, steps_per_call)))
+        return fail(n, r, std::string("solver: ") + lam_last_error(s));
+      if (!frozen && (r = lam_get_fields(s, nullptr, nullptr, nullptr, d_fields + 3 * N)))
         return fail(n, r, std::string("solver: ") + lam_last_error(s));
     }
     if ((r = lam_set_fields(s, d_fields, d_fields + N, nullptr)) || (r = lam_step(s, anchor_steps)))
@@ -629,6 +675,7 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
     }
     n->layers[i].shape = pick;
   }
+  n->shapes_version++;
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return rc;
@@ -667,6 +714,7 @@ const char* lsn_last_error(const lsn_net* n) { return n ? n->err.c_str() : g_nn_
 
 void lsn_destroy(lsn_net* n) {
   if (!n) return;
+  if (n->step_graph) (void)hipGraphExecDestroy(n->step_graph);
   if (n->ev0) (void)hipEventDestroy(n->ev0);
   if (n->ev1) (void)hipEventDestroy(n->ev1);
   delete n;

@@ -690,21 +690,29 @@ __global__ __launch_bounds__(256) void sum_f32_kernel(const float* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
 }
 
-// One surrogate step applied in place: f[c] += out[c] s_c (c < 3), phi shifted by the mean
-// phi increment (sum of the partials / npix) so that sum phi is unchanged.
-__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, size_t npix,
-                             float s0, float s1, float s2, const double* __restrict__ part,
-                             int nblk) {
-  __shared__ float mean;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b];
-    mean = (float)(s / (double)npix);
-  }
+// Mean of the phi increment: fixed-order tree over the per-block sums (one workgroup), written to
+// part[nblk].
+__global__ __launch_bounds__(256) void mean_kernel(double* __restrict__ part, int nblk, size_t npix) {
+  __shared__ double sm[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[b];
+  sm[threadIdx.x] = s;
   __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[nblk] = sm[0] / (double)npix;
+}
+
+// One surrogate step applied in place: f[c] += out[c] s_c (c < 3), phi shifted by the mean phi
+// increment so that sum phi is unchanged.
+__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, size_t npix,
+                             float s0, float s1, float s2, const double* __restrict__ mean) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  f[p] += (out[p] - mean) * s0;
+  const float mu = (float)*mean;
+  f[p] += (out[p] - mu) * s0;
   f[npix + p] += out[npix + p] * s1;
   f[2 * npix + p] += out[2 * npix + p] * s2;
 }
@@ -910,7 +918,9 @@ hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s,
                         hipStream_t st) {
   const int nb = (int)((npix + 255) / 256);
   hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out, npix, part);
-  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, npix, s[0], s[1], s[2], part, nb);
+  hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part, nb, npix);
+  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, npix, s[0], s[1], s[2],
+                     (const double*)(part + nb));
   return hipGetLastError();
 }
 

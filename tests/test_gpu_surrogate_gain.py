@@ -32,8 +32,9 @@ def test_trained_network_beats_no_network(gpu):
     for rnd in range(3):
         ST.train(net, train, 500, batch=2, lr=5e-4 * 0.5 ** rnd, seed=20 + rnd)
     v1 = ST.validation_loss(net, val)
-    inf = Surrogate(side, side, **norm).set_params(net.params())
-    zero = Surrogate(side, side, **norm).set_params(torch.zeros_like(th))
+    st = torch.cuda.Stream()
+    inf = Surrogate(side, side, stream=st, **norm).set_params(net.params())
+    zero = Surrogate(side, side, stream=st, **norm).set_params(torch.zeros_like(th))
     r = ST.evaluate(inf, dict(mem[0], tau=1.5), S.phi0((side, side), seed=99), t0=12000,
                     cycles=4, calls=10, steps_per_call=100, anchor_steps=50, zero_net=zero)
     print({k: r[k] for k in r if "err" in k or "l2" in k or "speedup" in k}, "val", v0, "->", v1)
