@@ -41,7 +41,7 @@ template <typename ST>
 __device__ __forceinline__ void pull9(const ST* __restrict__ G, size_t N, int nx, int ny,
                                       int walls, int x, int y, float g[9]) {
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  auto ld = [&](int q, int yy, int xx) { return to_f32(G[(size_t)q * N + (size_t)yy * nx + xx]); };
+  auto ld = [&](int q, int yy, int xx) { return to_f32(ld_nt(&G[(size_t)q * N + (size_t)yy * nx + xx])); };
   g[0] = ld(0, y, x);
   g[1] = ld(1, y, xm);
   g[3] = ld(3, y, xp);
@@ -213,15 +213,15 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
         return gq + om * (geq - gq) + frc;
       };
       const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
-      gout[0 * N + s] = from_f32<ST>(coll(g0, w0, 0.f, 0.f));
-      gout[1 * N + s] = from_f32<ST>(coll(g1, w1, ux, Fx));
-      gout[2 * N + s] = from_f32<ST>(coll(g2, w1, uy, Fy));
-      gout[3 * N + s] = from_f32<ST>(coll(g3, w1, -ux, -Fx));
-      gout[4 * N + s] = from_f32<ST>(coll(g4, w1, -uy, -Fy));
-      gout[5 * N + s] = from_f32<ST>(coll(g5, w2, ux + uy, Fx + Fy));
-      gout[6 * N + s] = from_f32<ST>(coll(g6, w2, uy - ux, Fy - Fx));
-      gout[7 * N + s] = from_f32<ST>(coll(g7, w2, -ux - uy, -Fx - Fy));
-      gout[8 * N + s] = from_f32<ST>(coll(g8, w2, ux - uy, Fx - Fy));
+      st_nt(&gout[0 * N + s], from_f32<ST>(coll(g0, w0, 0.f, 0.f)));
+      st_nt(&gout[1 * N + s], from_f32<ST>(coll(g1, w1, ux, Fx)));
+      st_nt(&gout[2 * N + s], from_f32<ST>(coll(g2, w1, uy, Fy)));
+      st_nt(&gout[3 * N + s], from_f32<ST>(coll(g3, w1, -ux, -Fx)));
+      st_nt(&gout[4 * N + s], from_f32<ST>(coll(g4, w1, -uy, -Fy)));
+      st_nt(&gout[5 * N + s], from_f32<ST>(coll(g5, w2, ux + uy, Fx + Fy)));
+      st_nt(&gout[6 * N + s], from_f32<ST>(coll(g6, w2, uy - ux, Fy - Fx)));
+      st_nt(&gout[7 * N + s], from_f32<ST>(coll(g7, w2, -ux - uy, -Fx - Fy)));
+      st_nt(&gout[8 * N + s], from_f32<ST>(coll(g8, w2, ux - uy, Fx - Fy)));
       uout[s] = ux;
       uout[N + s] = uy;
     } else if (MODE == MODE_FIELDS) {

@@ -36,6 +36,16 @@ __device__ __forceinline__ float from_f32<float>(float v) { return v; }
 template <>
 __device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half_rn(v); }
 
+// Streaming (non-temporal) access to the population fields, which are not re-read within a step.
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ __half ld_nt(const __half* p) {
+  return __ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p));
+}
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(__half* p, __half v) {
+  __builtin_nontemporal_store(__half_as_ushort(v), (unsigned short*)p);
+}
+
 // One member of an ensemble as the ensemble kernels see it: its parameters, its device buffers
 // (populations by step parity, phi by step parity, phi scratch, u, T by parity + scratch) and the
 // index of its first tile in the concatenated tile list.
