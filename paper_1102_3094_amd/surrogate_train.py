@@ -62,22 +62,41 @@ def mirror(f):
     return g
 
 
-def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augment=True):
+def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augment=True,
+          noise=0.0, pushforward=0.0):
     """Adam with a cosine learning-rate schedule; pairs drawn by SplitMix64 from `seed`; with
-    `augment`, every other draw uses the mirrored pair."""
+    `augment`, every other draw uses the mirrored pair.  With noise > 0 the input phi is
+    perturbed by uniform noise of that amplitude (relative to the spread of phi in the pair) and
+    the target is the step from the perturbed state to the true later state, so that the network
+    learns to pull a drifted state back (the error it meets in a rollout).  With pushforward > 0
+    that fraction of the draws starts from the network's own one-step prediction of a snapshot
+    and targets the true state one step later (pushforward training, Brandstetter, Worrall &
+    Welling, 2022: the rollout's own error distribution, without a gradient through the first
+    step)."""
     M, K = snaps.shape[0], snaps.shape[1] - 1
     draws = S.uniform01(seed, steps * batch)
     flips = S.uniform01(seed + 7919, steps * batch)
+    pushes = S.uniform01(seed + 104729, steps * batch)
     losses = []
     for it in range(steps):
         net.zero_grad()
         tot = 0.0
         for b in range(batch):
-            j = int(draws[it * batch + b] * M * K)
-            m, k = j // K, j % K
-            a, c = snaps[m, k], snaps[m, k + 1]
+            push = pushforward > 0.0 and K > 1 and pushes[it * batch + b] < pushforward
+            KK = K - 1 if push else K
+            j = int(draws[it * batch + b] * M * KK)
+            m, k = j // KK, j % KK
+            a, c = snaps[m, k], snaps[m, k + (2 if push else 1)]
             if augment and flips[it * batch + b] < 0.5:
                 a, c = mirror(a), mirror(c)
+            if push:
+                a = net.advance(a.clone())
+            if noise > 0.0:
+                import torch
+                a = a.clone()
+                gen = torch.Generator(device=a.device).manual_seed(int(seed) * 1000003 + it * batch + b)
+                r = torch.rand(a.shape[1:], generator=gen, device=a.device)
+                a[0] += (noise * float(a[0].std())) * (2.0 * r - 1.0)
             tgt = net.make_target(a, c)
             want = b == batch - 1 and (log is not None or it == steps - 1)
             r = net.loss_backward(a, tgt, want_loss=want)
@@ -161,12 +180,18 @@ def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=
         n.rollout(s, scratch, cycles, calls, steps_per_call, anchor_steps)
         s.stream.synchronize()
         res[f"{name}_s"] = time.perf_counter() - t
-        kp, sp = peak(s)
-        phi = s.fields()["phi"].double()
-        res[f"{name}_k_peak"], res[f"{name}_S_peak"] = kp, sp
-        res[f"{name}_k_peak_err"] = abs(kp - res["plain_k_peak"]) / res["plain_k_peak"]
-        res[f"{name}_S_peak_err"] = abs(sp - res["plain_S_peak"]) / res["plain_S_peak"]
-        res[f"{name}_phi_rel_l2"] = float((phi - phi_ref).norm() / phi_ref.norm())
-        res[f"{name}_finite"] = not s.observables()["nonfinite"]
+        finite = not s.observables()["nonfinite"]
+        res[f"{name}_finite"] = finite
+        if finite:
+            kp, sp = peak(s)
+            phi = s.fields()["phi"].double()
+            res[f"{name}_k_peak"], res[f"{name}_S_peak"] = kp, sp
+            res[f"{name}_k_peak_err"] = abs(kp - res["plain_k_peak"]) / res["plain_k_peak"]
+            res[f"{name}_S_peak_err"] = abs(sp - res["plain_S_peak"]) / res["plain_S_peak"]
+            res[f"{name}_phi_rel_l2"] = float((phi - phi_ref).norm() / phi_ref.norm())
+        else:  # a run that blew up counts as a 100 % error
+            res[f"{name}_k_peak"] = res[f"{name}_S_peak"] = None
+            res[f"{name}_k_peak_err"] = res[f"{name}_S_peak_err"] = 1.0
+            res[f"{name}_phi_rel_l2"] = None
         res[f"{name}_speedup"] = res["plain_best_s"] / res[f"{name}_s"]
     return res
