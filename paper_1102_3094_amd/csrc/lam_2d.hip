@@ -26,14 +26,20 @@ enum { MODE_STEP = 0, MODE_OBS = 1, MODE_FIELDS = 2 };
 
 template <int TY>
 struct Lb2dSmem {
+  static constexpr int NWMAX = TY / 2;  // waves per workgroup with 2 sites per thread
   float phi[TY + 6][TX + 6];
   float L[TY + 4][TX + 4];
   float P[3][TY + 2][TX + 2];  // Pxx, Pyy, Pxy (or mu in P[0] for the -phi grad mu form)
   float a[TY + 6];
   int rowoff[TY + 6];  // y * nx of each tile row (wrapped or reflected)
   int colx[TX + 6];    // x of each tile column (wrapped)
-  double red[TY / 4][R_N];
+  double red[NWMAX > 0 ? NWMAX : 1][R_N];
 };
+
+// Sites per thread of the D2Q9 step kernel (each thread owns SPT sites of one tile column): 2,
+// measured 1-2 % faster than 4 at 1024^2 and 4096^2, or 4 where 2 would exceed 1024 threads.
+constexpr int lb2d_spt(int ty) { return 64 * ty / 2 > 1024 ? 4 : 2; }
+constexpr int lb2d_threads(int ty) { return 64 * ty / lb2d_spt(ty); }
 
 // Pull of the 9 populations of site (x, y): f_q(x) = f*_q(x - e_q); across a wall the opposite
 // population of x itself (halfway bounce-back).
@@ -67,26 +73,26 @@ __device__ __forceinline__ void pull9(const ST* __restrict__ G, size_t N, int nx
   }
 }
 
-// One workgroup of 16*TY threads (TY/4 waves) per 64 x TY tile; every thread owns the 4 sites
-// (tx, ty + k TY/4), k < 4, of one column.  ST is the storage type of the populations (float or
-// __half); all arithmetic is FP32.
-template <int TY, int MODE, typename ST>
+// One workgroup of 64*TY/SPT threads (TY/SPT waves) per 64 x TY tile; every thread owns the SPT
+// sites (tx, ty + k TY/SPT), k < SPT, of one column.  ST is the storage type of the populations
+// (float or __half); all arithmetic is FP32.
+template <int TY, int MODE, typename ST, int SPT = lb2d_spt(TY)>
 __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict__ gin,
                                           ST* __restrict__ gout, const float* __restrict__ phi,
                                           const float* __restrict__ Trow,
                                           float* __restrict__ uout, float* __restrict__ nout,
                                           double* __restrict__ partials, const int x0,
                                           const int y0, Lb2dSmem<TY>& S) {
-  constexpr int NTH = 16 * TY, NW = TY / 4;
+  constexpr int NTH = 64 * TY / SPT, NW = TY / SPT;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;
 
   // issue the population pulls first so that their latency overlaps the stencil phases
-  float g[4][9];
+  float g[SPT][9];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < SPT; ++j) {
     const int x = x0 + tx, y = y0 + ty + NW * j;
     if (x < nx && y < ny) pull9(gin, N, nx, ny, P.walls, x, y, g[j]);
   }
@@ -167,7 +173,7 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
 
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < SPT; ++j) {
     const int row = ty + NW * j;
     const int x = x0 + tx, y = y0 + row;
     if (x >= nx || y >= ny) continue;
@@ -262,7 +268,7 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
 }
 
 template <int TY, int MODE, typename ST>
-__global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const ST* __restrict__ gin,
+__global__ __launch_bounds__(lb2d_threads(TY)) void lb2d_kernel(KParams P, const ST* __restrict__ gin,
                                                        ST* __restrict__ gout,
                                                        const float* __restrict__ phi,
                                                        const float* __restrict__ Trow,
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(16 * TY) void lb2d_kernel(KParams P, const ST* __re
 // Ensemble: workgroup b takes tile xcd_tile(b, ntiles) of the concatenated tile lists of all
 // members; the member's tiles are then processed exactly as in a single simulation.
 template <int TY, typename ST>
-__global__ __launch_bounds__(16 * TY) void lb2d_ens_kernel(const EnsMember* __restrict__ mem,
+__global__ __launch_bounds__(lb2d_threads(TY)) void lb2d_ens_kernel(const EnsMember* __restrict__ mem,
                                                            const int* __restrict__ tile_member,
                                                            int ntiles, int cur) {
   __shared__ Lb2dSmem<TY> S;
@@ -522,7 +528,7 @@ template <int TY, typename ST>
 static void lb2d_launch(const KParams& P, int mode, const void* gin, void* gout, const float* phi,
                         const float* Trow, float* u, float* n, double* partials, hipStream_t st,
                         hipEvent_t e0, hipEvent_t e1) {
-  dim3 grid(blocks2d(P, TY)), block(16 * TY);
+  dim3 grid(blocks2d(P, TY)), block(lb2d_threads(TY));
   const ST* gi = (const ST*)gin;
   ST* go = (ST*)gout;
   if (mode == MODE_STEP)
@@ -594,10 +600,10 @@ hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, flo
 template <int TY>
 static void ens_step_ty(const EnsMember* mem, const int* tile_member, int ntiles, int cur,
                         int half, int hydro, int nphi, hipStream_t st) {
-  dim3 grid(ntiles), block(16 * TY);
+  dim3 grid(ntiles), block(16 * TY), lb_block(lb2d_threads(TY));
   if (hydro) {
-    if (half) hipLaunchKernelGGL((lb2d_ens_kernel<TY, __half>), grid, block, 0, st, mem, tile_member, ntiles, cur);
-    else hipLaunchKernelGGL((lb2d_ens_kernel<TY, float>), grid, block, 0, st, mem, tile_member, ntiles, cur);
+    if (half) hipLaunchKernelGGL((lb2d_ens_kernel<TY, __half>), grid, lb_block, 0, st, mem, tile_member, ntiles, cur);
+    else hipLaunchKernelGGL((lb2d_ens_kernel<TY, float>), grid, lb_block, 0, st, mem, tile_member, ntiles, cur);
   }
   int remaining = nphi, pass = 0;
   while (remaining > 0) {
