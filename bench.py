@@ -111,9 +111,21 @@ def bench_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+def unet_shapes(in_ch, levels=4, base=32):
+    """(C_in, C_out) of the 3x3 layers in parameter order."""
+    widths = [base << l for l in range(levels)]
+    shapes = [(in_ch, base), (base, base)]
+    for l in range(1, levels):
+        shapes += [(widths[l - 1], widths[l]), (widths[l], widths[l])]
+    for l in range(levels - 2, -1, -1):
+        shapes += [(widths[l + 1] + widths[l], widths[l]), (widths[l], widths[l])]
+    return shapes
+
+
 def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noise=0.0,
-                    held_out=(99, 98, 97)):
-    """Train the surrogate on plain runs and compare the accelerated run with the plain solver."""
+                    held_out=(99, 98, 97), density=False):
+    """Train the surrogate on plain runs and compare the accelerated run with the plain solver.
+    With `density` the network also reads and predicts the lattice density n."""
     import numpy as np
     import torch
     import synthetic as S
@@ -122,20 +134,16 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
     t_start, nsnap, every = 8000, 200, 100
     mem, phis = S.surrogate_members(seed=7, count=members + 1, side=side, instant=members + 1)
     t = time.perf_counter()
-    snaps = ST.snapshots(mem, phis, t_start, nsnap, every)
+    snaps = ST.snapshots(mem, phis, t_start, nsnap, every, density=density)
     val, train = snaps[members:], snaps[:members]
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t
     print(f"surrogate: {members + 1} runs of {side}^2 snapshotted in {gen_s:.1f} s", file=sys.stderr,
           flush=True)
     norm = ST.normalisation(train, mem[0]["Tc"])
-    widths = [32 << l for l in range(4)]
-    shapes = [(5, 32), (32, 32)]
-    for l in range(1, 4):
-        shapes += [(widths[l - 1], widths[l]), (widths[l], widths[l])]
-    for l in range(2, -1, -1):
-        shapes += [(widths[l + 1] + widths[l], widths[l]), (widths[l], widths[l])]
-    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3)), dtype=torch.float32, device="cuda:0")
+    d = int(bool(density))
+    shapes = unet_shapes(5 + d)
+    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3 + d)), dtype=torch.float32, device="cuda:0")
     net = Surrogate(side, side, training=True, **norm).set_params(th)
     val0 = ST.validation_loss(net, val)
     stream = torch.cuda.Stream()  # a capturable stream: the rollout replays its step graph
@@ -161,7 +169,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
     fwd_ms = float(np.median(ts))
     flop = 0
     for lev, (ci, co) in zip([0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0], shapes):
-        flop += 2 * 9 * max(ci, 32) * co * (side >> lev) ** 2
+        flop += 2 * 9 * ci * co * (side >> lev) ** 2
     p = dict(mem[0], tau=1.5)
     runs = [ST.evaluate(inf, p, S.phi0((side, side), seed=sd), t0=15000, cycles=10, calls=10,
                         steps_per_call=every, anchor_steps=anchor_steps, zero_net=zero)
@@ -213,7 +221,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         "no_network_phi_rel_l2": None if r["no_network_phi_rel_l2"] is None else round(r["no_network_phi_rel_l2"], 4),
         "finite": bool(r["surrogate_finite"]),
         "finite_runs": sum(bool(q["surrogate_finite"]) for q in runs), "held_out_runs": len(runs),
-        "per_run": per_run, "input_noise": noise,
+        "per_run": per_run, "input_noise": noise, "density_channel": bool(density),
         "reanchor_every_5_calls": every5,
         "validation_loss_untrained": round(val0, 4), "validation_loss_trained": round(val1, 4),
         "snapshot_s": round(gen_s, 2), "train_s": round(train_s, 2), "train_steps": train_steps,
@@ -235,13 +243,8 @@ def surrogate_profile_pass(side=512, calls=50):
     from paper_1102_3094_amd import surrogate_train as ST
     mem, phis = S.surrogate_members(seed=7, count=1, side=side, instant=1)
     snaps = ST.snapshots(mem, phis, 2000, 1, 100)
-    widths = [32 << l for l in range(4)]
-    shapes = [(5, 32), (32, 32)]
-    for l in range(1, 4):
-        shapes += [(widths[l - 1], widths[l]), (widths[l], widths[l])]
-    for l in range(2, -1, -1):
-        shapes += [(widths[l + 1] + widths[l], widths[l]), (widths[l], widths[l])]
-    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3)), dtype=torch.float32, device="cuda:0")
+    th = torch.tensor(S.he_uniform(5, unet_shapes(5), head=(32, 3)), dtype=torch.float32,
+                      device="cuda:0")
     net = Surrogate(side, side, **ST.normalisation(snaps, 1.0)).set_params(th)
     codes = net.tune(snaps[0, 0])
     out = torch.empty((3, side, side), dtype=torch.float32, device="cuda:0")
@@ -266,6 +269,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the GPU, about a minute)")
     ap.add_argument("--surrogate-train-steps", type=int, default=6000)
+    ap.add_argument("--surrogate-density", type=int, default=0, choices=(0, 1),
+                    help="1: the surrogate also reads and predicts the lattice density")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the learned-surrogate leg, printed as its own JSON line")
     ap.add_argument("--surrogate-profile-pass", action="store_true",
                     help="for rocprofv3: 50 tuned forward passes of the 512^2 surrogate")
     ap.add_argument("--profile-pass", action="store_true",
@@ -287,6 +294,11 @@ def main():
         return surrogate_profile_pass()
     if args.ensemble:
         return bench_ensemble(args)
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": bench_surrogate(train_steps=args.surrogate_train_steps,
+                                                       density=bool(args.surrogate_density))}),
+              flush=True)
+        return
     wl = args.workload
     p = S.model_params(wl, pop_storage=args.pop_storage)
     phi0 = S.initial_phi(wl)
@@ -374,7 +386,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, phi0)
     if not args.no_surrogate and dim == 2 and wl == WORKLOAD:
-        out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps)
+        out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
+                                           density=bool(args.surrogate_density))
     print(json.dumps(out), flush=True)
 
 

@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE (part of the oracle).  Only tests and the benchmark's CPU ba
 The paper itself has no network; this is the learned part that advances the order parameter and
 the velocity of the hybrid lattice Boltzmann / finite-difference method by a fixed number of
 lattice steps.  The network maps the normalised fields (phi, u_x, u_y, T, a) on an H x W lattice
-to the increments of (phi, u_x, u_y) over those steps.
+to the increments of (phi, u_x, u_y) over those steps; with the density variant the input has a
+sixth channel (n) and the output a fourth (the increment of n).
 
 Architecture (L levels, widths w_1 .. w_L, default 4 levels of 32, 64, 128, 256 channels):
   encoder level l:   two 3x3 convolutions w_{l-1} -> w_l -> w_l, each followed by SiLU;
@@ -141,10 +142,10 @@ def up(x):
     return np.repeat(np.repeat(x, 2, axis=0), 2, axis=1)
 
 
-def forward(theta, x, widths=WIDTHS, q=False):
-    """x [H, W, IN_CH] -> (out [H, W, OUT_CH], cache for backward)."""
+def forward(theta, x, widths=WIDTHS, q=False, out_ch=OUT_CH):
+    """x [H, W, C_in] -> (out [H, W, out_ch], cache for backward)."""
     r = bf16 if q else (lambda v: v)
-    P = split(theta, widths, x.shape[2])
+    P = split(theta, widths, x.shape[2], out_ch)
     L = len(widths)
     cache = {"x": r(x)}
 
@@ -178,14 +179,15 @@ def backward(theta, cache, out, target, widths=WIDTHS, q=False):
     """Gradient of loss(out, target) with respect to theta and the input x."""
     r = bf16 if q else (lambda v: v)
     in_ch = cache["x"].shape[2]
-    P = split(theta, widths, in_ch)
+    out_ch = out.shape[2]
+    P = split(theta, widths, in_ch, out_ch)
     grad = np.zeros_like(np.asarray(theta, np.float64))
-    G = split(grad, widths, in_ch)
+    G = split(grad, widths, in_ch, out_ch)
     L = len(widths)
     g_out = 2.0 * (out - target) / out.size
     Wh, _ = P["head"]
     h = cache["head"]
-    G["head"][0][...] = g_out.reshape(-1, OUT_CH).T @ h.reshape(-1, h.shape[2])
+    G["head"][0][...] = g_out.reshape(-1, out_ch).T @ h.reshape(-1, h.shape[2])
     G["head"][1][...] = g_out.sum(axis=(0, 1))
     g = g_out @ Wh  # gradient with respect to the output of d1 (or eL when L = 1)
 

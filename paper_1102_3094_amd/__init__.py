@@ -221,10 +221,12 @@ class Sim:
         return self
 
     def fields_into(self, buf):
-        """phi, u_x, u_y, T of a 2D run into the planar FP32 device buffer buf [4][ny][nx]."""
-        assert self.dim == 2 and buf.is_contiguous() and buf.numel() == 4 * self.N
+        """phi, u_x, u_y, T (and, for a buffer of five planes, the density n) of a 2D run into the
+        planar FP32 device buffer buf [4 or 5][ny][nx]."""
+        assert self.dim == 2 and buf.is_contiguous() and buf.numel() in (4 * self.N, 5 * self.N)
         p = buf.data_ptr()
-        self._chk(load().lam_get_fields(self._h, C.c_void_p(p), C.c_void_p(p + 4 * self.N), None,
+        n = C.c_void_p(p + 16 * self.N) if buf.numel() == 5 * self.N else None
+        self._chk(load().lam_get_fields(self._h, C.c_void_p(p), C.c_void_p(p + 4 * self.N), n,
                                         C.c_void_p(p + 12 * self.N)))
         return buf
 

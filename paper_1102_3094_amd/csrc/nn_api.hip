@@ -22,7 +22,7 @@ using namespace lam::nn;
 
 namespace {
 constexpr int MAXL = 5;
-constexpr int IN_PAD = 32;                    // packed input channels (5 used)
+constexpr int IN_PAD = 32;                    // packed input channels (5 or 6 used)
 constexpr size_t WGRAD_MAX_FLOATS = 16u << 20;  // weight-gradient partials: 64 MB
 
 struct Layer {
@@ -53,6 +53,7 @@ static thread_local std::string g_nn_error;
 struct lsn_net {
   lsn_config c;
   int L, H, W, wid[MAXL];
+  int nf, nout;    // field planes (4 + with_density) and output channels (3 + with_density)
   size_t P[MAXL];  // pixels per level
   hipStream_t st;
   size_t nparam, head_off;
@@ -97,10 +98,12 @@ int check_config(const lsn_config* c) {
     return fail(nullptr, LAM_EINVAL,
                 "height must be a multiple of 4 * 2^(levels-1) and width of 32 * 2^(levels-1)");
   if (!(c->Tc != 0.f) || !isfinite(c->Tc)) return fail(nullptr, LAM_EINVAL, "Tc must be finite and non-zero");
-  for (int i = 0; i < 5; ++i)
+  if (c->with_density != 0 && c->with_density != 1)
+    return fail(nullptr, LAM_EINVAL, "with_density must be 0 or 1");
+  for (int i = 0; i < 5 + c->with_density; ++i)
     if (!isfinite(c->in_shift[i]) || !isfinite(c->in_scale[i]))
       return fail(nullptr, LAM_EINVAL, "input normalisation must be finite");
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3 + c->with_density; ++i)
     if (!isfinite(c->out_scale[i]) || c->out_scale[i] == 0.f)
       return fail(nullptr, LAM_EINVAL, "out_scale must be finite and non-zero");
   return LAM_OK;
@@ -114,7 +117,7 @@ void build_layers(const lsn_config& c, std::vector<Layer>& ly, size_t* nparam, s
   ly.clear();
   auto add = [&](int cin, int cout, int cin_pad) { ly.push_back(Layer{cin, cout, cin_pad, 0, 0, nullptr, nullptr, 0}); };
   for (int l = 0; l < L; ++l) {
-    if (l == 0) add(5, w[0], IN_PAD);
+    if (l == 0) add(5 + c.with_density, w[0], IN_PAD);
     else add(w[l - 1], w[l], w[l - 1]);
     add(w[l], w[l], w[l]);
   }
@@ -130,7 +133,8 @@ void build_layers(const lsn_config& c, std::vector<Layer>& ly, size_t* nparam, s
     o += q.cout;
   }
   *head_off = o;
-  *nparam = o + 3 * (size_t)w[0] + 3;
+  const size_t nout = 3 + c.with_density;
+  *nparam = o + nout * w[0] + nout;
 }
 
 int enc_a(int l) { return 2 * l; }
@@ -179,14 +183,15 @@ size_t carve(lsn_net* n, char* base) {
       }
     }
   }
-  n->out = cv.take<float>(3 * n->P[0]);
-  // FP64 partials: [0, loss_blocks] for the loss and the conservation shift, then per-block
-  // partials of the bias and head gradients.
-  size_t nd = (size_t)loss_blocks(n->P[0]) + 1;
+  n->out = cv.take<float>(n->nout * n->P[0]);
+  // FP64 partials: [0, 2 (loss_blocks + 1)) for the loss and the two conservation shifts, then
+  // per-block partials of the bias and head gradients from loss_blocks + 1 on (the shifts and
+  // the gradients are never in flight together).
+  size_t nd = 2 * ((size_t)loss_blocks(n->P[0]) + 1);
   if (tr) {
     n->gA = cv.take<bf16_t>(n->P[0] * n->wid[0]);
     n->gB = cv.take<bf16_t>(n->P[0] * n->wid[0]);
-    n->gout = cv.take<float>(3 * n->P[0]);
+    n->gout = cv.take<float>(n->nout * n->P[0]);
     size_t need = 0;
     // weight-gradient partials: the largest split buffer over the layers
     for (int i = 0; i < (int)n->layers.size(); ++i) {
@@ -199,7 +204,7 @@ size_t carve(lsn_net* n, char* base) {
       need = std::max(need, (size_t)ns * 9 * q.cout * q.cin_pad);
     }
     n->part = cv.take<float>(need);
-    nd += (size_t)bias_blocks(n->P[0]) * std::max(3 * n->wid[0] + 3, 256);
+    nd += (size_t)bias_blocks(n->P[0]) * std::max(n->nout * n->wid[0] + n->nout, 256);
   }
   n->dpart = cv.take<double>(nd);
   return cv.off;
@@ -271,11 +276,12 @@ LayerIO layer_io(const lsn_net* n, int i, bool keep) {
 
 PackArgs pack_args(const lsn_net* n) {
   PackArgs pa;
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     pa.shift[i] = n->c.in_shift[i];
     pa.scale[i] = n->c.in_scale[i];
   }
   pa.Tc = n->c.Tc;
+  pa.density = n->c.with_density;
   return pa;
 }
 
@@ -316,6 +322,7 @@ hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
       a.fuse = FUSE_HEAD;
       a.head_w = n->master + n->head_off;
       a.head_out = n->out;
+      a.nout = n->nout;
     }
   }
   return launch_conv(CONV_FWD, a, n->st);
@@ -336,7 +343,7 @@ hipError_t forward(lsn_net* n, const float* fields, bool keep) {
     if ((e = fwd_layer(n, dec_a(L, l), keep)) || (e = fwd_layer(n, dec_b(L, l), keep))) return e;
   if (fuses_head(n, keep)) return hipSuccess;
   const bf16_t* top = L > 1 ? n->dd[0] : n->enc_out[0];
-  return launch_head_fwd(top, n->wid[0], n->P[0], n->master + n->head_off, n->out, n->st);
+  return launch_head_fwd(top, n->wid[0], n->nout, n->P[0], n->master + n->head_off, n->out, n->st);
 }
 
 // Backward of layer i given gz = gradient w.r.t. its pre-activation: weight and bias gradients,
@@ -365,12 +372,12 @@ hipError_t backward(lsn_net* n, const float* target) {
   hipError_t e;
   const int L = n->L;
   const size_t P0 = n->P[0];
-  if ((e = launch_loss_grad(n->out, target, P0, n->gout, n->dpart, n->st))) return e;
+  if ((e = launch_loss_grad(n->out, target, n->nout, P0, n->gout, n->dpart, n->st))) return e;
   const bf16_t* top = L > 1 ? n->dd[0] : n->enc_out[0];
   const bf16_t* ztop = L > 1 ? n->zdd[0] : n->ze[0];
   // the loss partials stay in dpart[0 .. loss_blocks): head partials go after them
   double* hpart = n->dpart + loss_blocks(P0) + 1;
-  if ((e = launch_head_bwd(top, n->wid[0], P0, n->gout, n->master + n->head_off, ztop, n->gA, hpart,
+  if ((e = launch_head_bwd(top, n->wid[0], n->nout, P0, n->gout, n->master + n->head_off, ztop, n->gA, hpart,
                            n->grad + n->head_off, n->st)))
     return e;
   // gA: gradient w.r.t. the pre-activation of the top layer.
@@ -425,6 +432,8 @@ static void init_dims(lsn_net* n, const lsn_config* cfg) {
   n->L = cfg->levels;
   n->H = cfg->height;
   n->W = cfg->width;
+  n->nf = 4 + cfg->with_density;
+  n->nout = 3 + cfg->with_density;
   for (int l = 0; l < n->L; ++l) {
     n->wid[l] = cfg->base_width << l;
     n->P[l] = (size_t)(n->H >> l) * (n->W >> l);
@@ -497,7 +506,8 @@ int lsn_forward(lsn_net* n, const float* d_fields, float* d_out) {
     n->timed = true;
   }
   if (d_out != n->out &&
-      (e = hipMemcpyAsync(d_out, n->out, 3 * n->P[0] * sizeof(float), hipMemcpyDeviceToDevice, n->st)))
+      (e = hipMemcpyAsync(d_out, n->out, n->nout * n->P[0] * sizeof(float), hipMemcpyDeviceToDevice,
+                          n->st)))
     return hip_fail(n, e, "output");
   return LAM_OK;
 }
@@ -507,7 +517,7 @@ int lsn_advance(lsn_net* n, float* d_fields) {
   hipError_t e;
   if (n->timing && (e = hipEventRecord(n->ev0, n->st))) return hip_fail(n, e, "event");
   if ((e = forward(n, d_fields, n->c.training != 0))) return hip_fail(n, e, "forward");
-  if ((e = launch_apply(d_fields, n->out, n->P[0], n->c.out_scale, n->dpart, n->st)))
+  if ((e = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->st)))
     return hip_fail(n, e, "apply");
   if (n->timing) {
     if ((e = hipEventRecord(n->ev1, n->st))) return hip_fail(n, e, "event");
@@ -518,7 +528,8 @@ int lsn_advance(lsn_net* n, float* d_fields) {
 
 int lsn_make_target(lsn_net* n, const float* d_earlier, const float* d_later, float* d_target) {
   if (!n || !d_earlier || !d_later || !d_target) return fail(n, LAM_EINVAL, "null argument");
-  hipError_t e = launch_make_target(d_earlier, d_later, n->P[0], n->c.out_scale, d_target, n->st);
+  hipError_t e = launch_make_target(d_earlier, d_later, n->nout, n->P[0], n->c.out_scale, d_target,
+                                    n->st);
   return e ? hip_fail(n, e, "target") : LAM_OK;
 }
 
@@ -543,7 +554,7 @@ int lsn_loss_backward(lsn_net* n, const float* d_fields, const float* d_target, 
       return hip_fail(n, e, "loss");
     double s = 0.0;
     for (double p : part) s += p;
-    *h_loss = s / (3.0 * (double)n->P[0]);
+    *h_loss = s / ((double)n->nout * (double)n->P[0]);
     if (!isfinite(*h_loss)) return fail(n, LAM_ENONFINITE, "loss is not finite");
   }
   return LAM_OK;
@@ -587,7 +598,7 @@ int advance_step(lsn_net* n, float* d_fields) {
       hipError_t r = hipStreamBeginCapture(n->st, hipStreamCaptureModeThreadLocal);
       if (r == hipSuccess) {
         hipError_t r1 = forward(n, d_fields, false);
-        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->P[0], n->c.out_scale, n->dpart, n->st);
+        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->st);
         hipError_t r2 = hipStreamEndCapture(n->st, &g);
         if (r1 == hipSuccess && r2 == hipSuccess) {
           hipGraphExec_t ex;
@@ -621,9 +632,10 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
     return fail(n, LAM_EINVAL, "the simulation is not an initialised 2D run on the network's lattice");
   const size_t N = n->P[0];
   const bool frozen = lam::sim_temperature_frozen(s);
+  float* d_n = n->c.with_density ? d_fields + 4 * N : nullptr;
   int r;
   for (int c = 0; c < cycles; ++c) {
-    if ((r = lam_get_fields(s, d_fields, d_fields + N, nullptr, d_fields + 3 * N)))
+    if ((r = lam_get_fields(s, d_fields, d_fields + N, d_n, d_fields + 3 * N)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
     for (int k = 0; k < calls; ++k) {
       if ((r = advance_step(n, d_fields))) return r;
@@ -632,7 +644,7 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
       if (!frozen && (r = lam_get_fields(s, nullptr, nullptr, nullptr, d_fields + 3 * N)))
         return fail(n, r, std::string("solver: ") + lam_last_error(s));
     }
-    if ((r = lam_set_fields(s, d_fields, d_fields + N, nullptr)) || (r = lam_step(s, anchor_steps)))
+    if ((r = lam_set_fields(s, d_fields, d_fields + N, d_n)) || (r = lam_step(s, anchor_steps)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
   }
   return LAM_OK;

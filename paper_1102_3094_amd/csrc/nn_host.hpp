@@ -16,8 +16,9 @@ enum { CONV_FWD = 0, CONV_BWD_SILU = 1, CONV_BWD_PLAIN = 2 };
 enum { FUSE_NONE = 0, FUSE_FIELDS = 1, FUSE_POOL = 2, FUSE_HEAD = 3 };
 
 struct PackArgs {
-  float shift[5], scale[5];
+  float shift[6], scale[6];
   float Tc;
+  int density;  // the fields carry n as a fifth plane, packed as input channel 5
 };
 
 struct ConvArgs {
@@ -37,8 +38,9 @@ struct ConvArgs {
   int fuse;             // FUSE_*; forward passes only
   const float* fields;  // FUSE_FIELDS: planar FP32 [4][H][W] and its normalisation
   PackArgs pk;
-  const float* head_w;  // FUSE_HEAD: head weights [3][32] then biases [3]; output [3][H][W]
+  const float* head_w;  // FUSE_HEAD: head weights [nout][32] then biases [nout]; output [nout][H][W]
   float* head_out;
+  int nout;
   int tiles_x, nco;     // set by the launcher
 };
 
@@ -61,22 +63,23 @@ hipError_t launch_up_bwd_silu(const bf16_t* gcat, int cat_ld, int h, int w, int 
                               bf16_t* gz, hipStream_t st);
 hipError_t launch_pool_bwd_silu(const bf16_t* gskip, int skip_ld, const bf16_t* gpool, int H, int W,
                                 int C, const bf16_t* z, bf16_t* gz, hipStream_t st);
-hipError_t launch_head_fwd(const bf16_t* d, int C, size_t npix, const float* Wh, float* out,
+hipError_t launch_head_fwd(const bf16_t* d, int C, int nout, size_t npix, const float* Wh, float* out,
                            hipStream_t st);
 int loss_blocks(size_t npix);
-hipError_t launch_loss_grad(const float* out, const float* t, size_t npix, float* gout, double* part,
-                            hipStream_t st);
-hipError_t launch_head_bwd(const bf16_t* d, int C, size_t npix, const float* gout, const float* Wh,
-                           const bf16_t* z, bf16_t* gz, double* part, float* grad_head,
-                           hipStream_t st);
+hipError_t launch_loss_grad(const float* out, const float* t, int nout, size_t npix, float* gout,
+                            double* part, hipStream_t st);
+hipError_t launch_head_bwd(const bf16_t* d, int C, int nout, size_t npix, const float* gout,
+                           const float* Wh, const bf16_t* z, bf16_t* gz, double* part,
+                           float* grad_head, hipStream_t st);
 hipError_t launch_refresh(const float* W, int Cout, int Cin, int Cin_pad, bf16_t* wf, bf16_t* wd,
                           hipStream_t st);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, float lr, float b1,
                        float b2, float eps, float c1, float c2, float gscale, hipStream_t st);
-hipError_t launch_make_target(const float* e, const float* l, size_t npix, const float* s, float* t,
-                              hipStream_t st);
-hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s, double* part,
-                        hipStream_t st);
+hipError_t launch_make_target(const float* e, const float* l, int nout, size_t npix, const float* s,
+                              float* t, hipStream_t st);
+// part: at least 2 (ceil(npix / 256) + 1) doubles
+hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
+                        double* part, hipStream_t st);
 
 }  // namespace nn
 }  // namespace lam

@@ -79,13 +79,14 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
           if (FUSE == FUSE_FIELDS) {
             if (part == 0) {
               const size_t np = (size_t)H * W, q = (size_t)y * W + x;
-              float v[5];
+              float v[6];
 #pragma unroll
               for (int c = 0; c < 4; ++c) v[c] = (a.fields[c * np + q] - a.pk.shift[c]) * a.pk.scale[c];
               v[4] = ((a.fields[3 * np + q] - a.pk.Tc) / a.pk.Tc - a.pk.shift[4]) * a.pk.scale[4];
+              v[5] = a.pk.density ? (a.fields[4 * np + q] - a.pk.shift[5]) * a.pk.scale[5] : 0.f;
               rp[i][0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
               rp[i][1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-              rp[i][2] = (uint32_t)f2bf(v[4]);
+              rp[i][2] = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
             }
           } else if (FUSE == FUSE_POOL) {
             float s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -214,19 +215,22 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       if (FUSE == FUSE_HEAD) {
         // 1x1 head over the Cout = 32 channels of each pixel (launched with NJ = 1 only)
         const size_t np = (size_t)H * W;
+        const int no = a.nout;
         for (int pl = tid; pl < TP; pl += 256) {
-          float s0 = a.head_w[96], s1 = a.head_w[97], s2 = a.head_w[98];
+          float sacc[4];
+#pragma unroll
+          for (int o = 0; o < 4; ++o) sacc[o] = o < no ? a.head_w[32 * no + o] : 0.f;
 #pragma unroll
           for (int k = 0; k < 32; ++k) {
             const float x = bf2f(so[pl * PSTR + k]);
-            s0 += a.head_w[k] * x;
-            s1 += a.head_w[32 + k] * x;
-            s2 += a.head_w[64 + k] * x;
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+              if (o < no) sacc[o] += a.head_w[32 * o + k] * x;
           }
           const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
-          a.head_out[p] = s0;
-          a.head_out[np + p] = s1;
-          a.head_out[2 * np + p] = s2;
+#pragma unroll
+          for (int o = 0; o < 4; ++o)
+            if (o < no) a.head_out[o * np + p] = sacc[o];
         }
         continue;
       }
@@ -399,20 +403,22 @@ __global__ void reduce_blocks_f64_kernel(const double* __restrict__ part, int nb
   out[i] += (float)s;
 }
 
-// Input packing: fields [4][H][W] FP32 (phi, ux, uy, T) -> [H W][32] bfloat16, channels
-// (f - shift) * scale, channel 4 from a = (T - Tc) / Tc, channels 5..31 zero.
+// Input packing: fields [4 or 5][H][W] FP32 (phi, ux, uy, T, n) -> [H W][32] bfloat16, channels
+// (f - shift) * scale, channel 4 from a = (T - Tc) / Tc, channel 5 from n (zero without the
+// density), channels 6..31 zero.
 __global__ void pack_input_kernel(const float* __restrict__ f, size_t npix, PackArgs pa,
                                   bf16_t* __restrict__ x) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  float v[5];
+  float v[6];
 #pragma unroll
   for (int c = 0; c < 4; ++c) v[c] = (f[c * npix + p] - pa.shift[c]) * pa.scale[c];
   v[4] = ((f[3 * npix + p] - pa.Tc) / pa.Tc - pa.shift[4]) * pa.scale[4];
+  v[5] = pa.density ? (f[4 * npix + p] - pa.shift[5]) * pa.scale[5] : 0.f;
   u32x4 w0;
   w0[0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
   w0[1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-  w0[2] = (uint32_t)f2bf(v[4]);
+  w0[2] = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
   w0[3] = 0;
   u32x4* dst = (u32x4*)(x + p * 32);
   dst[0] = w0;
@@ -518,39 +524,41 @@ __global__ void pool_bwd_silu_kernel(const bf16_t* __restrict__ gskip, int skip_
   *(u32x4*)(gz + p * C + g * 8) = o;
 }
 
-// Head: out[c][p] = b[c] + sum_k Wh[c][k] d[p][k], FP32 planar output, C = d's channels (<= 64).
-__global__ void head_fwd_kernel(const bf16_t* __restrict__ d, int C, size_t npix,
+// Head: out[c][p] = b[c] + sum_k Wh[c][k] d[p][k] for c < nout (<= 4), FP32 planar output, C = d's
+// channels (<= 64).
+__global__ void head_fwd_kernel(const bf16_t* __restrict__ d, int C, int nout, size_t npix,
                                 const float* __restrict__ Wh, float* __restrict__ out) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  float s0 = Wh[3 * C], s1 = Wh[3 * C + 1], s2 = Wh[3 * C + 2];
+  float sacc[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) sacc[o] = o < nout ? Wh[nout * C + o] : 0.f;
   for (int k = 0; k < C; k += 8) {
     const u32x4 v = *(const u32x4*)(d + p * C + k);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const float x = __uint_as_float(t & 1 ? (v[t / 2] & 0xFFFF0000u) : (v[t / 2] << 16));
-      s0 += Wh[k + t] * x;
-      s1 += Wh[C + k + t] * x;
-      s2 += Wh[2 * C + k + t] * x;
+#pragma unroll
+      for (int o = 0; o < 4; ++o)
+        if (o < nout) sacc[o] += Wh[o * C + k + t] * x;
     }
   }
-  out[p] = s0;
-  out[npix + p] = s1;
-  out[2 * npix + p] = s2;
+#pragma unroll
+  for (int o = 0; o < 4; ++o)
+    if (o < nout) out[o * npix + p] = sacc[o];
 }
 
-// Loss gradient: gout[c][p] = 2 (out - t) / (3 npix); per-block FP64 partial of sum (out - t)^2.
+// Loss gradient: gout[c][p] = 2 (out - t) / (nout npix); per-block FP64 partial of sum (out - t)^2.
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ out,
-                                                        const float* __restrict__ t, size_t npix,
-                                                        float* __restrict__ gout,
+                                                        const float* __restrict__ t, int nout,
+                                                        size_t npix, float* __restrict__ gout,
                                                         double* __restrict__ part) {
   __shared__ double sm[4];
   const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
   double s = 0.0;
   if (p < npix) {
-    const float inv = 2.f / (3.f * (float)npix);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    const float inv = 2.f / ((float)nout * (float)npix);
+    for (int c = 0; c < nout; ++c) {
       const float d = out[c * npix + p] - t[c * npix + p];
       s += (double)d * d;
       gout[c * npix + p] = inv * d;
@@ -563,73 +571,59 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
 }
 
 // Head weight gradient partials over pixel ranges: part[b][c C + k] = sum_p gout[c][p] d[p][k],
-// part[b][3 C + c] = sum_p gout[c][p].  Thread = (k, pixel group); C <= 64.
+// part[b][nout C + c] = sum_p gout[c][p], c < nout (<= 4).  Thread = (k, pixel group); C <= 64.
 __global__ __launch_bounds__(256) void head_wgrad_kernel(const bf16_t* __restrict__ d, int C,
-                                                         size_t npix, int per,
+                                                         int nout, size_t npix, int per,
                                                          const float* __restrict__ gout,
                                                          double* __restrict__ part) {
   __shared__ double sm[256][4];
   const int tid = threadIdx.x, k = tid % C, grp = tid / C, ngrp = 256 / C;
   const size_t p0 = (size_t)blockIdx.x * per, p1 = min(npix, p0 + per);
-  double s0 = 0, s1 = 0, s2 = 0, b0 = 0, b1 = 0, b2 = 0;
+  double sacc[4] = {0, 0, 0, 0}, bacc[4] = {0, 0, 0, 0};
   for (size_t p = p0 + grp; p < p1; p += ngrp) {
     const float x = bf2f(d[p * C + k]);
-    const float g0 = gout[p], g1 = gout[npix + p], g2 = gout[2 * npix + p];
-    s0 += (double)g0 * x;
-    s1 += (double)g1 * x;
-    s2 += (double)g2 * x;
-    if (k == 0) {
-      b0 += g0;
-      b1 += g1;
-      b2 += g2;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      if (o < nout) {
+        const float g = gout[o * npix + p];
+        sacc[o] += (double)g * x;
+        if (k == 0) bacc[o] += g;
+      }
     }
   }
-  sm[tid][0] = s0;
-  sm[tid][1] = s1;
-  sm[tid][2] = s2;
-  sm[tid][3] = 0;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) sm[tid][o] = sacc[o];
   __syncthreads();
+  double* ob = part + (size_t)blockIdx.x * (nout * C + nout);
   if (grp == 0) {
-    for (int q = 1; q < ngrp; ++q) {
-      s0 += sm[q * C + k][0];
-      s1 += sm[q * C + k][1];
-      s2 += sm[q * C + k][2];
-    }
-    double* o = part + (size_t)blockIdx.x * (3 * C + 3);
-    o[k] = s0;
-    o[C + k] = s1;
-    o[2 * C + k] = s2;
+    for (int q = 1; q < ngrp; ++q)
+#pragma unroll
+      for (int o = 0; o < 4; ++o) sacc[o] += sm[q * C + k][o];
+    for (int o = 0; o < nout; ++o) ob[o * C + k] = sacc[o];
   }
   __syncthreads();
-  if (k == 0) {
-    sm[grp][0] = b0;
-    sm[grp][1] = b1;
-    sm[grp][2] = b2;
-  }
+  if (k == 0)
+#pragma unroll
+    for (int o = 0; o < 4; ++o) sm[grp][o] = bacc[o];
   __syncthreads();
-  if (tid == 0) {
-    double c0 = 0, c1 = 0, c2 = 0;
-    for (int q = 0; q < ngrp; ++q) {
-      c0 += sm[q][0];
-      c1 += sm[q][1];
-      c2 += sm[q][2];
+  if (tid == 0)
+    for (int o = 0; o < nout; ++o) {
+      double c = 0;
+      for (int q = 0; q < ngrp; ++q) c += sm[q][o];
+      ob[nout * C + o] = c;
     }
-    double* o = part + (size_t)blockIdx.x * (3 * C + 3);
-    o[3 * C] = c0;
-    o[3 * C + 1] = c1;
-    o[3 * C + 2] = c2;
-  }
 }
 
 // Gradient into the last decoder output: gz[p][k] = bf16(silu'(z[p][k]) sum_c gout[c][p] Wh[c][k]).
-__global__ void head_dgrad_kernel(const float* __restrict__ gout, size_t npix, int C,
+__global__ void head_dgrad_kernel(const float* __restrict__ gout, size_t npix, int C, int nout,
                                   const float* __restrict__ Wh, const bf16_t* __restrict__ z,
                                   bf16_t* __restrict__ gz) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npix * C) return;
   const size_t p = i / C;
   const int k = (int)(i % C);
-  const float g = gout[p] * Wh[k] + gout[npix + p] * Wh[C + k] + gout[2 * npix + p] * Wh[2 * C + k];
+  float g = gout[p] * Wh[k];
+  for (int o = 1; o < nout; ++o) g += gout[o * npix + p] * Wh[o * C + k];
   gz[i] = f2bf(g * dsilu(bf2f(z[i])));
 }
 
@@ -667,18 +661,20 @@ __global__ void adam_kernel(float* __restrict__ th, float* __restrict__ m, float
   th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Training target: t[c][p] = (later[c][p] - earlier[c][p]) / out_scale[c], c < 3.
+// Training target: t[c][p] = (later - earlier) / out_scale[c] for the output channels c < nout,
+// taken from the field planes phi, u_x, u_y and (c = 3) n.
 __global__ void make_target_kernel(const float* __restrict__ e, const float* __restrict__ l,
-                                   size_t npix, float s0, float s1, float s2,
+                                   int nout, size_t npix, float s0, float s1, float s2, float s3,
                                    float* __restrict__ t) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * npix) return;
+  if (i >= (size_t)nout * npix) return;
   const int c = (int)(i / npix);
-  const float s = c == 0 ? s0 : (c == 1 ? s1 : s2);
-  t[i] = (l[i] - e[i]) / s;
+  const size_t src = c == 3 ? i + npix : i;
+  const float s = c == 0 ? s0 : (c == 1 ? s1 : (c == 2 ? s2 : s3));
+  t[i] = (l[src] - e[src]) / s;
 }
 
-// Per-block FP64 sums of out[0][p] (the phi increment in units of out_scale[0]).
+// Per-block FP64 sums of one FP32 plane (an increment in units of its output scale).
 __global__ __launch_bounds__(256) void sum_f32_kernel(const float* __restrict__ x, size_t n,
                                                       double* __restrict__ part) {
   __shared__ double sm[4];
@@ -705,16 +701,19 @@ __global__ __launch_bounds__(256) void mean_kernel(double* __restrict__ part, in
   if (threadIdx.x == 0) part[nblk] = sm[0] / (double)npix;
 }
 
-// One surrogate step applied in place: f[c] += out[c] s_c (c < 3), phi shifted by the mean phi
-// increment so that sum phi is unchanged.
-__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, size_t npix,
-                             float s0, float s1, float s2, const double* __restrict__ mean) {
+// One surrogate step applied in place: f[c] += out[c] s_c for phi, u_x, u_y and (nout = 4) n, with
+// phi and n shifted by the mean of their increments so that their sums are unchanged.
+__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, int nout,
+                             size_t npix, float s0, float s1, float s2, float s3,
+                             const double* __restrict__ mean_phi,
+                             const double* __restrict__ mean_n) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  const float mu = (float)*mean;
+  const float mu = (float)*mean_phi;
   f[p] += (out[p] - mu) * s0;
   f[npix + p] += out[npix + p] * s1;
   f[2 * npix + p] += out[2 * npix + p] * s2;
+  if (nout > 3) f[4 * npix + p] += (out[3 * npix + p] - (float)*mean_n) * s3;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -874,26 +873,28 @@ hipError_t launch_pool_bwd_silu(const bf16_t* gskip, int skip_ld, const bf16_t* 
                      skip_ld, gpool, H, W, C, z, gz);
   return hipGetLastError();
 }
-hipError_t launch_head_fwd(const bf16_t* d, int C, size_t npix, const float* Wh, float* out,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(head_fwd_kernel, nblocks(npix, 256), 256, 0, st, d, C, npix, Wh, out);
+hipError_t launch_head_fwd(const bf16_t* d, int C, int nout, size_t npix, const float* Wh,
+                           float* out, hipStream_t st) {
+  hipLaunchKernelGGL(head_fwd_kernel, nblocks(npix, 256), 256, 0, st, d, C, nout, npix, Wh, out);
   return hipGetLastError();
 }
 int loss_blocks(size_t npix) { return (int)((npix + 255) / 256); }
-hipError_t launch_loss_grad(const float* out, const float* t, size_t npix, float* gout,
+hipError_t launch_loss_grad(const float* out, const float* t, int nout, size_t npix, float* gout,
                             double* part, hipStream_t st) {
-  hipLaunchKernelGGL(loss_grad_kernel, loss_blocks(npix), 256, 0, st, out, t, npix, gout, part);
+  hipLaunchKernelGGL(loss_grad_kernel, loss_blocks(npix), 256, 0, st, out, t, nout, npix, gout,
+                     part);
   return hipGetLastError();
 }
-hipError_t launch_head_bwd(const bf16_t* d, int C, size_t npix, const float* gout, const float* Wh,
-                           const bf16_t* z, bf16_t* gz, double* part, float* grad_head,
-                           hipStream_t st) {
+hipError_t launch_head_bwd(const bf16_t* d, int C, int nout, size_t npix, const float* gout,
+                           const float* Wh, const bf16_t* z, bf16_t* gz, double* part,
+                           float* grad_head, hipStream_t st) {
   const int nb = bias_blocks(npix);
   const int per = (int)((npix + nb - 1) / nb);
-  hipLaunchKernelGGL(head_wgrad_kernel, nb, 256, 0, st, d, C, npix, per, gout, part);
-  hipLaunchKernelGGL(reduce_blocks_f64_kernel, nblocks(3 * C + 3, 256), 256, 0, st, part, nb,
-                     3 * C + 3, grad_head);
-  hipLaunchKernelGGL(head_dgrad_kernel, nblocks(npix * C, 256), 256, 0, st, gout, npix, C, Wh, z, gz);
+  const int n = nout * C + nout;
+  hipLaunchKernelGGL(head_wgrad_kernel, nb, 256, 0, st, d, C, nout, npix, per, gout, part);
+  hipLaunchKernelGGL(reduce_blocks_f64_kernel, nblocks(n, 256), 256, 0, st, part, nb, n, grad_head);
+  hipLaunchKernelGGL(head_dgrad_kernel, nblocks(npix * C, 256), 256, 0, st, gout, npix, C, nout, Wh,
+                     z, gz);
   return hipGetLastError();
 }
 hipError_t launch_refresh(const float* W, int Cout, int Cin, int Cin_pad, bf16_t* wf, bf16_t* wd,
@@ -908,19 +909,25 @@ hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, 
                      c2, gscale);
   return hipGetLastError();
 }
-hipError_t launch_make_target(const float* e, const float* l, size_t npix, const float* s, float* t,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(make_target_kernel, nblocks(3 * npix, 256), 256, 0, st, e, l, npix, s[0], s[1],
-                     s[2], t);
+hipError_t launch_make_target(const float* e, const float* l, int nout, size_t npix, const float* s,
+                              float* t, hipStream_t st) {
+  hipLaunchKernelGGL(make_target_kernel, nblocks(nout * npix, 256), 256, 0, st, e, l, nout, npix,
+                     s[0], s[1], s[2], nout > 3 ? s[3] : 1.f, t);
   return hipGetLastError();
 }
-hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s, double* part,
-                        hipStream_t st) {
+hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
+                        double* part, hipStream_t st) {
   const int nb = (int)((npix + 255) / 256);
   hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out, npix, part);
   hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part, nb, npix);
-  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, npix, s[0], s[1], s[2],
-                     (const double*)(part + nb));
+  double* part_n = part + nb + 1;
+  if (nout > 3) {
+    hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out + 3 * npix, npix, part_n);
+    hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part_n, nb, npix);
+  }
+  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, nout, npix, s[0], s[1], s[2],
+                     nout > 3 ? s[3] : 0.f, (const double*)(part + nb),
+                     (const double*)(part_n + nb));
   return hipGetLastError();
 }
 

@@ -16,9 +16,9 @@ SURROGATE_EXPORTS = ("lsn_param_count", "lsn_workspace_bytes", "lsn_create", "ls
 
 class lsn_config(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("levels", C.c_int32),
-                ("base_width", C.c_int32), ("training", C.c_int32), ("Tc", C.c_float),
-                ("in_shift", C.c_float * 5), ("in_scale", C.c_float * 5),
-                ("out_scale", C.c_float * 3)]
+                ("base_width", C.c_int32), ("training", C.c_int32), ("with_density", C.c_int32),
+                ("Tc", C.c_float), ("in_shift", C.c_float * 6), ("in_scale", C.c_float * 6),
+                ("out_scale", C.c_float * 4)]
 
 
 _bound = None
@@ -54,15 +54,24 @@ def lib():
 
 
 def make_config(height, width, levels=4, base_width=32, training=False, Tc=1.0,
-                in_shift=(0.0,) * 5, in_scale=(1.0,) * 5, out_scale=(1.0,) * 3) -> lsn_config:
+                in_shift=None, in_scale=None, out_scale=None, with_density=False) -> lsn_config:
+    """Normalisation tuples have 5 (6 with the density) inputs and 3 (4) outputs; omitted ones
+    are the identity."""
+    d = int(bool(with_density))
+    in_shift = tuple(in_shift) if in_shift is not None else (0.0,) * (5 + d)
+    in_scale = tuple(in_scale) if in_scale is not None else (1.0,) * (5 + d)
+    out_scale = tuple(out_scale) if out_scale is not None else (1.0,) * (3 + d)
+    if len(in_shift) != 5 + d or len(in_scale) != 5 + d or len(out_scale) != 3 + d:
+        raise ValueError("normalisation of 5 + with_density inputs and 3 + with_density outputs")
     c = lsn_config()
     c.height, c.width, c.levels, c.base_width = int(height), int(width), int(levels), int(base_width)
     c.training = int(bool(training))
+    c.with_density = d
     c.Tc = float(Tc)
-    for i in range(5):
+    for i in range(5 + d):
         c.in_shift[i] = float(in_shift[i])
         c.in_scale[i] = float(in_scale[i])
-    for i in range(3):
+    for i in range(3 + d):
         c.out_scale[i] = float(out_scale[i])
     return c
 
@@ -80,8 +89,9 @@ def param_count(**cfg) -> int:
 
 
 class Surrogate:
-    """U-Net surrogate on one GPU.  Fields are planar FP32 device tensors [4, H, W] (phi, u_x,
-    u_y, T); outputs and targets are [3, H, W]."""
+    """U-Net surrogate on one GPU.  Fields are planar FP32 device tensors [NF, H, W] (phi, u_x,
+    u_y, T and, with the density, n); outputs and targets are [NOUT, H, W] (increments of phi,
+    u_x, u_y and n).  NF = 4 + with_density, NOUT = 3 + with_density."""
 
     def __init__(self, height, width, device="cuda:0", stream=None, **cfg):
         import torch
@@ -89,6 +99,7 @@ class Surrogate:
         self.device = torch.device(device)
         self.H, self.W = int(height), int(width)
         self.cfg = make_config(height, width, **cfg)
+        self.NF, self.NOUT = 4 + self.cfg.with_density, 3 + self.cfg.with_density
         n = C.c_size_t()
         _check(L.lsn_workspace_bytes(C.byref(self.cfg), C.byref(n)))
         with torch.cuda.device(self.device):
@@ -132,24 +143,25 @@ class Surrogate:
 
     def forward(self, fields, out=None):
         import torch
-        f = self._t(fields, (4, self.H, self.W))
+        f = self._t(fields, (self.NF, self.H, self.W))
         if out is None:
-            out = torch.empty((3, self.H, self.W), dtype=torch.float32, device=self.device)
+            out = torch.empty((self.NOUT, self.H, self.W), dtype=torch.float32, device=self.device)
         self._chk(lib().lsn_forward(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr())))
         return out
 
     def advance(self, fields):
-        """In place on a contiguous [4, H, W] FP32 device tensor."""
+        """In place on a contiguous [NF, H, W] FP32 device tensor."""
         assert fields.is_contiguous() and fields.dtype == torch_float32()
+        assert fields.numel() == self.NF * self.H * self.W, fields.shape
         self._chk(lib().lsn_advance(self._h, C.c_void_p(fields.data_ptr())))
         return fields
 
     def make_target(self, earlier, later, out=None):
         import torch
-        a = self._t(earlier, (4, self.H, self.W))
-        b = self._t(later, (4, self.H, self.W))
+        a = self._t(earlier, (self.NF, self.H, self.W))
+        b = self._t(later, (self.NF, self.H, self.W))
         if out is None:
-            out = torch.empty((3, self.H, self.W), dtype=torch.float32, device=self.device)
+            out = torch.empty((self.NOUT, self.H, self.W), dtype=torch.float32, device=self.device)
         self._chk(lib().lsn_make_target(self._h, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
                                         C.c_void_p(out.data_ptr())))
         return out
@@ -159,8 +171,8 @@ class Surrogate:
         return self
 
     def loss_backward(self, fields, target, want_loss=True):
-        f = self._t(fields, (4, self.H, self.W))
-        t = self._t(target, (3, self.H, self.W))
+        f = self._t(fields, (self.NF, self.H, self.W))
+        t = self._t(target, (self.NOUT, self.H, self.W))
         loss = C.c_double()
         self._chk(lib().lsn_loss_backward(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr()),
                                           C.byref(loss) if want_loss else None))
@@ -179,14 +191,14 @@ class Surrogate:
 
     def rollout(self, sim, fields_scratch, cycles, calls=10, steps_per_call=100, anchor_steps=100):
         """Surrogate-accelerated run of `sim` (a Sim on the same stream); fields_scratch is a
-        contiguous [4, H, W] FP32 device tensor."""
-        assert fields_scratch.is_contiguous() and fields_scratch.numel() == 4 * self.H * self.W
+        contiguous [NF, H, W] FP32 device tensor."""
+        assert fields_scratch.is_contiguous() and fields_scratch.numel() == self.NF * self.H * self.W
         self._chk(lib().lsn_rollout(self._h, sim._h, C.c_void_p(fields_scratch.data_ptr()),
                                     int(cycles), int(calls), int(steps_per_call), int(anchor_steps)))
         return sim
 
     def tune(self, fields, reps=3):
-        f = self._t(fields, (4, self.H, self.W))
+        f = self._t(fields, (self.NF, self.H, self.W))
         self._chk(lib().lsn_tune(self._h, C.c_void_p(f.data_ptr()), int(reps)))
         return self.shapes()
 

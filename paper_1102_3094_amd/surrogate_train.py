@@ -3,7 +3,8 @@ C-ABIs (solver runs and snapshots through lam.h; loss, gradients, Adam and rollo
 lam_surrogate.h); torch holds the snapshot tensors on the device.
 
 Workflow:
-  1. snapshots(): plain solver runs; fields (phi, u_x, u_y, T) every `every` steps from t_start.
+  1. snapshots(): plain solver runs; fields (phi, u_x, u_y, T and optionally the density n)
+     every `every` steps from t_start.
   2. normalisation(): input shifts/scales and output scales from the snapshot statistics.
   3. train(): Adam on random consecutive snapshot pairs (target = normalised increment).
   4. evaluate(): the same start state advanced by the plain solver and by the surrogate-
@@ -22,11 +23,13 @@ from . import Ensemble, Sim
 from .surrogate import Surrogate
 
 
-def snapshots(members, phis, t_start, count, every=100, device="cuda:0"):
-    """[M, count + 1, 4, H, W] FP32 device tensor of fields at t_start + k * every."""
+def snapshots(members, phis, t_start, count, every=100, device="cuda:0", density=False):
+    """[M, count + 1, NF, H, W] FP32 device tensor of fields at t_start + k * every (NF = 4, or 5
+    with the density plane)."""
     import torch
     H, W = members[0]["ny"], members[0]["nx"]
-    out = torch.empty((len(members), count + 1, 4, H, W), dtype=torch.float32, device=device)
+    nf = 5 if density else 4
+    out = torch.empty((len(members), count + 1, nf, H, W), dtype=torch.float32, device=device)
     for m, (p, phi) in enumerate(zip(members, phis)):
         sim = Sim(p, device=device).init_fields(torch.tensor(phi, dtype=torch.float32))
         sim.step(t_start)
@@ -43,15 +46,20 @@ def snapshots(members, phis, t_start, count, every=100, device="cuda:0"):
 def normalisation(snaps, Tc, u_ref=0.01, a_ref=0.25):
     """phi scaled to unit spread, velocities by a reference speed u_ref (a Mach-number scale:
     the spread of u is dominated by the few active runs), T - Tc and a by a reference reduced
-    temperature a_ref (T may be uniform in every run); outputs scaled by the standard deviation
-    of each increment over the pairs."""
+    temperature a_ref (T may be uniform in every run); with a density plane, n - 1 scaled to unit
+    spread; outputs scaled by the standard deviation of each increment over the pairs."""
+    density = snaps.shape[2] == 5
     x = snaps[:, :-1]
-    d = snaps[:, 1:, :3] - snaps[:, :-1, :3]
+    planes = (0, 1, 2, 4) if density else (0, 1, 2)
     sd = lambda t: max(float(t.double().std()), 1e-12)  # noqa: E731
     in_scale = (1.0 / sd(x[:, :, 0]), 1.0 / u_ref, 1.0 / u_ref, 1.0 / (a_ref * Tc), 1.0 / a_ref)
     in_shift = (0.0, 0.0, 0.0, Tc, 0.0)
-    out_scale = tuple(sd(d[:, :, c]) for c in range(3))
-    return dict(Tc=Tc, in_shift=in_shift, in_scale=in_scale, out_scale=out_scale)
+    if density:
+        in_scale += (1.0 / sd(x[:, :, 4]),)
+        in_shift += (1.0,)
+    out_scale = tuple(sd(snaps[:, 1:, c] - snaps[:, :-1, c]) for c in planes)
+    return dict(Tc=Tc, in_shift=in_shift, in_scale=in_scale, out_scale=out_scale,
+                with_density=density)
 
 
 def mirror(f):
@@ -168,7 +176,7 @@ def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=
     res["plain_k_peak"], res["plain_S_peak"] = kp, sp
     phi_ref = plain.fields()["phi"].double()
 
-    scratch = torch.empty((4, params["ny"], params["nx"]), dtype=torch.float32, device=device)
+    scratch = torch.empty((net.NF, params["ny"], params["nx"]), dtype=torch.float32, device=device)
     for name, n in (("surrogate", net), ("no_network", zero_net)):
         if n is None:
             continue

@@ -165,3 +165,26 @@ def test_he_uniform_bounds():
     w0 = th[:9 * 5 * 32]
     assert np.abs(w0).max() <= np.sqrt(6 / 45) and np.abs(w0).max() > 0.9 * np.sqrt(6 / 45)
     assert np.all(th[-(32 * 3 + 3):] == 0)
+
+
+def test_gradient_finite_differences_density_variant():
+    """Six input and four output channels (the variant with the density)."""
+    widths = (4, 6)
+    shapes = [(ci, co) for _, ci, co in U.layers(widths, in_ch=6)]
+    r = rng(9)
+    theta = S.he_uniform(8, shapes, head=(widths[0], 4))
+    theta[-(4 * widths[0] + 4):] = r.normal(size=4 * widths[0] + 4)
+    x = r.normal(size=(8, 8, 6))
+    t = r.normal(size=(8, 8, 4))
+    out, cache = U.forward(theta, x, widths, out_ch=4)
+    assert out.shape == (8, 8, 4) and theta.size == U.param_count(widths, 6, 4)
+    grad, gx = U.backward(theta, cache, out, t, widths)
+    h = 1e-6
+    for i in list(r.choice(theta.size, size=25, replace=False)) + [theta.size - 1]:
+        tp = theta.copy()
+        tp[i] += h
+        tm = theta.copy()
+        tm[i] -= h
+        fd = (U.loss(U.forward(tp, x, widths, out_ch=4)[0], t) -
+              U.loss(U.forward(tm, x, widths, out_ch=4)[0], t)) / (2 * h)
+        assert fd == pytest.approx(grad[i], rel=1e-5, abs=1e-9), i
