@@ -49,6 +49,26 @@ def kernel_source_hash(dim):
     return h.hexdigest()[:16]
 
 
+def copy_ceiling_gbps(nbytes, reps=20):
+    """Bandwidth of a plain device-to-device copy of `nbytes` (read + write counted), timed with
+    events on the current stream: the practical ceiling for streaming the population planes on
+    this device, next to the nominal HBM peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def traffic_from_profiles(workload, dim):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
     or None when it is missing or was taken from another version of the kernel source."""
@@ -203,6 +223,17 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
                            "S_peak_position_err": round(q["surrogate_k_peak_err"], 4),
                            "S_peak_height_err": round(q["surrogate_S_peak_err"], 4)}
                           for sd, q in zip(held_out, runs5)]}
+    # the survey's cadence without the order-parameter limiter
+    runs0 = [ST.evaluate(inf, p, S.phi0((side, side), seed=sd), t0=15000, cycles=10, calls=10,
+                         steps_per_call=every, anchor_steps=anchor_steps, limiter=0.0)
+             for sd in held_out]
+    no_lim = {"S_peak_position_err": round(float(np.mean([q["surrogate_k_peak_err"] for q in runs0])), 4),
+              "S_peak_height_err": round(float(np.mean([q["surrogate_S_peak_err"] for q in runs0])), 4),
+              "finite_runs": sum(bool(q["surrogate_finite"]) for q in runs0),
+              "per_run": [{"seed": sd, "finite": bool(q["surrogate_finite"]),
+                           "S_peak_position_err": round(q["surrogate_k_peak_err"], 4),
+                           "S_peak_height_err": round(q["surrogate_S_peak_err"], 4)}
+                          for sd, q in zip(held_out, runs0)]}
     tflops = flop / (fwd_ms * 1e-3) / 1e12
     return {
         "workload": f"D2Q9 {side}^2, walls at 0.95 Tc, instantaneous quench, tau in [1.25, 2]; "
@@ -223,6 +254,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         "finite_runs": sum(bool(q["surrogate_finite"]) for q in runs), "held_out_runs": len(runs),
         "per_run": per_run, "input_noise": noise, "density_channel": bool(density),
         "reanchor_every_5_calls": every5,
+        "limiter_factor": 1.05, "without_limiter": no_lim,
         "validation_loss_untrained": round(val0, 4), "validation_loss_trained": round(val1, 4),
         "snapshot_s": round(gen_s, 2), "train_s": round(train_s, 2), "train_steps": train_steps,
         "forward_ms": round(fwd_ms, 4),
@@ -348,6 +380,8 @@ def main():
     phi_ms, phi_n = kt["phi"]
     lb_avg_s = lb_ms / max(lb_n, 1) / 1e3
     achieved = lb_bytes * n_sites / lb_avg_s / 1e9
+    q = 9 if dim == 2 else 19
+    copy_gbps = copy_ceiling_gbps(q * n_sites * (2 if args.pop_storage else 4))
     ob = sim.observables()
     kname = "lb2d" if dim == 2 else "lb3d"
     shape = "x".join(str(p[k]) for k in (("nx", "ny") if dim == 2 else ("nx", "ny", "nz")))
@@ -376,6 +410,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profiles(wl, dim),
                      "kernel": f"{kname} (force + stream + collide)",
+                     "copy_ceiling": round(copy_gbps, 1),
+                     "frac_of_copy_ceiling": round(achieved / copy_gbps, 4),
                      "bytes_per_site": lb_bytes, "avg_launch_us": lb_avg_s * 1e6,
                      "launches": lb_n},
         "step_effective_roofline_frac": round(mlups * 1e6 * step_bytes / 8e12, 4),

@@ -95,9 +95,19 @@ int lsn_adam(lsn_net* net, float lr, float beta1, float beta2, float eps, float 
  * (lam_set_fields with the predicted n, or n = 1 without the density channel) and run
  * `anchor_steps` plain steps (lam_step).  The simulated time advances by
  * cycles * (calls * steps_per_call + anchor_steps) steps.  Asynchronous on the network's stream,
- * which must be the stream of s. */
+ * which must be the stream of s.
+ *
+ * Order-parameter limiter (on unless lsn_set_limiter turns it off): before each re-anchoring, phi
+ * is clamped to +-factor * M, M = max |phi| of s when the call starts, and the clamped-off excess
+ * is spread evenly over the lattice so that sum phi is unchanged.  Without it the surrogate's phi
+ * drifts past the bulk values of the free energy (eq. free) and the coupled solver can blow up
+ * after a re-anchoring. */
 int lsn_rollout(lsn_net* net, lam_sim* s, float* d_fields, int32_t cycles, int32_t calls,
                 int32_t steps_per_call, int32_t anchor_steps);
+
+/* Limiter factor of lsn_rollout (default 1.05); factor <= 0 turns the limiter off; LAM_EINVAL for
+ * a non-finite factor. */
+int lsn_set_limiter(lsn_net* net, float factor);
 
 /* Tile-shape autotuner: runs the forward pass on d_fields once, then times each 3x3 layer's
  * forward convolution (best of `reps` runs) with every tile shape its sizes allow and keeps the

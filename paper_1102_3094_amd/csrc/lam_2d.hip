@@ -41,13 +41,27 @@ struct Lb2dSmem {
 constexpr int lb2d_spt(int ty) { return 64 * ty / 2 > 1024 ? 4 : 2; }
 constexpr int lb2d_threads(int ty) { return 64 * ty / lb2d_spt(ty); }
 
+// Element `i` of the plane starting at `base`, addressed as base + a 32-bit byte offset (planes of
+// the 2D lattice hold fewer than 2^30 sites): the plane base is uniform, so the access takes the
+// scalar-base form with one 32-bit vector offset instead of 64-bit vector address arithmetic.
+template <typename T>
+__device__ __forceinline__ T* plane_at(T* base, uint32_t i) {
+  return (T*)((char*)base + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T* plane_at(const T* base, uint32_t i) {
+  return (const T*)((const char*)base + i * (uint32_t)sizeof(T));
+}
+
 // Pull of the 9 populations of site (x, y): f_q(x) = f*_q(x - e_q); across a wall the opposite
 // population of x itself (halfway bounce-back).
 template <typename ST>
 __device__ __forceinline__ void pull9(const ST* __restrict__ G, size_t N, int nx, int ny,
                                       int walls, int x, int y, float g[9]) {
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  auto ld = [&](int q, int yy, int xx) { return to_f32(ld_nt(&G[(size_t)q * N + (size_t)yy * nx + xx])); };
+  auto ld = [&](int q, int yy, int xx) {
+    return to_f32(ld_nt(plane_at(G + (size_t)q * N, (uint32_t)(yy * nx + xx))));
+  };
   g[0] = ld(0, y, x);
   g[1] = ld(1, y, xm);
   g[3] = ld(3, y, xp);
@@ -119,7 +133,7 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
       const int i = tid + k * NTH;
       if (i < CNT) {
         int r = i / (TX + 6), c = i - r * (TX + 6);
-        v[k] = phi[(size_t)S.rowoff[r] + S.colx[c]];
+        v[k] = *plane_at(phi, (uint32_t)(S.rowoff[r] + S.colx[c]));
       }
     }
 #pragma unroll
@@ -207,7 +221,7 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
       ux = (jx + 0.5f * Fx) * inv;
       uy = (jy + 0.5f * Fy) * inv;
     }
-    const size_t s = (size_t)y * nx + x;
+    const uint32_t s = (uint32_t)(y * nx + x);
     if (MODE == MODE_STEP) {
       // BGK collision towards the second-order equilibrium plus the forcing term
       const float usq = 1.5f * (ux * ux + uy * uy);
@@ -219,21 +233,21 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
         return gq + om * (geq - gq) + frc;
       };
       const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
-      st_nt(&gout[0 * N + s], from_f32<ST>(coll(g0, w0, 0.f, 0.f)));
-      st_nt(&gout[1 * N + s], from_f32<ST>(coll(g1, w1, ux, Fx)));
-      st_nt(&gout[2 * N + s], from_f32<ST>(coll(g2, w1, uy, Fy)));
-      st_nt(&gout[3 * N + s], from_f32<ST>(coll(g3, w1, -ux, -Fx)));
-      st_nt(&gout[4 * N + s], from_f32<ST>(coll(g4, w1, -uy, -Fy)));
-      st_nt(&gout[5 * N + s], from_f32<ST>(coll(g5, w2, ux + uy, Fx + Fy)));
-      st_nt(&gout[6 * N + s], from_f32<ST>(coll(g6, w2, uy - ux, Fy - Fx)));
-      st_nt(&gout[7 * N + s], from_f32<ST>(coll(g7, w2, -ux - uy, -Fx - Fy)));
-      st_nt(&gout[8 * N + s], from_f32<ST>(coll(g8, w2, ux - uy, Fx - Fy)));
-      uout[s] = ux;
-      uout[N + s] = uy;
+      st_nt(plane_at(gout + 0 * N, s), from_f32<ST>(coll(g0, w0, 0.f, 0.f)));
+      st_nt(plane_at(gout + 1 * N, s), from_f32<ST>(coll(g1, w1, ux, Fx)));
+      st_nt(plane_at(gout + 2 * N, s), from_f32<ST>(coll(g2, w1, uy, Fy)));
+      st_nt(plane_at(gout + 3 * N, s), from_f32<ST>(coll(g3, w1, -ux, -Fx)));
+      st_nt(plane_at(gout + 4 * N, s), from_f32<ST>(coll(g4, w1, -uy, -Fy)));
+      st_nt(plane_at(gout + 5 * N, s), from_f32<ST>(coll(g5, w2, ux + uy, Fx + Fy)));
+      st_nt(plane_at(gout + 6 * N, s), from_f32<ST>(coll(g6, w2, uy - ux, Fy - Fx)));
+      st_nt(plane_at(gout + 7 * N, s), from_f32<ST>(coll(g7, w2, -ux - uy, -Fx - Fy)));
+      st_nt(plane_at(gout + 8 * N, s), from_f32<ST>(coll(g8, w2, ux - uy, Fx - Fy)));
+      *plane_at(uout, s) = ux;
+      *plane_at(uout + N, s) = uy;
     } else if (MODE == MODE_FIELDS) {
-      uout[s] = ux;
-      uout[N + s] = uy;
-      if (nout) nout[s] = n;
+      *plane_at(uout, s) = ux;
+      *plane_at(uout + N, s) = uy;
+      if (nout) *plane_at(nout, s) = n;
     } else {
       const int R = row + 3, C = tx + 3;
       const float ph = S.phi[R][C], a = S.a[R], L = S.L[row + 2][tx + 2];

@@ -66,6 +66,8 @@ struct lsn_net {
   bf16_t *gA = nullptr, *gB = nullptr, *gcat[MAXL] = {}, *gp[MAXL] = {};
   float *out = nullptr, *gout = nullptr, *part = nullptr;
   double* dpart = nullptr;
+  double* lim = nullptr;  // rollout limiter: [0] max |phi| at the start of the call
+  float lim_factor = 1.05f;
   int64_t adam_t = 0;
   const float* fields = nullptr;  // fields of the forward pass in flight (fused input packing)
   // HIP graph of one surrogate step (forward + apply) on a given fields buffer
@@ -207,6 +209,7 @@ size_t carve(lsn_net* n, char* base) {
     nd += (size_t)bias_blocks(n->P[0]) * std::max(n->nout * n->wid[0] + n->nout, 256);
   }
   n->dpart = cv.take<double>(nd);
+  n->lim = cv.take<double>(4);
   return cv.off;
 }
 
@@ -633,10 +636,14 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
   const size_t N = n->P[0];
   const bool frozen = lam::sim_temperature_frozen(s);
   float* d_n = n->c.with_density ? d_fields + 4 * N : nullptr;
+  const bool limit = n->lim_factor > 0.f;
   int r;
+  hipError_t e;
   for (int c = 0; c < cycles; ++c) {
     if ((r = lam_get_fields(s, d_fields, d_fields + N, d_n, d_fields + 3 * N)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
+    if (c == 0 && limit && (e = launch_absmax(d_fields, N, n->dpart, n->lim, n->st)))
+      return hip_fail(n, e, "limiter");
     for (int k = 0; k < calls; ++k) {
       if ((r = advance_step(n, d_fields))) return r;
       if ((r = lam_advance_temperature(s, steps_per_call)))
@@ -644,9 +651,18 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
       if (!frozen && (r = lam_get_fields(s, nullptr, nullptr, nullptr, d_fields + 3 * N)))
         return fail(n, r, std::string("solver: ") + lam_last_error(s));
     }
+    if (limit && (e = launch_clamp_conserve(d_fields, N, n->lim, n->lim_factor, n->dpart, n->st)))
+      return hip_fail(n, e, "limiter");
     if ((r = lam_set_fields(s, d_fields, d_fields + N, d_n)) || (r = lam_step(s, anchor_steps)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
   }
+  return LAM_OK;
+}
+
+int lsn_set_limiter(lsn_net* n, float factor) {
+  if (!n) return fail(n, LAM_EINVAL, "null argument");
+  if (!isfinite(factor)) return fail(n, LAM_EINVAL, "limiter factor must be finite");
+  n->lim_factor = factor > 0.f ? factor : 0.f;
   return LAM_OK;
 }
 

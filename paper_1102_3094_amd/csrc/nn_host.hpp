@@ -77,6 +77,11 @@ hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, 
                        float b2, float eps, float c1, float c2, float gscale, hipStream_t st);
 hipError_t launch_make_target(const float* e, const float* l, int nout, size_t npix, const float* s,
                               float* t, hipStream_t st);
+// Rollout limiter: *out = max |x| (part: ceil(n / 256) doubles); phi clamped to +-factor * *bound
+// with the removed excess spread evenly so that sum phi is unchanged (part: ceil(n/256) + 1).
+hipError_t launch_absmax(const float* x, size_t n, double* part, double* out, hipStream_t st);
+hipError_t launch_clamp_conserve(float* phi, size_t n, const double* bound, float factor,
+                                 double* part, hipStream_t st);
 // part: at least 2 (ceil(npix / 256) + 1) doubles
 hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
                         double* part, hipStream_t st);

@@ -686,8 +686,8 @@ __global__ __launch_bounds__(256) void sum_f32_kernel(const float* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
 }
 
-// Mean of the phi increment: fixed-order tree over the per-block sums (one workgroup), written to
-// part[nblk].
+// Mean of the per-block sums (phi increment, density increment or clamp excess): fixed-order tree
+// over the blocks (one workgroup), written to part[nblk].
 __global__ __launch_bounds__(256) void mean_kernel(double* __restrict__ part, int nblk, size_t npix) {
   __shared__ double sm[256];
   double s = 0.0;
@@ -714,6 +714,55 @@ __global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ ou
   f[npix + p] += out[npix + p] * s1;
   f[2 * npix + p] += out[2 * npix + p] * s2;
   if (nout > 3) f[4 * npix + p] += (out[3 * npix + p] - (float)*mean_n) * s3;
+}
+
+// Order-parameter limiter of a rollout.  absmax: per-block max |phi| into part, then the block
+// maxima into part[nblk] (one workgroup, fixed order).
+__global__ __launch_bounds__(256) void absmax_f32_kernel(const float* __restrict__ x, size_t n,
+                                                         double* __restrict__ part) {
+  __shared__ double sm[4];
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double m = i < n ? fabs((double)x[i]) : 0.0;
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+__global__ __launch_bounds__(256) void max_final_kernel(double* __restrict__ part, int nblk,
+                                                        double* __restrict__ out) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, part[b]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+// phi <- clamp(phi, -b, b) with b = factor * (*bound); per-block FP64 sums of the removed excess.
+__global__ __launch_bounds__(256) void clamp_excess_kernel(float* __restrict__ phi, size_t n,
+                                                           const double* __restrict__ bound,
+                                                           float factor, double* __restrict__ part) {
+  __shared__ double sm[4];
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (i < n) {
+    const float b = factor * (float)*bound, v = phi[i];
+    const float c = fminf(fmaxf(v, -b), b);
+    phi[i] = c;
+    e = (double)v - (double)c;
+  }
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+// phi += mean excess (part[nblk]): the clamped field keeps its sum.
+__global__ void add_mean_kernel(float* __restrict__ phi, size_t n, const double* __restrict__ mean) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) phi[i] += (float)*mean;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -928,6 +977,21 @@ hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const
   hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, nout, npix, s[0], s[1], s[2],
                      nout > 3 ? s[3] : 0.f, (const double*)(part + nb),
                      (const double*)(part_n + nb));
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const float* x, size_t n, double* part, double* out, hipStream_t st) {
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(absmax_f32_kernel, nb, 256, 0, st, x, n, part);
+  hipLaunchKernelGGL(max_final_kernel, 1, 256, 0, st, part, nb, out);
+  return hipGetLastError();
+}
+hipError_t launch_clamp_conserve(float* phi, size_t n, const double* bound, float factor,
+                                 double* part, hipStream_t st) {
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(clamp_excess_kernel, nb, 256, 0, st, phi, n, bound, factor, part);
+  hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part, nb, n);
+  hipLaunchKernelGGL(add_mean_kernel, nb, 256, 0, st, phi, n, (const double*)(part + nb));
   return hipGetLastError();
 }
 

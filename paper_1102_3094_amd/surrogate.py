@@ -10,7 +10,7 @@ from . import LAM_OK, LamError, load
 SURROGATE_EXPORTS = ("lsn_param_count", "lsn_workspace_bytes", "lsn_create", "lsn_set_params",
                      "lsn_get_params", "lsn_forward", "lsn_advance", "lsn_make_target",
                      "lsn_zero_grad", "lsn_loss_backward", "lsn_get_grads", "lsn_adam",
-                     "lsn_rollout", "lsn_tune", "lsn_get_shapes", "lsn_set_timing", "lsn_forward_time", "lsn_last_error",
+                     "lsn_rollout", "lsn_set_limiter", "lsn_tune", "lsn_get_shapes", "lsn_set_timing", "lsn_forward_time", "lsn_last_error",
                      "lsn_destroy")
 
 
@@ -41,6 +41,7 @@ def lib():
     L.lsn_loss_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
     L.lsn_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float]
     L.lsn_rollout.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.lsn_set_limiter.argtypes = [vp, C.c_float]
     L.lsn_tune.argtypes = [vp, vp, C.c_int32]
     L.lsn_get_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     L.lsn_set_timing.argtypes = [vp, C.c_int32]
@@ -196,6 +197,11 @@ class Surrogate:
         self._chk(lib().lsn_rollout(self._h, sim._h, C.c_void_p(fields_scratch.data_ptr()),
                                     int(cycles), int(calls), int(steps_per_call), int(anchor_steps)))
         return sim
+
+    def set_limiter(self, factor=1.05):
+        """Order-parameter limiter of rollout(); factor <= 0 turns it off."""
+        self._chk(lib().lsn_set_limiter(self._h, float(factor)))
+        return self
 
     def tune(self, fields, reps=3):
         f = self._t(fields, (self.NF, self.H, self.W))

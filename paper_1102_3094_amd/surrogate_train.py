@@ -140,8 +140,9 @@ def peak(sim, nbins=None):
 
 
 def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=100,
-             anchor_steps=100, zero_net: Surrogate | None = None, device="cuda:0"):
-    """Plain solver against the surrogate-accelerated rollout from the same state at step t0."""
+             anchor_steps=100, zero_net: Surrogate | None = None, device="cuda:0", limiter=1.05):
+    """Plain solver against the surrogate-accelerated rollout from the same state at step t0
+    (`limiter`: the rollout's order-parameter limiter factor, 0 for none)."""
     import torch
     total = cycles * (calls * steps_per_call + anchor_steps)
     start = Sim(params, device=device).init_fields(torch.tensor(phi0, dtype=torch.float32)).step(t0)
@@ -180,6 +181,7 @@ def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=
     for name, n in (("surrogate", net), ("no_network", zero_net)):
         if n is None:
             continue
+        n.set_limiter(limiter)
         s = fresh()
         n.rollout(s, scratch, 1, calls, steps_per_call, 0)   # warm-up of the launch path
         s = fresh()

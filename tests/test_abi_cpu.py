@@ -56,12 +56,19 @@ offsetof(lam_params, n_phi_sub), sizeof(lam_obs), offsetof(lam_obs, step)); retu
 
 @pytest.mark.parametrize("bad", [dict(tau=0.5), dict(b=0.0), dict(c=-1.0), dict(nx=4),
                                  dict(dim=4), dict(force_form=3), dict(pop_storage=2),
-                                 dict(n_phi_sub=1), dict(n_T_sub=1, xi=1.0)])
+                                 dict(n_phi_sub=1), dict(n_T_sub=1, xi=1.0),
+                                 dict(nx=32768, ny=32768),                 # N 4 B = 2^32
+                                 dict(nx=65536, ny=32768, pop_storage=1)])  # N 2 B = 2^32
 def test_invalid_parameters_rejected(L, bad):
     p = S.model_params("c1_64sq", **bad)
     with pytest.raises(lam.LamError) as e:
         lam.workspace_bytes(p)
     assert e.value.code == lam.LAM_EINVAL
+
+
+def test_largest_2d_lattice_accepted(L):
+    """Just below the 32-bit plane-offset limit of the D2Q9 step kernel (sizing only)."""
+    assert lam.workspace_bytes(S.model_params("c1_64sq", nx=32768, ny=32767)) > 0
 
 
 def test_unstable_override_allowed_when_forced(L):

@@ -220,7 +220,7 @@ def test_rollout_graph_and_direct_paths_agree(gpu):
     results = []
     for use_stream in (True, False):
         st = torch.cuda.Stream() if use_stream else torch.cuda.current_stream()
-        net = Surrogate(H, W, stream=st, **CFG).set_params(dev(th))
+        net = Surrogate(H, W, stream=st, **CFG).set_params(dev(th)).set_limiter(0)
         sim = gpu.Sim(p, stream=st).set_state(state)
         scratch = torch.empty((4, H, W), dtype=torch.float32, device="cuda")
         net.rollout(sim, scratch, cycles=2, calls=3, steps_per_call=100, anchor_steps=20)
@@ -361,7 +361,7 @@ def test_density_rollout_reanchors_with_predicted_density(gpu):
     phi0 = torch.tensor(S.phi0((H, W), seed=5), dtype=torch.float32)
     state = gpu.Sim(p).init_fields(phi0).step(200).get_state()
     st = torch.cuda.Stream()
-    net = make_n(H, W, stream=st).set_params(dev(th))
+    net = make_n(H, W, stream=st).set_params(dev(th)).set_limiter(0)
     sim = gpu.Sim(p, stream=st).set_state(state)
     scratch = torch.empty((5, H, W), dtype=torch.float32, device="cuda")
     net.rollout(sim, scratch, cycles=2, calls=3, steps_per_call=100, anchor_steps=20)
@@ -381,3 +381,40 @@ def test_density_rollout_reanchors_with_predicted_density(gpu):
     want = ref.fields()
     assert torch.equal(got["phi"], want["phi"]) and torch.equal(got["n"], want["n"])
     assert not sim.observables()["nonfinite"]
+
+
+def test_rollout_limiter_clamps_and_conserves(gpu):
+    """With the limiter on, phi handed to the solver at re-anchoring is clamped to 1.05 x the
+    max |phi| at the start of the call, with the excess spread evenly (sum phi unchanged): the
+    same as single calls followed by that clamp, computed here in FP64."""
+    from paper_1102_3094_amd.surrogate import Surrogate
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    th = params(widths)
+    th[-(3 * 32 + 3):] *= 4.0          # large increments: the clamp is active
+    p = S.model_params("c1_64sq", nx=W, ny=H, Tw=0.95, tau=1.5, xi=-1.0)
+    phi0 = torch.tensor(S.phi0((H, W), seed=5), dtype=torch.float32)
+    state = gpu.Sim(p).init_fields(phi0).step(200).get_state()
+    st = torch.cuda.Stream()
+    net = Surrogate(H, W, stream=st, **CFG).set_params(dev(th))
+    sim = gpu.Sim(p, stream=st).set_state(state)
+    scratch = torch.empty((4, H, W), dtype=torch.float32, device="cuda")
+    net.rollout(sim, scratch, cycles=1, calls=3, steps_per_call=100, anchor_steps=0)
+    st.synchronize()
+    got = sim.fields()["phi"].double()
+    ref = gpu.Sim(p).set_state(state)
+    buf = torch.empty((4, H, W), dtype=torch.float32, device="cuda")
+    ref.fields_into(buf)
+    bound = 1.05 * float(buf[0].abs().max())
+    s0 = buf[0].double().sum()
+    net2 = Surrogate(H, W, **CFG).set_params(dev(th))
+    for _ in range(3):
+        net2.advance(buf)
+    torch.cuda.synchronize()
+    raw = buf[0].double()
+    assert raw.abs().max() > 1.1 * bound            # the clamp has work to do
+    clamped = raw.clamp(-bound, bound)
+    want = clamped + (raw.sum() - clamped.sum()) / raw.numel()
+    print(f"limiter: raw max {float(raw.abs().max()):.3f}, bound {bound:.3f}, "
+          f"max diff {float((got - want).abs().max()):.2e}")
+    assert torch.allclose(got, want, rtol=0, atol=2e-6)
+    assert abs(float(got.sum() - s0)) < 1e-6 * H * W
