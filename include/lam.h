@@ -53,7 +53,7 @@ extern "C" {
 
 typedef struct lam_params {
   int32_t dim;               /* 2 (D2Q9) or 3 (D3Q19)                                              */
-  int32_t nx, ny, nz;        /* lattice extents; nz = 1 in 2D; each >= 8; in 2D nx ny times the
+  int32_t nx, ny, nz;        /* lattice extents; nz = 1 in 2D; each >= 8; the site count times the
                               * population size (4 or 2 bytes) below 2^32                          */
   int32_t walls;             /* 1: cold walls on the first and last layer of the last axis        */
   int32_t hydro;             /* 1: lattice Boltzmann coupled; 0: phi and T only (Section 3 runs) */

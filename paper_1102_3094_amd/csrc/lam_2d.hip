@@ -41,18 +41,6 @@ struct Lb2dSmem {
 constexpr int lb2d_spt(int ty) { return 64 * ty / 2 > 1024 ? 4 : 2; }
 constexpr int lb2d_threads(int ty) { return 64 * ty / lb2d_spt(ty); }
 
-// Element `i` of the plane starting at `base`, addressed as base + a 32-bit byte offset (planes of
-// the 2D lattice hold fewer than 2^30 sites): the plane base is uniform, so the access takes the
-// scalar-base form with one 32-bit vector offset instead of 64-bit vector address arithmetic.
-template <typename T>
-__device__ __forceinline__ T* plane_at(T* base, uint32_t i) {
-  return (T*)((char*)base + i * (uint32_t)sizeof(T));
-}
-template <typename T>
-__device__ __forceinline__ const T* plane_at(const T* base, uint32_t i) {
-  return (const T*)((const char*)base + i * (uint32_t)sizeof(T));
-}
-
 // Pull of the 9 populations of site (x, y): f_q(x) = f*_q(x - e_q); across a wall the opposite
 // population of x itself (halfway bounce-back).
 template <typename ST>

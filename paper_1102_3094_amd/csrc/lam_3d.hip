@@ -1,7 +1,7 @@
 // lam_3d.hip -- gfx950 kernels of one D3Q19 time step (arXiv:1102.3094, Section 2, with the
 // standard three-dimensional velocity set; walls normal to z).
 //
-// Both kernels march along z over a 32 x 8 xy tile ("2.5D" blocking): LDS holds a few xy slices
+// Both kernels march along z over a 64 x 8 xy tile ("2.5D" blocking): LDS holds a few xy slices
 // of each field in ring buffers, so the 7-point Laplacian, the 25-point biharmonic and the
 // pressure-tensor divergence need halos only in x and y.  A workgroup owns a chunk of ZCH
 // slices and starts the pipeline a few slices early.
@@ -19,7 +19,7 @@
 
 namespace lam {
 
-constexpr int BX = 32, BY = 8, NT3 = BX * BY;
+constexpr int BX = 64, BY = 8, NT3 = BX * BY;
 constexpr int ZCH = 32;  // z slices per workgroup
 enum { MODE3_STEP = 0, MODE3_OBS = 1, MODE3_FIELDS = 2 };
 
@@ -51,9 +51,12 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P) {
 
 struct Lb3dSmem {
   int rowoff[BY + 6], colx[BX + 6];  // y * nx and x of the halo-3 xy tile (periodic)
+  float a[ZCH + 6];                  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
   float phi[5][BY + 6][BX + 6];
-  float L[4][BY + 4][BX + 4];
-  float P[4][6][BY + 2][BX + 2];  // xx, yy, zz, xy, xz, yz (or mu in [0] for -phi grad mu)
+  // L and P rings of 3: a slice's slot is rewritten only after the barrier that follows the last
+  // phase reading it, so three slots suffice and the workgroup fits four to a compute unit
+  float L[3][BY + 4][BX + 4];
+  float P[3][6][BY + 2][BX + 2];  // xx, yy, zz, xy, xz, yz (or mu in [0] for -phi grad mu)
   double red[NT3 / 64][R_N];
 };
 
@@ -80,38 +83,49 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
   float g[19];
 
-  for (int i = tid; i < (BY + 6) + (BX + 6); i += NT3) {
-    if (i < BY + 6) S.rowoff[i] = wrap(T.y0 - 3 + i, ny) * nx;
-    else S.colx[i - (BY + 6)] = wrap(T.x0 - 3 + (i - (BY + 6)), nx);
+  static_assert(NT3 >= (BY + 6) + (BX + 6) + ZCH + 6, "one pass fills the tables");
+  if (tid < BY + 6) {
+    S.rowoff[tid] = wrap(T.y0 - 3 + tid, ny) * nx;
+  } else if (tid < (BY + 6) + (BX + 6)) {
+    S.colx[tid - (BY + 6)] = wrap(T.x0 - 3 + (tid - (BY + 6)), nx);
+  } else if (tid < (BY + 6) + (BX + 6) + ZCH + 6) {
+    const int i = tid - (BY + 6) - (BX + 6);
+    bool f;
+    S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
   }
   __syncthreads();
-  // phi slices are loaded into registers one iteration before they are stored to LDS
+  // phi slices are loaded into registers two iterations before they are stored to LDS (two
+  // register buffers by iteration parity).  The memory counter drains in issue order: the pulls
+  // of an iteration are issued before its phi prefetch, so the collision waits for the pulls
+  // only, and the phi store of the next iteration only for the prefetch issued two iterations
+  // back.  The phi loads are unconditional (clamped index) and a comes from LDS so that no
+  // branch or late load forces an earlier wait.
   constexpr int CPH = (BY + 6) * (BX + 6), IPH = (CPH + NT3 - 1) / NT3;
-  float pv[IPH];
-  auto load_phi = [&](int sl) {
+  float pv[2][IPH];
+  auto load_phi = [&](int sl, float(&pb)[IPH]) {
     bool f;
     const size_t zoff = (size_t)wall_axis(sl, nz, P.walls, f) * plane;
 #pragma unroll
     for (int j = 0; j < IPH; ++j) {
-      const int i = tid + j * NT3;
-      if (i < CPH) {
-        const int r = i / (BX + 6), c = i - r * (BX + 6);
-        pv[j] = phi[zoff + S.rowoff[r] + S.colx[c]];
-      }
+      const int i = min(tid + j * NT3, CPH - 1);
+      const int r = i / (BX + 6), c = i - r * (BX + 6);
+      pb[j] = phi[zoff + S.rowoff[r] + S.colx[c]];
     }
   };
-  load_phi(T.z0 - 3);
+  const int K = T.z1 - T.z0 + 6;
+  load_phi(T.z0 - 3, pv[0]);
+  load_phi(T.z0 - 2, pv[1]);
 
-  for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
+  auto iteration = [&](const int k, float(&pb)[IPH]) {
     const int s_load = T.z0 - 3 + k, s_L = s_load - 1, s_P = s_load - 2, s_out = s_load - 3;
-    {  // phi slice s_load (loaded last iteration) into its ring slot
+    {  // phi slice s_load (loaded two iterations ago) into its ring slot
       float(*dst)[BX + 6] = S.phi[((s_load % 5) + 5) % 5];
 #pragma unroll
       for (int j = 0; j < IPH; ++j) {
         const int i = tid + j * NT3;
         if (i < CPH) {
           const int r = i / (BX + 6), c = i - r * (BX + 6);
-          dst[r][c] = pv[j];
+          dst[r][c] = pb[j];
         }
       }
     }
@@ -123,27 +137,27 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
       for (int q = 0; q < 19; ++q) {
         const int ex = E19[q][0], ey = E19[q][1], ez = E19[q][2];
         const int sz = z - ez;
-        size_t idx;
+        uint32_t idx;
         int qq = q;
-        if (P.walls && (sz < 0 || sz >= nz)) {
+        if (P.walls && (sz < 0 || sz >= nz)) {  // uniform: z is the workgroup's slice
           qq = opp19(q);
-          idx = ((size_t)z * ny + y) * nx + x;
+          idx = (uint32_t)((z * ny + y) * nx + x);
         } else {
           const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
           const int sy = ey == 1 ? ym : (ey == -1 ? yp : y);
           const int zz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
-          idx = ((size_t)zz * ny + sy) * nx + sx;
+          idx = (uint32_t)((zz * ny + sy) * nx + sx);
         }
-        g[q] = to_f32(gin[(size_t)qq * N + idx]);
+        g[q] = to_f32(*plane_at(gin + (size_t)qq * N, idx));
       }
     }
-    if (k + 1 < T.z1 - T.z0 + 6) load_phi(s_load + 1);
+    load_phi(s_load + 2, pb);
     __syncthreads();
     if (s_L >= T.z0 - 2) {  // L slice s_L with xy halo 2
       float(*pc)[BX + 6] = S.phi[((s_L % 5) + 5) % 5];
       float(*pd)[BX + 6] = S.phi[(((s_L - 1) % 5) + 5) % 5];
       float(*pu)[BX + 6] = S.phi[(((s_L + 1) % 5) + 5) % 5];
-      float(*dst)[BX + 4] = S.L[((s_L % 4) + 4) % 4];
+      float(*dst)[BX + 4] = S.L[((s_L % 3) + 3) % 3];
       for (int i = tid; i < (BY + 4) * (BX + 4); i += NT3) {
         int r = i / (BX + 4), c = i - r * (BX + 4);
         const int R = r + 1, C = c + 1;
@@ -153,16 +167,14 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
     }
     __syncthreads();
     if (P.hydro && s_P >= T.z0 - 1) {  // pressure tensor (or mu) of slice s_P with xy halo 1
-      bool f;
-      const int gz = wall_axis(s_P, nz, P.walls, f);
-      const float a = (Trow[gz] - P.Tc) / P.Tc;
+      const float a = S.a[s_P - (T.z0 - 3)];
       float(*pc)[BX + 6] = S.phi[((s_P % 5) + 5) % 5];
       float(*pd)[BX + 6] = S.phi[(((s_P - 1) % 5) + 5) % 5];
       float(*pu)[BX + 6] = S.phi[(((s_P + 1) % 5) + 5) % 5];
-      float(*lc)[BX + 4] = S.L[((s_P % 4) + 4) % 4];
-      float(*ld)[BX + 4] = S.L[(((s_P - 1) % 4) + 4) % 4];
-      float(*lu)[BX + 4] = S.L[(((s_P + 1) % 4) + 4) % 4];
-      float(*dst)[BY + 2][BX + 2] = S.P[((s_P % 4) + 4) % 4];
+      float(*lc)[BX + 4] = S.L[((s_P % 3) + 3) % 3];
+      float(*ld)[BX + 4] = S.L[(((s_P - 1) % 3) + 3) % 3];
+      float(*lu)[BX + 4] = S.L[(((s_P + 1) % 3) + 3) % 3];
+      float(*dst)[BY + 2][BX + 2] = S.P[((s_P % 3) + 3) % 3];
       for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
         int r = i / (BX + 2), c = i - r * (BX + 2);
         const int R = r + 2, C = c + 2, r1 = r + 1, c1 = c + 1;
@@ -194,9 +206,9 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
     __syncthreads();
     if (do_out) {
       const int z = s_out, r = ty + 1, c = tx + 1;
-      float(*Pc)[BY + 2][BX + 2] = S.P[((z % 4) + 4) % 4];
-      float(*Pd)[BY + 2][BX + 2] = S.P[(((z - 1) % 4) + 4) % 4];
-      float(*Pu)[BY + 2][BX + 2] = S.P[(((z + 1) % 4) + 4) % 4];
+      float(*Pc)[BY + 2][BX + 2] = S.P[((z % 3) + 3) % 3];
+      float(*Pd)[BY + 2][BX + 2] = S.P[(((z - 1) % 3) + 3) % 3];
+      float(*Pu)[BY + 2][BX + 2] = S.P[(((z + 1) % 3) + 3) % 3];
       float(*pc)[BX + 6] = S.phi[((z % 5) + 5) % 5];
       float Fx = 0.f, Fy = 0.f, Fz = 0.f;
       if (P.hydro) {
@@ -233,7 +245,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
         uy = (jy + 0.5f * Fy) * inv;
         uz = (jz + 0.5f * Fz) * inv;
       }
-      const size_t s = ((size_t)z * ny + y) * nx + x;
+      const uint32_t s = (uint32_t)((z * ny + y) * nx + x);
       if (MODE == MODE3_STEP) {
         const float usq = 1.5f * (ux * ux + uy * uy + uz * uz);
         const float uF = ux * Fx + uy * Fy + uz * Fz;
@@ -245,23 +257,21 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
           const float eF = E19[q][0] * Fx + E19[q][1] * Fy + E19[q][2] * Fz;
           const float geq = w * (dn + n * (eu * (3.f + 4.5f * eu) - usq));
           const float frc = kf * w * (3.f * (eF - uF) + 9.f * eu * eF);
-          gout[(size_t)q * N + s] = from_f32<ST>(g[q] + om * (geq - g[q]) + frc);
+          *plane_at(gout + (size_t)q * N, s) = from_f32<ST>(g[q] + om * (geq - g[q]) + frc);
         }
-        uout[s] = ux;
-        uout[N + s] = uy;
-        uout[2 * N + s] = uz;
+        *plane_at(uout, s) = ux;
+        *plane_at(uout + N, s) = uy;
+        *plane_at(uout + 2 * N, s) = uz;
       } else if (MODE == MODE3_FIELDS) {
-        uout[s] = ux;
-        uout[N + s] = uy;
-        uout[2 * N + s] = uz;
-        if (nout) nout[s] = n;
+        *plane_at(uout, s) = ux;
+        *plane_at(uout + N, s) = uy;
+        *plane_at(uout + 2 * N, s) = uz;
+        if (nout) *plane_at(nout, s) = n;
       } else {
-        bool f;
-        const int gz = wall_axis(z, nz, P.walls, f);
-        const float a = (Trow[gz] - P.Tc) / P.Tc;
+        const float a = S.a[z - (T.z0 - 3)];
         float(*pu)[BX + 6] = S.phi[(((z + 1) % 5) + 5) % 5];
         const float ph = pc[ty + 3][tx + 3];
-        const float L = S.L[((z % 4) + 4) % 4][ty + 2][tx + 2];
+        const float L = S.L[((z % 3) + 3) % 3][ty + 2][tx + 2];
         const float dx = pc[ty + 3][tx + 4] - ph, dy = pc[ty + 4][tx + 3] - ph,
                     dz = pu[ty + 3][tx + 3] - ph;
         const float fe = 0.5f * a * ph * ph + 0.25f * P.b * ph * ph * ph * ph +
@@ -277,6 +287,10 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
           acc[R_BAD] = 1.0;
       }
     }
+  };
+  for (int k = 0; k < K; k += 2) {
+    iteration(k, pv[0]);
+    if (k + 1 < K) iteration(k + 1, pv[1]);
   }
 
   if (MODE == MODE3_OBS) {
@@ -298,12 +312,15 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
 
 // ------------------------------------------------------------------------------------------------
 // psi ring of 6: the load of slice z + 4 must not overwrite slice z - 1, which slower threads may
-// still read for the output slice z of the previous iteration (no barrier between them).
+// still read for the output slice z of the previous iteration (no barrier between them).  mu and u
+// are written after the iteration's first barrier, so rings of 3 suffice for them.
+template <bool HYDRO>
 struct Phi3dSmem {
   int rowoff[BY + 6], colx[BX + 6];
+  float a[ZCH + 6];  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
   float psi[6][BY + 6][BX + 6];
-  float mu[4][BY + 2][BX + 2];
-  float u[4][3][BY + 2][BX + 2];
+  float mu[3][BY + 2][BX + 2];
+  float u[HYDRO ? 3 : 1][3][BY + 2][BX + 2];
 };
 
 template <bool HYDRO>
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
                                                     const float* __restrict__ Trow,
                                                     float* __restrict__ Tnext,
                                                     float* __restrict__ Tscr, int do_T) {
-  __shared__ Phi3dSmem S;
+  __shared__ Phi3dSmem<HYDRO> S;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const size_t plane = (size_t)nx * ny, N = plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
@@ -321,84 +338,91 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
 
-  for (int i = tid; i < (BY + 6) + (BX + 6); i += NT3) {
-    if (i < BY + 6) S.rowoff[i] = wrap(T.y0 - 3 + i, ny) * nx;
-    else S.colx[i - (BY + 6)] = wrap(T.x0 - 3 + (i - (BY + 6)), nx);
+  static_assert(NT3 >= (BY + 6) + (BX + 6) + ZCH + 6, "one pass fills the tables");
+  if (tid < BY + 6) {
+    S.rowoff[tid] = wrap(T.y0 - 3 + tid, ny) * nx;
+  } else if (tid < (BY + 6) + (BX + 6)) {
+    S.colx[tid - (BY + 6)] = wrap(T.x0 - 3 + (tid - (BY + 6)), nx);
+  } else if (tid < (BY + 6) + (BX + 6) + ZCH + 6) {
+    const int i = tid - (BY + 6) - (BX + 6);
+    bool f;
+    S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
   }
   __syncthreads();
-  // psi slice s and u slice s - 2 are loaded into registers one iteration before their LDS store
+  // psi slice s and u slice s - 2 are loaded into registers two iterations before their LDS
+  // store (two register buffers, selected by the parity of the iteration): the memory counter of
+  // a wave drains in issue order, so the stores of iteration k wait only for the loads issued at
+  // k - 2 while those of k - 1 stay in flight.  Every load is unconditional (clamped index, a
+  // u slice is fetched and stored even where it goes unused, the last two iterations prefetch a
+  // slice they do not need) so that no branch forces an early wait; the per-slice a comes from
+  // LDS for the same reason.
   constexpr int CPS = (BY + 6) * (BX + 6), IPS = (CPS + NT3 - 1) / NT3;
   constexpr int CUS = (BY + 2) * (BX + 2), IUS = (CUS + NT3 - 1) / NT3;
-  float pv[IPS], uv[3][IUS];
-  auto load = [&](int sl) {
+  float pv[2][IPS], uv[2][3][IUS];
+  auto load = [&](int sl, float(&pb)[IPS], float(&ub)[3][IUS]) {
     bool f;
     const size_t zoff = (size_t)wall_axis(sl, nz, P.walls, f) * plane;
 #pragma unroll
     for (int j = 0; j < IPS; ++j) {
-      const int i = tid + j * NT3;
-      if (i < CPS) {
-        const int r = i / (BX + 6), c = i - r * (BX + 6);
-        pv[j] = psi_in[zoff + S.rowoff[r] + S.colx[c]];
-      }
+      const int i = min(tid + j * NT3, CPS - 1);
+      const int r = i / (BX + 6), c = i - r * (BX + 6);
+      pb[j] = psi_in[zoff + S.rowoff[r] + S.colx[c]];
     }
-    const int su = sl - 2;
-    if (HYDRO && su >= T.z0 - 1) {
+    if (HYDRO) {
       bool fl;
-      const size_t uoff = (size_t)wall_axis(su, nz, P.walls, fl) * plane;
+      const size_t uoff = (size_t)wall_axis(sl - 2, nz, P.walls, fl) * plane;
       const float sg = fl ? -1.f : 1.f;
 #pragma unroll
       for (int j = 0; j < IUS; ++j) {
-        const int i = tid + j * NT3;
-        if (i < CUS) {
-          const int r = i / (BX + 2), c = i - r * (BX + 2);
-          const size_t s = uoff + S.rowoff[r + 2] + S.colx[c + 2];
-          uv[0][j] = u[s];
-          uv[1][j] = u[N + s];
-          uv[2][j] = sg * u[2 * N + s];
-        }
+        const int i = min(tid + j * NT3, CUS - 1);
+        const int r = i / (BX + 2), c = i - r * (BX + 2);
+        const size_t s = uoff + S.rowoff[r + 2] + S.colx[c + 2];
+        ub[0][j] = u[s];
+        ub[1][j] = u[N + s];
+        ub[2][j] = sg * u[2 * N + s];
       }
     }
   };
-  load(T.z0 - 3);
+  const int K = T.z1 - T.z0 + 6;
+  load(T.z0 - 3, pv[0], uv[0]);
+  load(T.z0 - 2, pv[1], uv[1]);
 
-  for (int k = 0; k < T.z1 - T.z0 + 6; ++k) {
+  auto iteration = [&](const int k, float(&pb)[IPS], float(&ub)[3][IUS]) {
     const int s_load = T.z0 - 3 + k, s_mu = s_load - 2, s_out = s_load - 3;
-    {  // psi slice s_load (xy halo 3); u slice s_mu (xy halo 1, normal component odd)
+    {  // psi slice s_load (xy halo 3)
       float(*dst)[BX + 6] = S.psi[((s_load % 6) + 6) % 6];
 #pragma unroll
       for (int j = 0; j < IPS; ++j) {
         const int i = tid + j * NT3;
         if (i < CPS) {
           const int r = i / (BX + 6), c = i - r * (BX + 6);
-          dst[r][c] = pv[j];
-        }
-      }
-      if (HYDRO && s_mu >= T.z0 - 1) {
-        float(*ud)[BY + 2][BX + 2] = S.u[((s_mu % 4) + 4) % 4];
-#pragma unroll
-        for (int j = 0; j < IUS; ++j) {
-          const int i = tid + j * NT3;
-          if (i < CUS) {
-            const int r = i / (BX + 2), c = i - r * (BX + 2);
-            ud[0][r][c] = uv[0][j];
-            ud[1][r][c] = uv[1][j];
-            ud[2][r][c] = uv[2][j];
-          }
+          dst[r][c] = pb[j];
         }
       }
     }
-    if (k + 1 < T.z1 - T.z0 + 6) load(s_load + 1);
     __syncthreads();
+    if (HYDRO) {  // u slice s_mu (xy halo 1, normal component odd)
+      float(*ud)[BY + 2][BX + 2] = S.u[((s_mu % 3) + 3) % 3];
+#pragma unroll
+      for (int j = 0; j < IUS; ++j) {
+        const int i = tid + j * NT3;
+        if (i < CUS) {
+          const int r = i / (BX + 2), c = i - r * (BX + 2);
+          ud[0][r][c] = ub[0][j];
+          ud[1][r][c] = ub[1][j];
+          ud[2][r][c] = ub[2][j];
+        }
+      }
+    }
+    load(s_load + 2, pb, ub);
     if (s_mu >= T.z0 - 1) {  // mu of slice s_mu with xy halo 1 (25-point biharmonic)
-      bool f;
-      const int gz = wall_axis(s_mu, nz, P.walls, f);
-      const float a = (Trow[gz] - P.Tc) / P.Tc;
+      const float a = S.a[s_mu - (T.z0 - 3)];
       float(*c0)[BX + 6] = S.psi[((s_mu % 6) + 6) % 6];
       float(*m1)[BX + 6] = S.psi[(((s_mu - 1) % 6) + 6) % 6];
       float(*p1)[BX + 6] = S.psi[(((s_mu + 1) % 6) + 6) % 6];
       float(*m2)[BX + 6] = S.psi[(((s_mu - 2) % 6) + 6) % 6];
       float(*p2)[BX + 6] = S.psi[(((s_mu + 2) % 6) + 6) % 6];
-      float(*dst)[BX + 2] = S.mu[((s_mu % 4) + 4) % 4];
+      float(*dst)[BX + 2] = S.mu[((s_mu % 3) + 3) % 3];
       for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
         int r = i / (BX + 2), cc = i - r * (BX + 2);
         const int R = r + 2, C = cc + 2;
@@ -418,9 +442,9 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
     __syncthreads();
     if (s_out >= T.z0 && in_xy) {
       const int z = s_out, r = ty + 1, c = tx + 1, R = ty + 3, C = tx + 3;
-      float(*mc)[BX + 2] = S.mu[((z % 4) + 4) % 4];
-      float(*md)[BX + 2] = S.mu[(((z - 1) % 4) + 4) % 4];
-      float(*mu_)[BX + 2] = S.mu[(((z + 1) % 4) + 4) % 4];
+      float(*mc)[BX + 2] = S.mu[((z % 3) + 3) % 3];
+      float(*md)[BX + 2] = S.mu[(((z - 1) % 3) + 3) % 3];
+      float(*mu_)[BX + 2] = S.mu[(((z + 1) % 3) + 3) % 3];
       float(*pc)[BX + 6] = S.psi[((z % 6) + 6) % 6];
       float(*pd)[BX + 6] = S.psi[(((z - 1) % 6) + 6) % 6];
       float(*pu)[BX + 6] = S.psi[(((z + 1) % 6) + 6) % 6];
@@ -428,15 +452,19 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
                           (mu_[r][c] + md[r][c]) - 6.f * mc[r][c];
       float adv = 0.f;
       if (HYDRO) {
-        float(*uc)[BY + 2][BX + 2] = S.u[((z % 4) + 4) % 4];
-        float(*ud)[BY + 2][BX + 2] = S.u[(((z - 1) % 4) + 4) % 4];
-        float(*uu)[BY + 2][BX + 2] = S.u[(((z + 1) % 4) + 4) % 4];
+        float(*uc)[BY + 2][BX + 2] = S.u[((z % 3) + 3) % 3];
+        float(*ud)[BY + 2][BX + 2] = S.u[(((z - 1) % 3) + 3) % 3];
+        float(*uu)[BY + 2][BX + 2] = S.u[(((z + 1) % 3) + 3) % 3];
         adv = 0.5f * (pc[R][C + 1] * uc[0][r][c + 1] - pc[R][C - 1] * uc[0][r][c - 1]) +
               0.5f * (pc[R + 1][C] * uc[1][r + 1][c] - pc[R - 1][C] * uc[1][r - 1][c]) +
               0.5f * (pu[R][C] * uu[2][r][c] - pd[R][C] * ud[2][r][c]);
       }
       psi_out[((size_t)z * ny + y) * nx + x] = pc[R][C] + P.h * (-adv + P.Gamma * lapmu);
     }
+  };
+  for (int k = 0; k < K; k += 2) {
+    iteration(k, pv[0], uv[0]);
+    if (k + 1 < K) iteration(k + 1, pv[1], uv[1]);
   }
 
   // Temperature: FTCS sub-steps along z (T is uniform in x and y); wall layers held.

@@ -176,9 +176,9 @@ int validate(const lam_params* p, std::string& why) {
   if (p->dim != 2 && p->dim != 3) return why = "dim must be 2 or 3", LAM_EINVAL;
   if (p->nx < 8 || p->ny < 8) return why = "nx and ny must be >= 8", LAM_EINVAL;
   if (p->dim == 2 && p->nz != 1) return why = "nz must be 1 in 2D", LAM_EINVAL;
-  // the D2Q9 step kernel addresses each population plane with 32-bit byte offsets
-  if (p->dim == 2 && (double)p->nx * p->ny * (p->pop_storage ? 2 : 4) >= 4294967296.0)
-    return why = "2D lattice too large: a population plane must stay below 2^32 bytes", LAM_EINVAL;
+  // the step kernels address each population plane with 32-bit byte offsets
+  if ((double)p->nx * p->ny * (p->dim == 3 ? p->nz : 1) * (p->pop_storage ? 2 : 4) >= 4294967296.0)
+    return why = "lattice too large: a population plane must stay below 2^32 bytes", LAM_EINVAL;
   if (p->dim == 3 && p->nz < 8) return why = "nz must be >= 8 in 3D", LAM_EINVAL;
   if (!(p->tau > 0.5)) return why = "tau must exceed 1/2", LAM_EINVAL;
   if (!(p->b > 0) || !(p->c > 0)) return why = "b and c must be positive (Section 2)", LAM_EINVAL;

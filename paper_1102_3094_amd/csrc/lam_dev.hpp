@@ -37,6 +37,18 @@ template <>
 __device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half_rn(v); }
 
 // Streaming (non-temporal) access to the population fields, which are not re-read within a step.
+// Element `i` of the plane starting at `base`, addressed as base + a 32-bit byte offset (the host
+// keeps every population plane below 2^32 bytes): the plane base is uniform, so the access takes
+// the scalar-base form with one 32-bit vector offset instead of 64-bit vector address arithmetic.
+template <typename T>
+__device__ __forceinline__ T* plane_at(T* base, uint32_t i) {
+  return (T*)((char*)base + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T* plane_at(const T* base, uint32_t i) {
+  return (const T*)((const char*)base + i * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ __half ld_nt(const __half* p) {
   return __ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p));

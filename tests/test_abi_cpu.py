@@ -58,7 +58,8 @@ offsetof(lam_params, n_phi_sub), sizeof(lam_obs), offsetof(lam_obs, step)); retu
                                  dict(dim=4), dict(force_form=3), dict(pop_storage=2),
                                  dict(n_phi_sub=1), dict(n_T_sub=1, xi=1.0),
                                  dict(nx=32768, ny=32768),                 # N 4 B = 2^32
-                                 dict(nx=65536, ny=32768, pop_storage=1)])  # N 2 B = 2^32
+                                 dict(nx=65536, ny=32768, pop_storage=1),   # N 2 B = 2^32
+                                 dict(dim=3, nx=1024, ny=1024, nz=1024)])   # N 4 B = 2^32
 def test_invalid_parameters_rejected(L, bad):
     p = S.model_params("c1_64sq", **bad)
     with pytest.raises(lam.LamError) as e:
