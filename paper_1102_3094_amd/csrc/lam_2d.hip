@@ -361,46 +361,41 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
   }
   __syncthreads();
 
-  // Tile loads: every load of a thread is issued before its LDS stores (overlapped latency).
+  // Tile loads: psi, then the velocity, all issued before any LDS store; every load is
+  // unconditional (clamped index) and its value is not touched until it is stored.  The memory
+  // counter drains in issue order, so the psi stores wait for psi alone, and the velocity (which
+  // the first mu phase does not need) is stored to LDS only after that phase, its loads in flight
+  // meanwhile.
+  constexpr int CU = HYDRO ? HU * WU : 0, IU = (CU + NTH - 1) / NTH;
+  float vx[IU > 0 ? IU : 1], vy[IU > 0 ? IU : 1];
   {
     constexpr int CA = H * W, IA = (CA + NTH - 1) / NTH;
-    constexpr int CU = HYDRO ? HU * WU : 0, IU = (CU + NTH - 1) / NTH;
-    float va[IA], vx[IU > 0 ? IU : 1], vy[IU > 0 ? IU : 1];
+    float va[IA];
 #pragma unroll
     for (int k = 0; k < IA; ++k) {
-      const int i = tid + k * NTH;
-      if (i < CA) {
-        int r = i / W, c = i - r * W;
-        va[k] = psi_in[(size_t)rowoff[r] + colx[c]];
-      }
+      const int i = min(tid + k * NTH, CA - 1);
+      int r = i / W, c = i - r * W;
+      va[k] = psi_in[(size_t)rowoff[r] + colx[c]];
     }
-    // velocity at depth 2 (plane offset 2); the wall-normal component is odd across a wall
+    __builtin_amdgcn_sched_barrier(0);  // keep the issue order: psi first
+    // velocity at depth 2 (plane offset 2); the wall-normal component is odd across a wall (the
+    // sign is applied when it is stored)
 #pragma unroll
     for (int k = 0; k < IU; ++k) {
-      const int i = tid + k * NTH;
-      if (i < CU) {
-        int r = i / WU, c = i - r * WU;
-        size_t s = (size_t)rowoff[r + 2] + colx[c + 2];
-        vx[k] = u[s];
-        vy[k] = rowsgn[r + 2] * u[N + s];
-      }
+      const int i = min(tid + k * NTH, CU - 1);
+      int r = i / WU, c = i - r * WU;
+      size_t s = (size_t)rowoff[r + 2] + colx[c + 2];
+      vx[k] = u[s];
+      vy[k] = u[N + s];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    // stores at the same clamped index (a duplicate store of the same value beyond the end), so
+    // that no load is sunk into a branch and issued late
 #pragma unroll
     for (int k = 0; k < IA; ++k) {
-      const int i = tid + k * NTH;
-      if (i < CA) {
-        int r = i / W, c = i - r * W;
-        A[r][c] = va[k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < IU; ++k) {
-      const int i = tid + k * NTH;
-      if (i < CU) {
-        int r = i / WU, c = i - r * WU;
-        Ux[r][c] = vx[k];
-        Uy[r][c] = vy[k];
-      }
+      const int i = min(tid + k * NTH, CA - 1);
+      int r = i / W, c = i - r * W;
+      A[r][c] = va[k];
     }
   }
   __syncthreads();
@@ -422,6 +417,15 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
         const float far = (ps[r][c + 2] + ps[r][c - 2]) + (ps[r + 2][c] + ps[r - 2][c]);
         const float M = 20.f * v - 8.f * ((e + w) + (n + so)) + 2.f * diag + far;
         Cm[r - 2][c - 2] = sa[r] * v + P.b * v * v * v - P.kappa * L + P.c * M;
+      }
+    }
+    if (HYDRO && s == 0) {
+#pragma unroll
+      for (int k = 0; k < IU; ++k) {
+        const int i = min(tid + k * NTH, CU - 1);
+        int r = i / WU, c = i - r * WU;
+        Ux[r][c] = vx[k];
+        Uy[r][c] = rowsgn[r + 2] * vy[k];
       }
     }
     __syncthreads();
