@@ -677,7 +677,23 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
   }
   int rc = LAM_OK;
   const bool keep = n->c.training != 0;
-  if ((e = forward(n, d_fields, keep))) rc = hip_fail(n, e, "forward");
+  // time of the whole forward pass (best of reps after one warm-up): a layer's shape is judged
+  // in place, with its input just written by the layer before, as in a real pass
+  auto pass_ms = [&](float* out) -> int {
+    float t = 1e30f;
+    for (int r = 0; r <= reps; ++r) {
+      float ms = 0.f;
+      if ((e = hipEventRecord(a, n->st)) || (e = forward(n, d_fields, keep)) ||
+          (e = hipEventRecord(b, n->st)) || (e = hipEventSynchronize(b)) ||
+          (e = hipEventElapsedTime(&ms, a, b)))
+        return hip_fail(n, e, "tuning");
+      if (r) t = std::min(t, ms);
+    }
+    *out = t;
+    return LAM_OK;
+  };
+  // one sweep of coordinate descent from the default shapes
+  for (auto& q : n->layers) q.shape = 0;
   for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
     const int lev = level_of(n, i);
     int codes[8];
@@ -685,17 +701,9 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
     float best = 1e30f;
     int pick = 0;
     for (int k = 0; rc == LAM_OK && k < nc; ++k) {
-      float t = 1e30f;
-      for (int r = 0; r <= reps; ++r) {  // the first launch warms up
-        float ms = 0.f;
-        if ((e = hipEventRecord(a, n->st)) || (e = fwd_layer(n, i, keep, codes[k])) ||
-            (e = hipEventRecord(b, n->st)) || (e = hipEventSynchronize(b)) ||
-            (e = hipEventElapsedTime(&ms, a, b))) {
-          rc = hip_fail(n, e, "tuning");
-          break;
-        }
-        if (r) t = std::min(t, ms);
-      }
+      n->layers[i].shape = codes[k];
+      float t;
+      if ((rc = pass_ms(&t)) != LAM_OK) break;
       if (t < best) {
         best = t;
         pick = codes[k];

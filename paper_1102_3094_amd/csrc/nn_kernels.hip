@@ -65,7 +65,33 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   const int H = a.H, W = a.W;
 
   u32x4 rp[LP], rw[LW];
+  // FUSE_FIELDS: one thread per patch pixel (consecutive lanes read consecutive x of each FP32
+  // plane); channels 0..7 packed into one vector, channels 8..15 zero, 16..31 never read
+  constexpr int NPX = PR * PC, LPX = (NPX + 255) / 256;
+  static_assert(LPX <= LP, "pixel registers fit the vector registers");
   auto load = [&](int c0) {
+    if (FUSE == FUSE_FIELDS) {
+#pragma unroll
+      for (int i = 0; i < LPX; ++i) {
+        const int p = tid + i * 256;
+        rp[i] = u32x4{0, 0, 0, 0};
+        const int pr = p / PC, col = p - pr * PC;
+        const int y = y0 - 1 + pr;
+        int x = x0 - 1 + col;
+        x = x < 0 ? x + W : (x >= W ? x - W : x);
+        if (p < NPX && y >= 0 && y < H) {
+          const size_t np = (size_t)H * W, q = (size_t)y * W + x;
+          float v[6];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[c] = (a.fields[c * np + q] - a.pk.shift[c]) * a.pk.scale[c];
+          v[4] = ((a.fields[3 * np + q] - a.pk.Tc) / a.pk.Tc - a.pk.shift[4]) * a.pk.scale[4];
+          v[5] = a.pk.density ? (a.fields[4 * np + q] - a.pk.shift[5]) * a.pk.scale[5] : 0.f;
+          rp[i][0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+          rp[i][1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+          rp[i][2] = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
+        }
+      }
+    } else {
 #pragma unroll
     for (int i = 0; i < LP; ++i) {
       const int idx = tid + i * 256;
@@ -76,19 +102,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         int x = x0 - 1 + col;
         x = x < 0 ? x + W : (x >= W ? x - W : x);
         if (y >= 0 && y < H) {
-          if (FUSE == FUSE_FIELDS) {
-            if (part == 0) {
-              const size_t np = (size_t)H * W, q = (size_t)y * W + x;
-              float v[6];
-#pragma unroll
-              for (int c = 0; c < 4; ++c) v[c] = (a.fields[c * np + q] - a.pk.shift[c]) * a.pk.scale[c];
-              v[4] = ((a.fields[3 * np + q] - a.pk.Tc) / a.pk.Tc - a.pk.shift[4]) * a.pk.scale[4];
-              v[5] = a.pk.density ? (a.fields[4 * np + q] - a.pk.shift[5]) * a.pk.scale[5] : 0.f;
-              rp[i][0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-              rp[i][1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-              rp[i][2] = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
-            }
-          } else if (FUSE == FUSE_POOL) {
+          if (FUSE == FUSE_POOL) {
             float s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
@@ -111,6 +125,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         }
       }
     }
+    }
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
       const int idx = tid + i * 256;
@@ -121,6 +136,16 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     }
   };
   auto stage = [&]() {
+    if (FUSE == FUSE_FIELDS) {
+#pragma unroll
+      for (int i = 0; i < LPX; ++i) {
+        const int p = tid + i * 256;
+        if (p < NPX) {
+          *(u32x4*)(sp + p * PSTR) = rp[i];
+          *(u32x4*)(sp + p * PSTR + 8) = u32x4{0, 0, 0, 0};
+        }
+      }
+    } else {
 #pragma unroll
     for (int i = 0; i < LP; ++i) {
       const int idx = tid + i * 256;
@@ -128,6 +153,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const int pr = idx / (PC * 4), rem = idx % (PC * 4), col = rem >> 2, part = rem & 3;
         *(u32x4*)(sp + (pr * PC + col) * PSTR + part * 8) = rp[i];
       }
+    }
     }
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
@@ -192,6 +218,14 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     const int passes = (MODE == CONV_FWD && a.zout) ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
       __syncthreads();
+      if (FUSE == FUSE_HEAD && tid < 132) {
+        // head weights into the free weight buffer: [4][32] (zero rows beyond nout), biases [4]
+        float* hw = (float*)sw;
+        const int o = tid < 128 ? tid >> 5 : tid - 128;
+        float v = 0.f;
+        if (o < a.nout) v = tid < 128 ? a.head_w[tid] : a.head_w[32 * a.nout + o];
+        hw[tid] = v;
+      }
 #pragma unroll
       for (int r = 0; r < RW; ++r) {
 #pragma unroll
@@ -214,18 +248,24 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       __syncthreads();
       if (FUSE == FUSE_HEAD) {
         // 1x1 head over the Cout = 32 channels of each pixel (launched with NJ = 1 only)
+        // (weights from LDS, read at the same address by every lane; rows o >= nout are zero)
         const size_t np = (size_t)H * W;
         const int no = a.nout;
+        const float* hw = (const float*)sw;
         for (int pl = tid; pl < TP; pl += 256) {
           float sacc[4];
 #pragma unroll
-          for (int o = 0; o < 4; ++o) sacc[o] = o < no ? a.head_w[32 * no + o] : 0.f;
+          for (int o = 0; o < 4; ++o) sacc[o] = hw[128 + o];
 #pragma unroll
-          for (int k = 0; k < 32; ++k) {
-            const float x = bf2f(so[pl * PSTR + k]);
+          for (int k8 = 0; k8 < 4; ++k8) {
+            const u32x4 v = *(const u32x4*)(so + pl * PSTR + 8 * k8);
 #pragma unroll
-            for (int o = 0; o < 4; ++o)
-              if (o < no) sacc[o] += a.head_w[32 * o + k] * x;
+            for (int t = 0; t < 8; ++t) {
+              const float x = __uint_as_float(t & 1 ? (v[t / 2] & 0xFFFF0000u) : (v[t / 2] << 16));
+              const int k = 8 * k8 + t;
+#pragma unroll
+              for (int o = 0; o < 4; ++o) sacc[o] += hw[32 * o + k] * x;
+            }
           }
           const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
 #pragma unroll
