@@ -66,6 +66,7 @@ struct lsn_net {
   bf16_t *gA = nullptr, *gB = nullptr, *gcat[MAXL] = {}, *gp[MAXL] = {};
   float *out = nullptr, *gout = nullptr, *part = nullptr;
   double* dpart = nullptr;
+  int head_parts = 0;     // per-workgroup sums left in dpart by the last fused forward pass
   double* lim = nullptr;  // rollout limiter: [0] max |phi| at the start of the call
   float lim_factor = 1.05f;
   int64_t adam_t = 0;
@@ -186,10 +187,10 @@ size_t carve(lsn_net* n, char* base) {
     }
   }
   n->out = cv.take<float>(n->nout * n->P[0]);
-  // FP64 partials: [0, 2 (loss_blocks + 1)) for the loss and the two conservation shifts, then
-  // per-block partials of the bias and head gradients from loss_blocks + 1 on (the shifts and
-  // the gradients are never in flight together).
-  size_t nd = 2 * ((size_t)loss_blocks(n->P[0]) + 1);
+  // FP64 partials: the loss, then (from loss_blocks + 1 on) per-block partials of the bias and
+  // head gradients; and, never in flight with those, the two conservation shifts of a step:
+  // 2 (blocks + 1) with up to npix / 128 blocks (the fused head's workgroups).
+  size_t nd = 2 * (n->P[0] / 128 + 1);
   if (tr) {
     n->gA = cv.take<bf16_t>(n->P[0] * n->wid[0]);
     n->gB = cv.take<bf16_t>(n->P[0] * n->wid[0]);
@@ -326,6 +327,8 @@ hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
       a.head_w = n->master + n->head_off;
       a.head_out = n->out;
       a.nout = n->nout;
+      a.head_part = n->dpart;
+      n->head_parts = conv_blocks(a);
     }
   }
   return launch_conv(CONV_FWD, a, n->st);
@@ -335,6 +338,7 @@ hipError_t forward(lsn_net* n, const float* fields, bool keep) {
   hipError_t e;
   const int L = n->L;
   n->fields = fields;
+  n->head_parts = 0;
   if (keep && (e = launch_pack(fields, n->P[0], pack_args(n), n->x0, n->st))) return e;
   for (int l = 0; l < L; ++l) {
     if ((e = fwd_layer(n, enc_a(l), keep)) || (e = fwd_layer(n, enc_b(l), keep))) return e;
@@ -520,7 +524,7 @@ int lsn_advance(lsn_net* n, float* d_fields) {
   hipError_t e;
   if (n->timing && (e = hipEventRecord(n->ev0, n->st))) return hip_fail(n, e, "event");
   if ((e = forward(n, d_fields, n->c.training != 0))) return hip_fail(n, e, "forward");
-  if ((e = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->st)))
+  if ((e = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->head_parts, n->st)))
     return hip_fail(n, e, "apply");
   if (n->timing) {
     if ((e = hipEventRecord(n->ev1, n->st))) return hip_fail(n, e, "event");
@@ -601,7 +605,7 @@ int advance_step(lsn_net* n, float* d_fields) {
       hipError_t r = hipStreamBeginCapture(n->st, hipStreamCaptureModeThreadLocal);
       if (r == hipSuccess) {
         hipError_t r1 = forward(n, d_fields, false);
-        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->st);
+        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->head_parts, n->st);
         hipError_t r2 = hipStreamEndCapture(n->st, &g);
         if (r1 == hipSuccess && r2 == hipSuccess) {
           hipGraphExec_t ex;

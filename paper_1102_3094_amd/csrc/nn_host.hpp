@@ -41,6 +41,8 @@ struct ConvArgs {
   const float* head_w;  // FUSE_HEAD: head weights [nout][32] then biases [nout]; output [nout][H][W]
   float* head_out;
   int nout;
+  double* head_part;    // FUSE_HEAD, optional: per-workgroup FP64 sums of output 0 at [block] and
+                        // of output 3 at [blocks + 1 + block] (the conservation shifts of a step)
   int tiles_x, nco;     // set by the launcher
 };
 
@@ -82,9 +84,12 @@ hipError_t launch_make_target(const float* e, const float* l, int nout, size_t n
 hipError_t launch_absmax(const float* x, size_t n, double* part, double* out, hipStream_t st);
 hipError_t launch_clamp_conserve(float* phi, size_t n, const double* bound, float factor,
                                  double* part, hipStream_t st);
-// part: at least 2 (ceil(npix / 256) + 1) doubles
+// part: at least 2 (max(parts, ceil(npix / 256)) + 1) doubles.  parts > 0: the per-block sums
+// of the increments are already in part (written by the fused head of the forward pass).
 hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
-                        double* part, hipStream_t st);
+                        double* part, int parts, hipStream_t st);
+// Workgroups of a forward convolution launch (the grid launch_conv uses for these arguments).
+int conv_blocks(const ConvArgs& a);
 
 }  // namespace nn
 }  // namespace lam

@@ -252,6 +252,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const size_t np = (size_t)H * W;
         const int no = a.nout;
         const float* hw = (const float*)sw;
+        double hs0 = 0.0, hs3 = 0.0;
         for (int pl = tid; pl < TP; pl += 256) {
           float sacc[4];
 #pragma unroll
@@ -271,6 +272,22 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
           for (int o = 0; o < 4; ++o)
             if (o < no) a.head_out[o * np + p] = sacc[o];
+          hs0 += (double)sacc[0];
+          hs3 += (double)sacc[3];
+        }
+        if (a.head_part) {  // per-workgroup sums for the conservation shifts of a surrogate step
+          __shared__ double hred[2][4];
+          hs0 = wave_sum(hs0);
+          hs3 = wave_sum(hs3);
+          if (lane == 0) {
+            hred[0][wave] = hs0;
+            hred[1][wave] = hs3;
+          }
+          __syncthreads();
+          if (tid == 0) {
+            a.head_part[blockIdx.x] = (hred[0][0] + hred[0][1]) + (hred[0][2] + hred[0][3]);
+            a.head_part[gridDim.x + 1 + blockIdx.x] = (hred[1][0] + hred[1][1]) + (hred[1][2] + hred[1][3]);
+          }
         }
         continue;
       }
@@ -874,6 +891,13 @@ static hipError_t conv_mode(const ConvArgs& a, hipStream_t st) {
   }
 }
 
+int conv_blocks(const ConvArgs& a) {
+  int code = a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout);
+  if (a.fuse == FUSE_HEAD) code = (code / 10) * 10 + 1;
+  const int rw = code / 10, nj = code % 10;
+  return (a.W / 32) * (a.H / (4 * rw)) * (a.Cout / (32 * nj));
+}
+
 hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st) {
   if (mode == CONV_FWD) return conv_mode<CONV_FWD>(a, st);
   if (a.fuse != FUSE_NONE) return hipErrorInvalidValue;
@@ -1005,18 +1029,19 @@ hipError_t launch_make_target(const float* e, const float* l, int nout, size_t n
   return hipGetLastError();
 }
 hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
-                        double* part, hipStream_t st) {
+                        double* part, int parts, hipStream_t st) {
   const int nb = (int)((npix + 255) / 256);
-  hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out, npix, part);
-  hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part, nb, npix);
-  double* part_n = part + nb + 1;
+  const int np = parts > 0 ? parts : nb;  // partial sums per plane
+  if (parts <= 0) hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out, npix, part);
+  hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part, np, npix);
+  double* part_n = part + np + 1;
   if (nout > 3) {
-    hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out + 3 * npix, npix, part_n);
-    hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part_n, nb, npix);
+    if (parts <= 0) hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out + 3 * npix, npix, part_n);
+    hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part_n, np, npix);
   }
   hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, nout, npix, s[0], s[1], s[2],
-                     nout > 3 ? s[3] : 0.f, (const double*)(part + nb),
-                     (const double*)(part_n + nb));
+                     nout > 3 ? s[3] : 0.f, (const double*)(part + np),
+                     (const double*)(part_n + np));
   return hipGetLastError();
 }
 
