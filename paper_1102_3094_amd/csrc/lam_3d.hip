@@ -7,7 +7,7 @@
 // slices and starts the pipeline a few slices early.
 //
 // lb3d: per slice, load phi (xy halo 3) -> L = lap phi (halo 2) -> pressure tensor (6 entries,
-//   halo 1) -> for the output slice, -div P, pull of 19 populations (issued one pipeline stage
+//   halo 1) -> for the output slice, -div P, pull of 19 populations (issued one iteration
 //   ahead), moments, BGK + forcing collision, write 19 populations and u.
 // phi3d: per slice, load psi (halo 3) and u (halo 1) -> mu with the 25-point biharmonic (halo 1)
 //   -> psi' = psi + h (Gamma lap mu - div(psi u)) for the output slice.  One Euler sub-step per
@@ -39,11 +39,13 @@ struct Tile3 {
 
 __device__ __forceinline__ Tile3 tile3(const KParams& P) {
   const int nbx = (P.nx + BX - 1) / BX, nby = (P.ny + BY - 1) / BY, nbz = (P.nz + ZCH - 1) / ZCH;
+  // x fastest, then y, then z: the tiles an XCD runs together are xy neighbours, so the halo
+  // lines they share (x +- 1 pulls cross a cache line) are fetched from HBM once into that L2
   const int t = xcd_tile(blockIdx.x, nbx * nby * nbz);
-  const int bz = t % nbz, rest = t / nbz;
+  const int bx = t % nbx, by = (t / nbx) % nby, bz = t / (nbx * nby);
   Tile3 T;
-  T.x0 = (rest % nbx) * BX;
-  T.y0 = (rest / nbx) * BY;
+  T.x0 = bx * BX;
+  T.y0 = by * BY;
   T.z0 = bz * ZCH;
   T.z1 = min(T.z0 + ZCH, P.nz);
   return T;
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
   double acc[R_N];
 #pragma unroll
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
-  float g[19];
+  float g2[2][19];  // populations of the output slice, pulled one iteration ahead
 
   static_assert(NT3 >= (BY + 6) + (BX + 6) + ZCH + 6, "one pass fills the tables");
   if (tid < BY + 6) {
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
   load_phi(T.z0 - 3, pv[0]);
   load_phi(T.z0 - 2, pv[1]);
 
-  auto iteration = [&](const int k, float(&pb)[IPH]) {
+  auto iteration = [&](const int k, float(&pb)[IPH], float(&g)[19], float(&gn)[19]) {
     const int s_load = T.z0 - 3 + k, s_L = s_load - 1, s_P = s_load - 2, s_out = s_load - 3;
     {  // phi slice s_load (loaded two iterations ago) into its ring slot
       float(*dst)[BX + 6] = S.phi[((s_load % 5) + 5) % 5];
@@ -130,9 +132,11 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
       }
     }
     const bool do_out = s_out >= T.z0 && in_xy;
-    // pulls of the output slice first: f_q(x) = f*_q(x - e_q), bounce-back across a wall
-    if (do_out) {
-      const int z = s_out;
+    // pulls of the next iteration's output slice, issued before this iteration's phi prefetch
+    // so that they have a whole iteration to arrive: f_q(x) = f*_q(x - e_q), bounce-back across
+    // a wall
+    if (s_out + 1 >= T.z0 && s_out + 1 < T.z1 && in_xy) {
+      const int z = s_out + 1;
 #pragma unroll
       for (int q = 0; q < 19; ++q) {
         const int ex = E19[q][0], ey = E19[q][1], ez = E19[q][2];
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
           const int zz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
           idx = (uint32_t)((zz * ny + sy) * nx + sx);
         }
-        g[q] = to_f32(*plane_at(gin + (size_t)qq * N, idx));
+        gn[q] = to_f32(*plane_at(gin + (size_t)qq * N, idx));
       }
     }
     load_phi(s_load + 2, pb);
@@ -289,8 +293,8 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
     }
   };
   for (int k = 0; k < K; k += 2) {
-    iteration(k, pv[0]);
-    if (k + 1 < K) iteration(k + 1, pv[1]);
+    iteration(k, pv[0], g2[0], g2[1]);
+    if (k + 1 < K) iteration(k + 1, pv[1], g2[1], g2[0]);
   }
 
   if (MODE == MODE3_OBS) {
