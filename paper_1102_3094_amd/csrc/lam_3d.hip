@@ -3,7 +3,7 @@
 //
 // Both kernels march along z over a 64 x 8 xy tile ("2.5D" blocking): LDS holds a few xy slices
 // of each field in ring buffers, so the 7-point Laplacian, the 25-point biharmonic and the
-// pressure-tensor divergence need halos only in x and y.  A workgroup owns a chunk of ZCH
+// pressure-tensor divergence need halos only in x and y.  A workgroup owns a chunk of ZLB / ZPH
 // slices and starts the pipeline a few slices early.
 //
 // lb3d: per slice, load phi (xy halo 3) -> L = lap phi (halo 2) -> pressure tensor (6 entries,
@@ -20,7 +20,9 @@
 namespace lam {
 
 constexpr int BX = 64, BY = 8, NT3 = BX * BY;
-constexpr int ZCH = 32;  // z slices per workgroup
+// z slices per workgroup (measured at 256^3: 16 for lb3d, whose pipeline prologue is short
+// against its per-slice work, 64 for phi3d)
+constexpr int ZLB = 16, ZPH = 64;
 enum { MODE3_STEP = 0, MODE3_OBS = 1, MODE3_FIELDS = 2 };
 
 // D3Q19: rest; faces +-x, +-y, +-z; edges in xy, xz, yz (opposites adjacent).
@@ -37,6 +39,7 @@ struct Tile3 {
   int x0, y0, z0, z1;
 };
 
+template <int ZCH>
 __device__ __forceinline__ Tile3 tile3(const KParams& P) {
   const int nbx = (P.nx + BX - 1) / BX, nby = (P.ny + BY - 1) / BY, nbz = (P.nz + ZCH - 1) / ZCH;
   // x fastest, then y, then z: the tiles an XCD runs together are xy neighbours, so the halo
@@ -53,7 +56,7 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P) {
 
 struct Lb3dSmem {
   int rowoff[BY + 6], colx[BX + 6];  // y * nx and x of the halo-3 xy tile (periodic)
-  float a[ZCH + 6];                  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
+  float a[ZLB + 6];                  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
   float phi[5][BY + 6][BX + 6];
   // L and P rings of 3: a slice's slot is rewritten only after the barrier that follows the last
   // phase reading it, so three slots suffice and the workgroup fits four to a compute unit
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const size_t plane = (size_t)nx * ny, N = plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
-  const Tile3 T = tile3(P);
+  const Tile3 T = tile3<ZLB>(P);
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x >= nx - 1 ? 0 : x + 1;
@@ -85,12 +88,12 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
   for (int k = 0; k < R_N; ++k) acc[k] = 0.0;
   float g2[2][19];  // populations of the output slice, pulled one iteration ahead
 
-  static_assert(NT3 >= (BY + 6) + (BX + 6) + ZCH + 6, "one pass fills the tables");
+  static_assert(NT3 >= (BY + 6) + (BX + 6) + ZLB + 6, "one pass fills the tables");
   if (tid < BY + 6) {
     S.rowoff[tid] = wrap(T.y0 - 3 + tid, ny) * nx;
   } else if (tid < (BY + 6) + (BX + 6)) {
     S.colx[tid - (BY + 6)] = wrap(T.x0 - 3 + (tid - (BY + 6)), nx);
-  } else if (tid < (BY + 6) + (BX + 6) + ZCH + 6) {
+  } else if (tid < (BY + 6) + (BX + 6) + ZLB + 6) {
     const int i = tid - (BY + 6) - (BX + 6);
     bool f;
     S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
 template <bool HYDRO>
 struct Phi3dSmem {
   int rowoff[BY + 6], colx[BX + 6];
-  float a[ZCH + 6];  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
+  float a[ZPH + 6];  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
   float psi[6][BY + 6][BX + 6];
   float mu[3][BY + 2][BX + 2];
   float u[HYDRO ? 3 : 1][3][BY + 2][BX + 2];
@@ -338,16 +341,16 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const size_t plane = (size_t)nx * ny, N = plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
-  const Tile3 T = tile3(P);
+  const Tile3 T = tile3<ZPH>(P);
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
 
-  static_assert(NT3 >= (BY + 6) + (BX + 6) + ZCH + 6, "one pass fills the tables");
+  static_assert(NT3 >= (BY + 6) + (BX + 6) + ZPH + 6, "one pass fills the tables");
   if (tid < BY + 6) {
     S.rowoff[tid] = wrap(T.y0 - 3 + tid, ny) * nx;
   } else if (tid < (BY + 6) + (BX + 6)) {
     S.colx[tid - (BY + 6)] = wrap(T.x0 - 3 + (tid - (BY + 6)), nx);
-  } else if (tid < (BY + 6) + (BX + 6) + ZCH + 6) {
+  } else if (tid < (BY + 6) + (BX + 6) + ZPH + 6) {
     const int i = tid - (BY + 6) - (BX + 6);
     bool f;
     S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
@@ -493,8 +496,12 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
 }
 
 // ------------------------------------------------------------------------------------------------
+// workgroups of lb3d (also the count of its observable partials) and of phi3d
 int blocks3d(const KParams& P) {
-  return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + ZCH - 1) / ZCH);
+  return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + ZLB - 1) / ZLB);
+}
+static int blocks3d_phi(const KParams& P) {
+  return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + ZPH - 1) / ZPH);
 }
 
 template <typename K, typename... A>
@@ -531,7 +538,7 @@ hipError_t launch_lb3d(const KParams& P, int mode, const void* gin, void* gout,
 hipError_t launch_phi3d(const KParams& P, const float* in, float* out, const float* u,
                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
                         hipEvent_t e0, hipEvent_t e1) {
-  const int nb = blocks3d(P);
+  const int nb = blocks3d_phi(P);
   if (P.hydro)
     launch3(phi3d_kernel<true>, nb, st, e0, e1, P, in, out, u, T, Tn, Ts, do_T);
   else
