@@ -346,6 +346,8 @@ int lam_advance_temperature(lam_sim* s, int64_t nsteps) {
   return LAM_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // Event pair of the next timed launch of class cls, or (nullptr, nullptr) when timing is off.
 struct EvPair {
@@ -370,6 +372,8 @@ EvPair timing_slot(lam_sim* s, int cls) {
   return e;
 }
 }  // namespace
+
+extern "C" {
 
 int lam_set_timing(lam_sim* s, int32_t enable) {
   if (!s) return LAM_EINVAL;
@@ -564,7 +568,7 @@ const char* lam_last_error(const lam_sim* s) {
 
 void lam_destroy(lam_sim* s) {
   if (!s) return;
-  for (hipEvent_t e : s->ev) hipEventDestroy(e);
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -643,7 +647,7 @@ int ens_build_tiles(lam_ensemble* e, int ty) {
                   hipMemcpyHostToDevice);
   if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("tile table: ") + hipGetErrorString(r));
   if (e->graph) {
-    hipGraphExecDestroy(e->graph);
+    (void)hipGraphExecDestroy(e->graph);
     e->graph = nullptr;
   }
   return LAM_OK;
@@ -761,7 +765,7 @@ int lam_ensemble_step(lam_ensemble* e, int64_t nsteps) {
       hipError_t r2 = hipStreamEndCapture(e->st, &g);
       if (r == hipSuccess) r = r2;
       if (r == hipSuccess) r = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
-      if (r2 == hipSuccess) hipGraphDestroy(g);
+      if (r2 == hipSuccess) (void)hipGraphDestroy(g);
       if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("graph capture: ") + hipGetErrorString(r));
     }
     while (nsteps - done >= 2) {
@@ -782,30 +786,38 @@ int lam_ensemble_step(lam_ensemble* e, int64_t nsteps) {
 int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height) {
   if (!e || steps < 1) return efail(e, LAM_EINVAL, "bad arguments");
   for (lam_sim* s : e->sims) s->initialised = true;  // timing does not depend on the values
-  hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
     return efail(e, LAM_EHIP, "event creation");
+  }
   const int cand[3] = {16, 32, 64};
   int best = 32;
   float best_ms = 1e30f;
+  int rc = LAM_OK;
   for (int c : cand) {
-    int rc = ens_build_tiles(e, c);
-    if (rc) return rc;
-    if ((rc = lam_ensemble_step(e, 2))) return rc;
-    hipEventRecord(a, e->st);
-    if ((rc = lam_ensemble_step(e, steps))) return rc;
-    hipEventRecord(b, e->st);
-    hipEventSynchronize(b);
+    if ((rc = ens_build_tiles(e, c)) || (rc = lam_ensemble_step(e, 2))) break;
+    hipError_t h;
+    if ((h = hipEventRecord(a, e->st))) {
+      rc = efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(h));
+      break;
+    }
+    if ((rc = lam_ensemble_step(e, steps))) break;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, a, b);
+    if ((h = hipEventRecord(b, e->st)) || (h = hipEventSynchronize(b)) ||
+        (h = hipEventElapsedTime(&ms, a, b))) {
+      rc = efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(h));
+      break;
+    }
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
     }
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  int rc = ens_build_tiles(e, best);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  rc = ens_build_tiles(e, best);
   if (rc) return rc;
   if (tile_height) *tile_height = best;
   return LAM_OK;
@@ -823,7 +835,7 @@ const char* lam_ensemble_last_error(const lam_ensemble* e) {
 
 void lam_ensemble_destroy(lam_ensemble* e) {
   if (!e) return;
-  if (e->graph) hipGraphExecDestroy(e->graph);
+  if (e->graph) (void)hipGraphExecDestroy(e->graph);
   for (lam_sim* s : e->sims) lam_destroy(s);
   delete e;
 }
