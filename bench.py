@@ -109,7 +109,7 @@ def bench_ensemble(args):
     import synthetic as S
     members, phis = S.ensemble_members(seed=1, count=64, pop_storage=1)
     ens = lam.Ensemble(members)
-    tile = ens.tune(10)
+    tile = ens.tune(40)
     ens.init_fields(phis)
     ens.step(args.warmup)
     ens.synchronize()
