@@ -93,3 +93,12 @@ def test_workspace_sizes(L):
     h = C.c_void_p()
     assert L.lsn_create(C.byref(c), C.c_void_p(256), 1024, None, C.byref(h)) == lam.LAM_ESIZE
     assert L.lsn_create(C.byref(c), C.c_void_p(8), n_tr.value, None, C.byref(h)) == lam.LAM_EINVAL
+
+
+def test_null_handles_rejected(L):
+    """Calls on a null network return LAM_EINVAL without touching a device."""
+    import ctypes as C
+    assert L.lsn_set_limiter(None, C.c_float(1.05)) == lam.LAM_EINVAL
+    assert L.lsn_zero_grad(None) == lam.LAM_EINVAL
+    assert L.lsn_set_timing(None, 1) == lam.LAM_EINVAL
+    assert L.lsn_rollout(None, None, None, 1, 1, 1, 1) == lam.LAM_EINVAL
