@@ -223,7 +223,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
                            "S_peak_position_err": round(q["surrogate_k_peak_err"], 4),
                            "S_peak_height_err": round(q["surrogate_S_peak_err"], 4)}
                           for sd, q in zip(held_out, runs5)]}
-    # the survey's cadence without the order-parameter limiter
+    # the 10-call cadence without the order-parameter limiter
     runs0 = [ST.evaluate(inf, p, S.phi0((side, side), seed=sd), t0=15000, cycles=10, calls=10,
                          steps_per_call=every, anchor_steps=anchor_steps, limiter=0.0)
              for sd in held_out]

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu():
-    """The GPU binding; fails (not skips) when the HIP library is missing on a GPU machine."""
+    """The GPU binding; fails (not skips) when the HIP library is missing on a machine with a GPU."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU visible")
