@@ -177,7 +177,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
     train_s = time.perf_counter() - t
     val1 = ST.validation_loss(net, val)
     inf = Surrogate(side, side, stream=stream, **norm).set_params(net.params())
-    inf.tune(train[0, 0])
+    inf.tune(train[0, 0], reps=5)
     zero = Surrogate(side, side, stream=stream, **norm).set_params(torch.zeros_like(th))
     f = train[0, 0].clone()
     inf.set_timing(True)

@@ -109,9 +109,9 @@ int lsn_rollout(lsn_net* net, lam_sim* s, float* d_fields, int32_t cycles, int32
  * a non-finite factor. */
 int lsn_set_limiter(lsn_net* net, float factor);
 
-/* Tile-shape autotuner: one sweep of coordinate descent over the 3x3 layers from the default
- * shapes: each layer tries every tile shape its sizes allow, timed as the whole forward pass on
- * d_fields (best of `reps` runs), and keeps the fastest.  The shapes change the speed only:
+/* Tile-shape autotuner: coordinate descent over the 3x3 layers from the default shapes (at most
+ * three sweeps, until one changes nothing): each layer tries every tile shape its sizes allow,
+ * timed as the whole forward pass on d_fields (best of `reps` runs), and keeps the fastest.  The shapes change the speed only:
  * every output is summed in the same order.
  * Synchronises.  lsn_get_shapes writes the shape codes (10 x rows per wave + 32-channel output
  * blocks) of the 3x3 layers in parameter order into codes[count]. */

@@ -234,10 +234,13 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   s->nphi = p->n_phi_sub > 0 ? p->n_phi_sub : auto_nphi(*p);
   s->nT = p->n_T_sub > 0 ? p->n_T_sub : auto_nT(*p);
   s->st = (hipStream_t)hip_stream;
-  // 64 x 32 tiles measured fastest on MI355X for 512^2, 1024^2 and 4096^2 lattices (lower tiles
-  // fill more compute units on small lattices but read more halo: 64 x 8 is 20 % slower at 512^2)
-  s->ty_lb = p->tile_hint ? p->tile_hint : 32;
-  s->ty_phi = p->tile_hint ? p->tile_hint : 32;
+  // 2D tile height: 32 (64 x 32 tiles, measured fastest at 1024^2 and 4096^2) unless that leaves
+  // fewer tiles than compute units, then 16 (512^2: lb2d 7.5 -> 6.3 us, phi2d 6.7 -> 6.5 us; the
+  // halo of lower tiles costs more than the idle units they fill at 1024^2 and above)
+  int ty_auto = 32;
+  if (p->dim == 2 && ((p->nx + 63) / 64) * ((p->ny + 31) / 32) < 256) ty_auto = 16;
+  s->ty_lb = p->tile_hint ? p->tile_hint : ty_auto;
+  s->ty_phi = p->tile_hint ? p->tile_hint : ty_auto;
   s->ws = (char*)d_workspace;
   s->ws_bytes = bytes;
   for (int i = 0; i < 2; ++i) {

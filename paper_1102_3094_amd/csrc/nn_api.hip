@@ -696,24 +696,30 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
     *out = t;
     return LAM_OK;
   };
-  // one sweep of coordinate descent from the default shapes
+  // coordinate descent from the default shapes, until a sweep changes nothing (at most three)
   for (auto& q : n->layers) q.shape = 0;
-  for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
-    const int lev = level_of(n, i);
-    int codes[8];
-    const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, codes, 8);
-    float best = 1e30f;
-    int pick = 0;
-    for (int k = 0; rc == LAM_OK && k < nc; ++k) {
-      n->layers[i].shape = codes[k];
-      float t;
-      if ((rc = pass_ms(&t)) != LAM_OK) break;
-      if (t < best) {
-        best = t;
-        pick = codes[k];
+  for (int sweep = 0; rc == LAM_OK && sweep < 3; ++sweep) {
+    bool changed = false;
+    for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
+      const int lev = level_of(n, i);
+      int codes[8];
+      const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, codes, 8);
+      const int before = n->layers[i].shape;
+      float best = 1e30f;
+      int pick = 0;
+      for (int k = 0; rc == LAM_OK && k < nc; ++k) {
+        n->layers[i].shape = codes[k];
+        float t;
+        if ((rc = pass_ms(&t)) != LAM_OK) break;
+        if (t < best) {
+          best = t;
+          pick = codes[k];
+        }
       }
+      n->layers[i].shape = pick;
+      changed |= pick != before;
     }
-    n->layers[i].shape = pick;
+    if (!changed) break;
   }
   n->shapes_version++;
   (void)hipEventDestroy(a);

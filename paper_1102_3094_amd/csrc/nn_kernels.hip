@@ -27,7 +27,9 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (bf16_t)(u >> 16);
 }
-__device__ __forceinline__ float sigm(float z) { return 1.f / (1.f + __expf(-z)); }
+// Logistic function with the hardware reciprocal (one rounding more than an IEEE division,
+// far below the bfloat16 rounding every activation goes through); exp overflow gives 0.
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 __device__ __forceinline__ float dsilu(float z) {
   float s = sigm(z);
   return s * (1.f + z * (1.f - s));
