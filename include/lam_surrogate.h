@@ -110,8 +110,10 @@ int lsn_rollout(lsn_net* net, lam_sim* s, float* d_fields, int32_t cycles, int32
 int lsn_set_limiter(lsn_net* net, float factor);
 
 /* Tile-shape autotuner: coordinate descent over the 3x3 layers from the default shapes (at most
- * three sweeps, until one changes nothing): each layer tries every tile shape its sizes allow,
- * timed as the whole forward pass on d_fields (best of `reps` runs), and keeps the fastest.  The shapes change the speed only:
+ * three sweeps, until one changes nothing): each layer tries every tile shape its sizes allow
+ * (and, for the first layer of a coarser level of an inference network, its 2x2 pool fused into
+ * the staging or run as a kernel of its own), timed in place inside whole forward passes on
+ * d_fields (its own kernels, best of `reps` passes), and keeps the fastest.  The shapes change the speed only:
  * every output is summed in the same order.
  * Synchronises.  lsn_get_shapes writes the shape codes (10 x rows per wave + 32-channel output
  * blocks) of the 3x3 layers in parameter order into codes[count]. */

@@ -31,6 +31,8 @@ struct Layer {
   bf16_t* wf;           // [9][cout][cin_pad]
   bf16_t* wd;           // [9][cin][cout] (training; not for e1a)
   int shape;            // tile shape of the forward convolution (0: default)
+  bool pool_apart;      // first layer of a coarser level: 2x2 pool as its own kernel instead of
+                        // fused into the staging (inference; chosen by the tuner, same bits)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -77,6 +79,9 @@ struct lsn_net {
   uint64_t shapes_version = 0, step_graph_version = 0;
   bool timing = false, timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // tuner: events around the work of one layer (its pool kernel included) inside a full pass
+  int time_layer = -1;
+  hipEvent_t tl0 = nullptr, tl1 = nullptr;
   std::string err;
 };
 
@@ -118,7 +123,7 @@ void build_layers(const lsn_config& c, std::vector<Layer>& ly, size_t* nparam, s
   int w[MAXL];
   for (int l = 0; l < L; ++l) w[l] = c.base_width << l;
   ly.clear();
-  auto add = [&](int cin, int cout, int cin_pad) { ly.push_back(Layer{cin, cout, cin_pad, 0, 0, nullptr, nullptr, 0}); };
+  auto add = [&](int cin, int cout, int cin_pad) { ly.push_back(Layer{cin, cout, cin_pad, 0, 0, nullptr, nullptr, 0, false}); };
   for (int l = 0; l < L; ++l) {
     if (l == 0) add(5 + c.with_density, w[0], IN_PAD);
     else add(w[l - 1], w[l], w[l - 1]);
@@ -316,7 +321,7 @@ hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
           a.fuse = FUSE_FIELDS;
           a.fields = n->fields;
           a.pk = pack_args(n);
-        } else {
+        } else if (!q.pool_apart) {
           a.fuse = FUSE_POOL;
           a.in = n->enc_out[l - 1];  // the pool is applied while staging
           a.in_ld = n->wid[l - 1];
@@ -340,14 +345,22 @@ hipError_t forward(lsn_net* n, const float* fields, bool keep) {
   n->fields = fields;
   n->head_parts = 0;
   if (keep && (e = launch_pack(fields, n->P[0], pack_args(n), n->x0, n->st))) return e;
-  for (int l = 0; l < L; ++l) {
-    if ((e = fwd_layer(n, enc_a(l), keep)) || (e = fwd_layer(n, enc_b(l), keep))) return e;
-    if (keep && l < L - 1 &&
-        (e = launch_pool(n->enc_out[l], n->wid[l], n->H >> l, n->W >> l, n->wid[l], n->pool[l], n->st)))
-      return e;
-  }
+  // layer i, preceded by the 2x2 pool of its input when that runs as a kernel of its own
+  auto layer = [&](int i, int pool_level) -> hipError_t {
+    hipError_t r;
+    if (i == n->time_layer && (r = hipEventRecord(n->tl0, n->st))) return r;
+    if (pool_level >= 0 && (keep || n->layers[i].pool_apart) &&
+        (r = launch_pool(n->enc_out[pool_level], n->wid[pool_level], n->H >> pool_level,
+                         n->W >> pool_level, n->wid[pool_level], n->pool[pool_level], n->st)))
+      return r;
+    if ((r = fwd_layer(n, i, keep))) return r;
+    if (i == n->time_layer && (r = hipEventRecord(n->tl1, n->st))) return r;
+    return hipSuccess;
+  };
+  for (int l = 0; l < L; ++l)
+    if ((e = layer(enc_a(l), l - 1)) || (e = layer(enc_b(l), -1))) return e;
   for (int l = L - 2; l >= 0; --l)
-    if ((e = fwd_layer(n, dec_a(L, l), keep)) || (e = fwd_layer(n, dec_b(L, l), keep))) return e;
+    if ((e = layer(dec_a(L, l), -1)) || (e = layer(dec_b(L, l), -1))) return e;
   if (fuses_head(n, keep)) return hipSuccess;
   const bf16_t* top = L > 1 ? n->dd[0] : n->enc_out[0];
   return launch_head_fwd(top, n->wid[0], n->nout, n->P[0], n->master + n->head_off, n->out, n->st);
@@ -683,21 +696,32 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
   const bool keep = n->c.training != 0;
   // time of the whole forward pass (best of reps after one warm-up): a layer's shape is judged
   // in place, with its input just written by the layer before, as in a real pass
-  auto pass_ms = [&](float* out) -> int {
+  // time of layer i's work inside a whole forward pass (best of reps after one warm-up): the
+  // layer runs on the input the layer before has just written, as in a real pass
+  n->tl0 = a;
+  n->tl1 = b;
+  auto layer_ms = [&](int i, float* out) -> int {
     float t = 1e30f;
+    n->time_layer = i;
     for (int r = 0; r <= reps; ++r) {
       float ms = 0.f;
-      if ((e = hipEventRecord(a, n->st)) || (e = forward(n, d_fields, keep)) ||
-          (e = hipEventRecord(b, n->st)) || (e = hipEventSynchronize(b)) ||
-          (e = hipEventElapsedTime(&ms, a, b)))
+      if ((e = forward(n, d_fields, keep)) || (e = hipEventSynchronize(b)) ||
+          (e = hipEventElapsedTime(&ms, a, b))) {
+        n->time_layer = -1;
         return hip_fail(n, e, "tuning");
+      }
       if (r) t = std::min(t, ms);
     }
+    n->time_layer = -1;
     *out = t;
     return LAM_OK;
   };
-  // coordinate descent from the default shapes, until a sweep changes nothing (at most three)
-  for (auto& q : n->layers) q.shape = 0;
+  // coordinate descent from the default shapes (pools fused), until a sweep changes nothing (at
+  // most three); the first layer of each coarser level also tries its pool as a kernel apart
+  for (auto& q : n->layers) {
+    q.shape = 0;
+    q.pool_apart = false;
+  }
   for (int sweep = 0; rc == LAM_OK && sweep < 3; ++sweep) {
     bool changed = false;
     for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
@@ -705,19 +729,27 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
       int codes[8];
       const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, codes, 8);
       const int before = n->layers[i].shape;
+      const bool before_apart = n->layers[i].pool_apart;
+      bool pooled = false;
+      for (int l = 1; l < n->L; ++l) pooled |= i == enc_a(l);
       float best = 1e30f;
       int pick = 0;
-      for (int k = 0; rc == LAM_OK && k < nc; ++k) {
-        n->layers[i].shape = codes[k];
-        float t;
-        if ((rc = pass_ms(&t)) != LAM_OK) break;
-        if (t < best) {
-          best = t;
-          pick = codes[k];
+      bool pick_apart = false;
+      for (int apart = 0; rc == LAM_OK && apart <= (pooled && !keep ? 1 : 0); ++apart)
+        for (int k = 0; rc == LAM_OK && k < nc; ++k) {
+          n->layers[i].shape = codes[k];
+          n->layers[i].pool_apart = apart != 0;
+          float t;
+          if ((rc = layer_ms(i, &t)) != LAM_OK) break;
+          if (t < best) {
+            best = t;
+            pick = codes[k];
+            pick_apart = apart != 0;
+          }
         }
-      }
       n->layers[i].shape = pick;
-      changed |= pick != before;
+      n->layers[i].pool_apart = pick_apart;
+      changed |= pick != before || pick_apart != before_apart;
     }
     if (!changed) break;
   }
