@@ -26,9 +26,11 @@ def test_force_and_velocity_at_start_3d(gpu):
         assert np.abs(fg["n"] - fo["n"]).max() < 1e-6
 
 
-@pytest.mark.parametrize("shape,walls", [((20, 16, 24), 1), ((37, 12, 40), 1), ((16, 24, 8), 0)])
+@pytest.mark.parametrize("shape,walls", [((20, 16, 24), 1), ((37, 12, 40), 1), ((16, 24, 8), 0),
+                                         ((70, 8, 16), 1)])
 def test_parity_3d(gpu, shape, walls):
-    """Several z chunks and ragged x/y tiles; walls on and fully periodic."""
+    """Several z chunks (the step kernel's 16-slice and the phi kernel's 64-slice chunks, ragged
+    last chunks) and ragged x/y tiles; walls on and fully periodic."""
     nz, ny, nx = shape
     p = params3(nx=nx, ny=ny, nz=nz, walls=walls, Tw=0.9, T0=1.5 if walls else 0.95)
     phi0 = S.phi0(shape, seed=7)
