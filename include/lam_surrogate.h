@@ -113,10 +113,10 @@ int lsn_set_limiter(lsn_net* net, float factor);
  * three sweeps, until one changes nothing): each layer tries every tile shape its sizes allow
  * (and, for the first layer of a coarser level of an inference network, its 2x2 pool fused into
  * the staging or run as a kernel of its own), timed in place inside whole forward passes on
- * d_fields (its own kernels, best of `reps` passes), and keeps the fastest.  The shapes change the speed only:
- * every output is summed in the same order.
- * Synchronises.  lsn_get_shapes writes the shape codes (10 x rows per wave + 32-channel output
- * blocks) of the 3x3 layers in parameter order into codes[count]. */
+ * d_fields (its own kernels, best of `reps` passes), and keeps the fastest.  The shapes change
+ * the speed only: every output is summed in the same order.  Synchronises.  lsn_get_shapes
+ * writes the shape codes (10 x rows per wave + 32-channel output blocks, + 100 for workgroups of
+ * eight waves instead of four) of the 3x3 layers in parameter order into codes[count]. */
 int lsn_tune(lsn_net* net, const float* d_fields, int32_t reps);
 int lsn_get_shapes(const lsn_net* net, int32_t* codes, int32_t count);
 

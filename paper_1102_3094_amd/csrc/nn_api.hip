@@ -726,8 +726,8 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
     bool changed = false;
     for (int i = 0; rc == LAM_OK && i < (int)n->layers.size(); ++i) {
       const int lev = level_of(n, i);
-      int codes[8];
-      const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, codes, 8);
+      int codes[16];
+      const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, codes, 16);
       const int before = n->layers[i].shape;
       const bool before_apart = n->layers[i].pool_apart;
       bool pooled = false;

@@ -52,30 +52,32 @@ constexpr int PSTR = 40;  // LDS elements per pixel (or weight row) of a 32-chan
 // tile in LDS and writes the FP32 output instead of the activation (the arithmetic of
 // head_fwd_kernel; needs all output channels in one tile).  Each gives the same bits as the
 // separate kernels.
-template <int MODE, int RW, int NJ, int FUSE>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
-  constexpr int PR = 4 * RW + 2, PC = 34;
+template <int MODE, int RW, int NJ, int FUSE, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void conv3x3_kernel(ConvArgs a) {
+  // WV waves (4 or 8) per workgroup, each RW rows of 32 pixels
+  constexpr int NT = 64 * WV;
+  constexpr int PR = WV * RW + 2, PC = 34;
   constexpr int NPV = PR * PC * 4, NWV = 9 * 32 * NJ * 4;  // 16-byte vectors per chunk
-  constexpr int LP = (NPV + 255) / 256, LW = (NWV + 255) / 256;
+  constexpr int LP = (NPV + NT - 1) / NT, LW = (NWV + NT - 1) / NT;
   __shared__ __align__(16) bf16_t sp[PR * PC * PSTR];
   __shared__ __align__(16) bf16_t sw[9 * 32 * NJ * PSTR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 31, kh = lane >> 5;
   const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int cob = L % a.nco, tile = L / a.nco;
-  const int x0 = (tile % a.tiles_x) * 32, y0 = (tile / a.tiles_x) * 4 * RW, co0 = cob * 32 * NJ;
+  const int x0 = (tile % a.tiles_x) * 32, y0 = (tile / a.tiles_x) * WV * RW, co0 = cob * 32 * NJ;
   const int H = a.H, W = a.W;
 
   u32x4 rp[LP], rw[LW];
   // FUSE_FIELDS: one thread per patch pixel (consecutive lanes read consecutive x of each FP32
   // plane); channels 0..7 packed into one vector, channels 8..15 zero, 16..31 never read
-  constexpr int NPX = PR * PC, LPX = (NPX + 255) / 256;
+  constexpr int NPX = PR * PC, LPX = (NPX + NT - 1) / NT;
   static_assert(LPX <= LP, "pixel registers fit the vector registers");
   auto load = [&](int c0) {
     if (FUSE == FUSE_FIELDS) {
 #pragma unroll
       for (int i = 0; i < LPX; ++i) {
-        const int p = tid + i * 256;
+        const int p = tid + i * NT;
         rp[i] = u32x4{0, 0, 0, 0};
         const int pr = p / PC, col = p - pr * PC;
         const int y = y0 - 1 + pr;
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     } else {
 #pragma unroll
     for (int i = 0; i < LP; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       rp[i] = u32x4{0, 0, 0, 0};
       if (idx < NPV) {
         const int pr = idx / (PC * 4), rem = idx % (PC * 4), col = rem >> 2, part = rem & 3;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       if (idx < NWV) {
         const int tap = idx / (32 * NJ * 4), rem = idx % (32 * NJ * 4), co = rem >> 2, part = rem & 3;
         rw[i] = *(const u32x4*)(a.w + ((size_t)tap * a.Cout + co0 + co) * a.Cin + c0 + part * 8);
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     if (FUSE == FUSE_FIELDS) {
 #pragma unroll
       for (int i = 0; i < LPX; ++i) {
-        const int p = tid + i * 256;
+        const int p = tid + i * NT;
         if (p < NPX) {
           *(u32x4*)(sp + p * PSTR) = rp[i];
           *(u32x4*)(sp + p * PSTR + 8) = u32x4{0, 0, 0, 0};
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     } else {
 #pragma unroll
     for (int i = 0; i < LP; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       if (idx < NPV) {
         const int pr = idx / (PC * 4), rem = idx % (PC * 4), col = rem >> 2, part = rem & 3;
         *(u32x4*)(sp + (pr * PC + col) * PSTR + part * 8) = rp[i];
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       if (idx < NWV) {
         const int tap = idx / (32 * NJ * 4), rem = idx % (32 * NJ * 4), co = rem >> 2, part = rem & 3;
         *(u32x4*)(sw + (tap * 32 * NJ + co) * PSTR + part * 8) = rw[i];
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   // 8 (q / 4) + 4 kh + (q % 4), q = 0..15 (pixel within the 32-column row).  Per 32-channel
   // block j (and per stored quantity: the output, then the forward pass's pre-activation) the
   // wave writes its values into LDS as [pixel][channel] and the workgroup stores 16-byte pieces.
-  constexpr int TP = 4 * RW * 32;  // pixels of the tile
+  constexpr int TP = WV * RW * 32;  // pixels of the tile
   static_assert(TP * PSTR <= PR * PC * PSTR, "epilogue tile exceeds the patch buffer");
   bf16_t* so = sp;
 #pragma unroll
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const int no = a.nout;
         const float* hw = (const float*)sw;
         double hs0 = 0.0, hs3 = 0.0;
-        for (int pl = tid; pl < TP; pl += 256) {
+        for (int pl = tid; pl < TP; pl += NT) {
           float sacc[4];
 #pragma unroll
           for (int o = 0; o < 4; ++o) sacc[o] = hw[128 + o];
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
           hs3 += (double)sacc[3];
         }
         if (a.head_part) {  // per-workgroup sums for the conservation shifts of a surrogate step
-          __shared__ double hred[2][4];
+          __shared__ double hred[2][WV];
           hs0 = wave_sum(hs0);
           hs3 = wave_sum(hs3);
           if (lane == 0) {
@@ -287,13 +289,18 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
           }
           __syncthreads();
           if (tid == 0) {
-            a.head_part[blockIdx.x] = (hred[0][0] + hred[0][1]) + (hred[0][2] + hred[0][3]);
-            a.head_part[gridDim.x + 1 + blockIdx.x] = (hred[1][0] + hred[1][1]) + (hred[1][2] + hred[1][3]);
+            double s0 = 0.0, s3 = 0.0;
+            for (int w = 0; w < WV; ++w) {
+              s0 += hred[0][w];
+              s3 += hred[1][w];
+            }
+            a.head_part[blockIdx.x] = s0;
+            a.head_part[gridDim.x + 1 + blockIdx.x] = s3;
           }
         }
         continue;
       }
-      for (int t = tid; t < TP * 4; t += 256) {
+      for (int t = tid; t < TP * 4; t += NT) {
         const int pl = t >> 2, part = t & 3;
         const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
         bf16_t* dst = pass == 0 ? a.out + p * a.out_ld : a.zout + p * a.Cout;
@@ -836,6 +843,9 @@ int conv_shapes(int H, int Cout, int* codes, int max_codes) {
   for (int rw : {1, 2, 4})
     for (int nj : {1, 2})
       if (H % (4 * rw) == 0 && Cout % (32 * nj) == 0 && n < max_codes) codes[n++] = 10 * rw + nj;
+  for (int rw : {1, 2})  // eight waves per workgroup: twice the rows per staged weight tile
+    for (int nj : {1, 2})
+      if (H % (8 * rw) == 0 && Cout % (32 * nj) == 0 && n < max_codes) codes[n++] = 100 + 10 * rw + nj;
   return n;
 }
 
@@ -851,12 +861,12 @@ int conv_default_shape(int H, int W, int Cout) {
   return 10 * rw + nj;
 }
 
-template <int MODE, int RW, int NJ, int FUSE>
+template <int MODE, int RW, int NJ, int FUSE, int WV = 4>
 static void conv_launch(ConvArgs a, hipStream_t st) {
   a.tiles_x = a.W / 32;
   a.nco = a.Cout / (32 * NJ);
-  const unsigned grid = (unsigned)((a.W / 32) * (a.H / (4 * RW)) * a.nco);
-  hipLaunchKernelGGL((conv3x3_kernel<MODE, RW, NJ, FUSE>), grid, 256, 0, st, a);
+  const unsigned grid = (unsigned)((a.W / 32) * (a.H / (WV * RW)) * a.nco);
+  hipLaunchKernelGGL((conv3x3_kernel<MODE, RW, NJ, FUSE, WV>), grid, 64 * WV, 0, st, a);
 }
 
 template <int MODE, int FUSE>
@@ -868,6 +878,10 @@ static hipError_t conv_shape_dispatch(const ConvArgs& a, int code, hipStream_t s
     case 22: conv_launch<MODE, 2, 2, FUSE>(a, st); break;
     case 41: conv_launch<MODE, 4, 1, FUSE>(a, st); break;
     case 42: conv_launch<MODE, 4, 2, FUSE>(a, st); break;
+    case 111: conv_launch<MODE, 1, 1, FUSE, 8>(a, st); break;
+    case 112: conv_launch<MODE, 1, 2, FUSE, 8>(a, st); break;
+    case 121: conv_launch<MODE, 2, 1, FUSE, 8>(a, st); break;
+    case 122: conv_launch<MODE, 2, 2, FUSE, 8>(a, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -876,9 +890,9 @@ static hipError_t conv_shape_dispatch(const ConvArgs& a, int code, hipStream_t s
 template <int MODE>
 static hipError_t conv_mode(const ConvArgs& a, hipStream_t st) {
   int code = a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout);
-  if (a.fuse == FUSE_HEAD) code = (code / 10) * 10 + 1;  // all 32 channels in one tile
-  const int rw = code / 10, nj = code % 10;
-  if (a.H % (4 * rw) || a.Cout % (32 * nj) || a.W % 32 || a.Cin % 32 || a.c_split % 32)
+  if (a.fuse == FUSE_HEAD) code = ((code % 100) / 10) * 10 + 1;  // 4 waves, 32 channels per tile
+  const int wv = code >= 100 ? 8 : 4, rw = (code % 100) / 10, nj = code % 10;
+  if (a.H % (wv * rw) || a.Cout % (32 * nj) || a.W % 32 || a.Cin % 32 || a.c_split % 32)
     return hipErrorInvalidValue;
   if (MODE != CONV_FWD && a.fuse != FUSE_NONE) return hipErrorInvalidValue;
   if ((a.fuse == FUSE_FIELDS && a.Cin != 32) || (a.fuse == FUSE_HEAD && a.Cout != 32) ||
@@ -895,9 +909,9 @@ static hipError_t conv_mode(const ConvArgs& a, hipStream_t st) {
 
 int conv_blocks(const ConvArgs& a) {
   int code = a.shape ? a.shape : conv_default_shape(a.H, a.W, a.Cout);
-  if (a.fuse == FUSE_HEAD) code = (code / 10) * 10 + 1;
-  const int rw = code / 10, nj = code % 10;
-  return (a.W / 32) * (a.H / (4 * rw)) * (a.Cout / (32 * nj));
+  if (a.fuse == FUSE_HEAD) code = ((code % 100) / 10) * 10 + 1;
+  const int wv = code >= 100 ? 8 : 4, rw = (code % 100) / 10, nj = code % 10;
+  return (a.W / 32) * (a.H / (wv * rw)) * (a.Cout / (32 * nj));
 }
 
 hipError_t launch_conv(int mode, const ConvArgs& a, hipStream_t st) {
