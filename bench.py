@@ -143,9 +143,10 @@ def unet_shapes(in_ch, levels=4, base=32):
 
 
 def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noise=0.0,
-                    held_out=(99, 98, 97), density=False):
+                    held_out=(99, 98, 97), density=False, unroll_steps=0):
     """Train the surrogate on plain runs and compare the accelerated run with the plain solver.
-    With `density` the network also reads and predicts the lattice density n."""
+    With `density` the network also reads and predicts the lattice density n; `unroll_steps`
+    Adam steps of two-step training follow the one-step rounds."""
     import numpy as np
     import torch
     import synthetic as S
@@ -174,6 +175,11 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         torch.cuda.synchronize()
         print(f"surrogate: training round {rnd + 1}/4 done ({time.perf_counter() - t:.1f} s)",
               file=sys.stderr, flush=True)
+    if unroll_steps:
+        ST.train(net, train, unroll_steps, batch=4, lr=1.25e-4, seed=20, unroll=True)
+        torch.cuda.synchronize()
+        print(f"surrogate: two-step training done ({time.perf_counter() - t:.1f} s)", file=sys.stderr,
+              flush=True)
     train_s = time.perf_counter() - t
     val1 = ST.validation_loss(net, val)
     inf = Surrogate(side, side, stream=stream, **norm).set_params(net.params())
@@ -257,6 +263,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         "limiter_factor": 1.05, "without_limiter": no_lim,
         "validation_loss_untrained": round(val0, 4), "validation_loss_trained": round(val1, 4),
         "snapshot_s": round(gen_s, 2), "train_s": round(train_s, 2), "train_steps": train_steps,
+        "two_step_train_steps": unroll_steps,
         "forward_ms": round(fwd_ms, 4),
         "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 4),
@@ -301,6 +308,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the GPU, about a minute)")
     ap.add_argument("--surrogate-train-steps", type=int, default=6000)
+    ap.add_argument("--surrogate-two-step", type=int, default=0,
+                    help="Adam steps of two-step (unrolled) training after the one-step rounds")
     ap.add_argument("--surrogate-density", type=int, default=0, choices=(0, 1),
                     help="1: the surrogate also reads and predicts the lattice density")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -328,7 +337,8 @@ def main():
         return bench_ensemble(args)
     if args.surrogate_only:
         print(json.dumps({"surrogate": bench_surrogate(train_steps=args.surrogate_train_steps,
-                                                       density=bool(args.surrogate_density))}),
+                                                       density=bool(args.surrogate_density),
+                                                       unroll_steps=args.surrogate_two_step)}),
               flush=True)
         return
     wl = args.workload
@@ -423,7 +433,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(p, phi0)
     if not args.no_surrogate and dim == 2 and wl == WORKLOAD:
         out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
-                                           density=bool(args.surrogate_density))
+                                           density=bool(args.surrogate_density),
+                                           unroll_steps=args.surrogate_two_step)
     print(json.dumps(out), flush=True)
 
 

@@ -82,6 +82,15 @@ int lsn_make_target(lsn_net* net, const float* d_earlier, const float* d_later, 
  * the call synchronises; LAM_ENONFINITE if it is not finite. */
 int lsn_zero_grad(lsn_net* net);
 int lsn_loss_backward(lsn_net* net, const float* d_fields, const float* d_target, double* h_loss);
+/* The same, chained with later uses of the output (training through several surrogate steps):
+ * d_out_grad (nullable, FP32 [NOUT][H][W], read only) is added to the loss gradient with respect
+ * to the output before back-propagation, and d_field_grad (nullable, FP32 [NF][H][W], written,
+ * must not alias an input) receives the gradient with respect to d_fields: of phi, u_x, u_y (and
+ * n) through their input channels, of T through both T and a = (T - Tc) / Tc.  It is computed from
+ * the bfloat16 gradient of the packed input (relative precision 2^-8).  LAM_EINVAL on a null
+ * network, fields or target, an inference network or an aliased d_field_grad. */
+int lsn_loss_backward_ex(lsn_net* net, const float* d_fields, const float* d_target,
+                         const float* d_out_grad, float* d_field_grad, double* h_loss);
 int lsn_get_grads(lsn_net* net, float* d_grads);
 
 /* One Adam step (Kingma & Ba, 2015, with bias correction) on the accumulated gradient scaled by

@@ -175,8 +175,10 @@ def loss(out, target):
     return float(np.mean((out - target) ** 2))
 
 
-def backward(theta, cache, out, target, widths=WIDTHS, q=False):
-    """Gradient of loss(out, target) with respect to theta and the input x."""
+def backward(theta, cache, out, target, widths=WIDTHS, q=False, g_extra=None):
+    """Gradient of loss(out, target) with respect to theta and the input x.  With g_extra
+    ([H, W, out_ch]) the gradient is that of loss(out, target) + sum(g_extra * out): g_extra is the
+    gradient of a later use of the output (the chain rule through several surrogate steps)."""
     r = bf16 if q else (lambda v: v)
     in_ch = cache["x"].shape[2]
     out_ch = out.shape[2]
@@ -185,6 +187,8 @@ def backward(theta, cache, out, target, widths=WIDTHS, q=False):
     G = split(grad, widths, in_ch, out_ch)
     L = len(widths)
     g_out = 2.0 * (out - target) / out.size
+    if g_extra is not None:
+        g_out = g_out + g_extra
     Wh, _ = P["head"]
     h = cache["head"]
     G["head"][0][...] = g_out.reshape(-1, out_ch).T @ h.reshape(-1, h.shape[2])

@@ -165,7 +165,7 @@ size_t carve(lsn_net* n, char* base) {
   for (size_t i = 0; i < n->layers.size(); ++i) {
     Layer& q = n->layers[i];
     q.wf = cv.take<bf16_t>((size_t)9 * q.cout * q.cin_pad);
-    q.wd = (tr && i != 0) ? cv.take<bf16_t>((size_t)9 * q.cout * q.cin) : nullptr;
+    q.wd = tr ? cv.take<bf16_t>((size_t)9 * q.cout * q.cin_pad) : nullptr;
   }
   n->x0 = cv.take<bf16_t>(n->P[0] * IN_PAD);
   for (int l = 0; l < L; ++l) {
@@ -381,18 +381,21 @@ hipError_t bwd_layer(lsn_net* n, int i, const bf16_t* gz, bf16_t* gin, int gin_l
                             n->grad + q.b_off, n->st)))
     return e;
   if (!gin) return hipSuccess;
-  ConvArgs a = conv_args(n, lev, gz, q.cout, q.cout, q.wd, q.cin);
+  ConvArgs a = conv_args(n, lev, gz, q.cout, q.cout, q.wd, q.cin_pad);
   a.out = gin;
   a.out_ld = gin_ld;
   a.zprev = zin;
   return launch_conv(zin ? CONV_BWD_SILU : CONV_BWD_PLAIN, a, n->st);
 }
 
-hipError_t backward(lsn_net* n, const float* target) {
+// Back-propagation of the loss (plus `extra`, nullable: a gradient with respect to the output
+// from its later uses) after a forward pass that kept its activations; with field_grad the
+// gradient with respect to the input fields as well.
+hipError_t backward(lsn_net* n, const float* target, const float* extra, float* field_grad) {
   hipError_t e;
   const int L = n->L;
   const size_t P0 = n->P[0];
-  if ((e = launch_loss_grad(n->out, target, n->nout, P0, n->gout, n->dpart, n->st))) return e;
+  if ((e = launch_loss_grad(n->out, target, extra, n->nout, P0, n->gout, n->dpart, n->st))) return e;
   const bf16_t* top = L > 1 ? n->dd[0] : n->enc_out[0];
   const bf16_t* ztop = L > 1 ? n->zdd[0] : n->ze[0];
   // the loss partials stay in dpart[0 .. loss_blocks): head partials go after them
@@ -418,10 +421,11 @@ hipError_t backward(lsn_net* n, const float* target) {
                                   n->W >> l, w, n->ze[l], n->gA, n->st)))
       return e;
     if ((e = bwd_layer(n, enc_b(l), n->gA, n->gB, w, n->za[l]))) return e;
-    if ((e = bwd_layer(n, enc_a(l), n->gB, l > 0 ? n->gp[l - 1] : nullptr, l > 0 ? n->wid[l - 1] : 0,
-                       nullptr)))
-      return e;
+    // level 0: gA (consumed by the layer above) takes the gradient of the packed input
+    bf16_t* gin = l > 0 ? n->gp[l - 1] : field_grad ? n->gA : nullptr;
+    if ((e = bwd_layer(n, enc_a(l), n->gB, gin, l > 0 ? n->wid[l - 1] : IN_PAD, nullptr))) return e;
   }
+  if (field_grad && (e = launch_field_grad(n->gA, P0, pack_args(n), field_grad, n->st))) return e;
   return hipGetLastError();
 }
 
@@ -561,11 +565,18 @@ int lsn_zero_grad(lsn_net* n) {
 }
 
 int lsn_loss_backward(lsn_net* n, const float* d_fields, const float* d_target, double* h_loss) {
+  return lsn_loss_backward_ex(n, d_fields, d_target, nullptr, nullptr, h_loss);
+}
+
+int lsn_loss_backward_ex(lsn_net* n, const float* d_fields, const float* d_target,
+                         const float* d_out_grad, float* d_field_grad, double* h_loss) {
   if (!n || !d_fields || !d_target) return fail(n, LAM_EINVAL, "null argument");
   if (!n->c.training) return fail(n, LAM_EINVAL, "not a training network");
+  if (d_field_grad && (d_field_grad == d_fields || d_field_grad == d_target || d_field_grad == d_out_grad))
+    return fail(n, LAM_EINVAL, "d_field_grad must not alias an input");
   hipError_t e;
   if ((e = forward(n, d_fields, true))) return hip_fail(n, e, "forward");
-  if ((e = backward(n, d_target))) return hip_fail(n, e, "backward");
+  if ((e = backward(n, d_target, d_out_grad, d_field_grad))) return hip_fail(n, e, "backward");
   if (h_loss) {
     const int nb = loss_blocks(n->P[0]);
     std::vector<double> part(nb);

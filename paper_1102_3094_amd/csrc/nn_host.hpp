@@ -68,8 +68,12 @@ hipError_t launch_pool_bwd_silu(const bf16_t* gskip, int skip_ld, const bf16_t* 
 hipError_t launch_head_fwd(const bf16_t* d, int C, int nout, size_t npix, const float* Wh, float* out,
                            hipStream_t st);
 int loss_blocks(size_t npix);
-hipError_t launch_loss_grad(const float* out, const float* t, int nout, size_t npix, float* gout,
-                            double* part, hipStream_t st);
+// gout = d loss / d out (+ extra, nullable: a gradient of later uses of the output)
+hipError_t launch_loss_grad(const float* out, const float* t, const float* extra, int nout,
+                            size_t npix, float* gout, double* part, hipStream_t st);
+// Gradient with respect to the planar fields [4 + density][npix] from that of the packed input.
+hipError_t launch_field_grad(const bf16_t* gx, size_t npix, const PackArgs& pa, float* g,
+                             hipStream_t st);
 hipError_t launch_head_bwd(const bf16_t* d, int C, int nout, size_t npix, const float* gout,
                            const float* Wh, const bf16_t* z, bf16_t* gz, double* part,
                            float* grad_head, hipStream_t st);

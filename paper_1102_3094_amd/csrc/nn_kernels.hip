@@ -491,6 +491,27 @@ __global__ void pack_input_kernel(const float* __restrict__ f, size_t npix, Pack
   dst[1] = dst[2] = dst[3] = u32x4{0, 0, 0, 0};
 }
 
+// Gradient with respect to the planar FP32 fields from the gradient gx with respect to the packed
+// input (pixel stride 32): the chain rule through the affine maps of pack_input_kernel; T enters
+// channel 3 directly and channel 4 through a = (T - Tc) / Tc.
+__global__ void field_grad_kernel(const bf16_t* __restrict__ gx, size_t npix, PackArgs pa,
+                                  float* __restrict__ g) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const u32x4 w = *(const u32x4*)(gx + p * 32);
+  float v[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[2 * k] = bf2f((bf16_t)(w[k] & 0xffffu));
+    v[2 * k + 1] = bf2f((bf16_t)(w[k] >> 16));
+  }
+  g[p] = v[0] * pa.scale[0];
+  g[npix + p] = v[1] * pa.scale[1];
+  g[2 * npix + p] = v[2] * pa.scale[2];
+  g[3 * npix + p] = v[3] * pa.scale[3] + v[4] * (pa.scale[4] / pa.Tc);
+  if (pa.density) g[4 * npix + p] = v[5] * pa.scale[5];
+}
+
 // 2x2 average pool: in [H][W] (pixel stride in_ld) -> out [H/2][W/2][C]; one thread per output
 // pixel and group of 8 channels.
 __global__ void pool_kernel(const bf16_t* __restrict__ in, int in_ld, int H, int W, int C,
@@ -616,7 +637,8 @@ __global__ void head_fwd_kernel(const bf16_t* __restrict__ d, int C, int nout, s
 
 // Loss gradient: gout[c][p] = 2 (out - t) / (nout npix); per-block FP64 partial of sum (out - t)^2.
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ out,
-                                                        const float* __restrict__ t, int nout,
+                                                        const float* __restrict__ t,
+                                                        const float* __restrict__ extra, int nout,
                                                         size_t npix, float* __restrict__ gout,
                                                         double* __restrict__ part) {
   __shared__ double sm[4];
@@ -627,7 +649,7 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
     for (int c = 0; c < nout; ++c) {
       const float d = out[c * npix + p] - t[c * npix + p];
       s += (double)d * d;
-      gout[c * npix + p] = inv * d;
+      gout[c * npix + p] = extra ? inv * d + extra[c * npix + p] : inv * d;
     }
   }
   s = wave_sum(s);
@@ -694,8 +716,9 @@ __global__ void head_dgrad_kernel(const float* __restrict__ gout, size_t npix, i
 }
 
 // bfloat16 copies of one 3x3 layer's FP32 weights W[9][Cout][Cin]: wf[9][Cout][Cin_pad] (zero
-// beyond Cin) for the forward pass and, if wd is given, wd[8 - tap][ci][co] for the input
-// gradient (the same kernel run backwards: taps mirrored, channel roles swapped).
+// beyond Cin) for the forward pass and, if wd is given, wd[8 - tap][ci][co] (ci < Cin_pad, zero
+// beyond Cin) for the input gradient (the same kernel run backwards: taps mirrored, channel roles
+// swapped).
 __global__ void refresh_weights_kernel(const float* __restrict__ W, int Cout, int Cin, int Cin_pad,
                                        bf16_t* __restrict__ wf, bf16_t* __restrict__ wd) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -703,13 +726,15 @@ __global__ void refresh_weights_kernel(const float* __restrict__ W, int Cout, in
   const int ci = (int)(i % Cin_pad);
   const size_t r = i / Cin_pad;
   const int co = (int)(r % Cout), tap = (int)(r / Cout);
+  const size_t id = ((size_t)(8 - tap) * Cin_pad + ci) * Cout + co;
   if (ci >= Cin) {
     wf[i] = 0;
+    if (wd) wd[id] = 0;
     return;
   }
   const bf16_t v = f2bf(W[((size_t)tap * Cout + co) * Cin + ci]);
   wf[i] = v;
-  if (wd) wd[((size_t)(8 - tap) * Cin + ci) * Cout + co] = v;
+  if (wd) wd[id] = v;
 }
 
 // Adam (Kingma & Ba, 2015): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
@@ -1008,10 +1033,15 @@ hipError_t launch_head_fwd(const bf16_t* d, int C, int nout, size_t npix, const 
   return hipGetLastError();
 }
 int loss_blocks(size_t npix) { return (int)((npix + 255) / 256); }
-hipError_t launch_loss_grad(const float* out, const float* t, int nout, size_t npix, float* gout,
-                            double* part, hipStream_t st) {
-  hipLaunchKernelGGL(loss_grad_kernel, loss_blocks(npix), 256, 0, st, out, t, nout, npix, gout,
-                     part);
+hipError_t launch_loss_grad(const float* out, const float* t, const float* extra, int nout,
+                            size_t npix, float* gout, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(loss_grad_kernel, loss_blocks(npix), 256, 0, st, out, t, extra, nout, npix,
+                     gout, part);
+  return hipGetLastError();
+}
+hipError_t launch_field_grad(const bf16_t* gx, size_t npix, const PackArgs& pa, float* g,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(field_grad_kernel, nblocks(npix, 256), 256, 0, st, gx, npix, pa, g);
   return hipGetLastError();
 }
 hipError_t launch_head_bwd(const bf16_t* d, int C, int nout, size_t npix, const float* gout,

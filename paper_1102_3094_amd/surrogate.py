@@ -9,7 +9,7 @@ from . import LAM_OK, LamError, load
 
 SURROGATE_EXPORTS = ("lsn_param_count", "lsn_workspace_bytes", "lsn_create", "lsn_set_params",
                      "lsn_get_params", "lsn_forward", "lsn_advance", "lsn_make_target",
-                     "lsn_zero_grad", "lsn_loss_backward", "lsn_get_grads", "lsn_adam",
+                     "lsn_zero_grad", "lsn_loss_backward", "lsn_loss_backward_ex", "lsn_get_grads", "lsn_adam",
                      "lsn_rollout", "lsn_set_limiter", "lsn_tune", "lsn_get_shapes", "lsn_set_timing", "lsn_forward_time", "lsn_last_error",
                      "lsn_destroy")
 
@@ -39,6 +39,7 @@ def lib():
     L.lsn_make_target.argtypes = [vp, vp, vp, vp]
     L.lsn_zero_grad.argtypes = [vp]
     L.lsn_loss_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
+    L.lsn_loss_backward_ex.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.lsn_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float]
     L.lsn_rollout.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.lsn_set_limiter.argtypes = [vp, C.c_float]
@@ -171,12 +172,27 @@ class Surrogate:
         self._chk(lib().lsn_zero_grad(self._h))
         return self
 
-    def loss_backward(self, fields, target, want_loss=True):
+    def loss_backward(self, fields, target, want_loss=True, out_grad=None, field_grad=None):
+        """Adds the parameter gradient of the loss to the gradient buffer.  out_grad (optional,
+        [NOUT, H, W]) is added to the loss gradient with respect to the output; field_grad
+        (optional, contiguous FP32 [NF, H, W] device tensor) receives the gradient with respect
+        to the fields."""
         f = self._t(fields, (self.NF, self.H, self.W))
         t = self._t(target, (self.NOUT, self.H, self.W))
         loss = C.c_double()
-        self._chk(lib().lsn_loss_backward(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr()),
-                                          C.byref(loss) if want_loss else None))
+        if out_grad is None and field_grad is None:
+            self._chk(lib().lsn_loss_backward(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr()),
+                                              C.byref(loss) if want_loss else None))
+            return loss.value if want_loss else None
+        g = None if out_grad is None else self._t(out_grad, (self.NOUT, self.H, self.W))
+        if field_grad is not None:
+            assert field_grad.is_contiguous() and field_grad.dtype == torch_float32()
+            assert tuple(field_grad.shape) == (self.NF, self.H, self.W), field_grad.shape
+        self._chk(lib().lsn_loss_backward_ex(
+            self._h, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr()),
+            None if g is None else C.c_void_p(g.data_ptr()),
+            None if field_grad is None else C.c_void_p(field_grad.data_ptr()),
+            C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
     def grads(self):

@@ -70,8 +70,32 @@ def mirror(f):
     return g
 
 
+def two_step_backward(net: Surrogate, a, b, c, field_grad, want_loss=False):
+    """Gradients of L1 + L2 added to the gradient buffer, where L1 is the one-step loss from
+    snapshot a to b and L2 the loss of the second surrogate step, taken from the network's own
+    prediction x2 of b (T of x2 is b's: T advances exactly between surrogate calls) towards c.
+    The gradient of L2 flows back into the first step: through the input of the second pass
+    (lsn_loss_backward_ex's field gradient) and through its target (c - x2) / s, then through
+    x2 = a + s (y1 - conservation shift) to the first output.  field_grad: [NF, H, W] scratch.
+    Returns (L1, L2) when want_loss."""
+    x2 = net.advance(a.clone())
+    x2[3] = b[3]
+    t2 = net.make_target(x2, c)
+    y2 = net.forward(x2)
+    g2 = (2.0 / y2.numel()) * (y2 - t2)          # d L2 / d y2
+    l2 = net.loss_backward(x2, t2, want_loss=want_loss, field_grad=field_grad)
+    og = g2.clone()                               # s d L2 / d x2 = s (J^T g2 + g2 / s)
+    for ch, plane in enumerate((0, 1, 2, 4)[:net.NOUT]):
+        og[ch] += float(net.cfg.out_scale[ch]) * field_grad[plane]
+    og[0] -= og[0].mean()                         # adjoint of the shift that keeps sum phi
+    if net.NOUT > 3:
+        og[3] -= og[3].mean()
+    l1 = net.loss_backward(a, net.make_target(a, b), want_loss=want_loss, out_grad=og)
+    return (l1, l2) if want_loss else None
+
+
 def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augment=True,
-          noise=0.0, pushforward=0.0):
+          noise=0.0, pushforward=0.0, unroll=False):
     """Adam with a cosine learning-rate schedule; pairs drawn by SplitMix64 from `seed`; with
     `augment`, every other draw uses the mirrored pair.  With noise > 0 the input phi is
     perturbed by uniform noise of that amplitude (relative to the spread of phi in the pair) and
@@ -80,8 +104,11 @@ def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augm
     that fraction of the draws starts from the network's own one-step prediction of a snapshot
     and targets the true state one step later (pushforward training, Brandstetter, Worrall &
     Welling, 2022: the rollout's own error distribution, without a gradient through the first
-    step)."""
+    step).  With `unroll` every draw is a snapshot triple trained through two surrogate steps
+    (two_step_backward: the gradient of the second step's error reaches the first)."""
+    import torch
     M, K = snaps.shape[0], snaps.shape[1] - 1
+    fg = torch.empty(snaps.shape[2:], dtype=torch.float32, device=snaps.device) if unroll else None
     draws = S.uniform01(seed, steps * batch)
     flips = S.uniform01(seed + 7919, steps * batch)
     pushes = S.uniform01(seed + 104729, steps * batch)
@@ -90,6 +117,16 @@ def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augm
         net.zero_grad()
         tot = 0.0
         for b in range(batch):
+            want = b == batch - 1 and (log is not None or it == steps - 1)
+            if unroll:
+                j = int(draws[it * batch + b] * M * (K - 1))
+                m, k = j // (K - 1), j % (K - 1)
+                trip = [snaps[m, k + i] for i in range(3)]
+                if augment and flips[it * batch + b] < 0.5:
+                    trip = [mirror(t) for t in trip]
+                r = two_step_backward(net, *trip, fg, want_loss=want)
+                tot = sum(r) if r is not None else tot
+                continue
             push = pushforward > 0.0 and K > 1 and pushes[it * batch + b] < pushforward
             KK = K - 1 if push else K
             j = int(draws[it * batch + b] * M * KK)
@@ -100,13 +137,11 @@ def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augm
             if push:
                 a = net.advance(a.clone())
             if noise > 0.0:
-                import torch
                 a = a.clone()
                 gen = torch.Generator(device=a.device).manual_seed(int(seed) * 1000003 + it * batch + b)
                 r = torch.rand(a.shape[1:], generator=gen, device=a.device)
                 a[0] += (noise * float(a[0].std())) * (2.0 * r - 1.0)
             tgt = net.make_target(a, c)
-            want = b == batch - 1 and (log is not None or it == steps - 1)
             r = net.loss_backward(a, tgt, want_loss=want)
             tot = r if r is not None else tot
         rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / steps))

@@ -418,3 +418,133 @@ def test_rollout_limiter_clamps_and_conserves(gpu):
           f"max diff {float((got - want).abs().max()):.2e}")
     assert torch.allclose(got, want, rtol=0, atol=2e-6)
     assert abs(float(got.sum() - s0)) < 1e-6 * H * W
+
+
+def test_full_size_forward_parity_tuned(gpu):
+    """The 512 x 512 inference network in the launch configuration the benchmark times (fused
+    packing, pools and head; tile shapes from the tuner, eight-wave and separate-pool variants
+    included) against the oracle over the whole output."""
+    H = W = 512
+    widths = (32, 64, 128, 256)
+    th = params(widths)
+    f = fields(H, W)
+    net = make(gpu, H, W).set_params(dev(th))
+    tuned = net.tune(dev(f), reps=1)
+    print("tuned shapes", tuned)
+    out = net.forward(dev(f)).cpu().double().numpy()
+    ref, _ = U.forward(th, packed(f), widths, q=True)
+    err = rel_l2(out, np.moveaxis(ref, 2, 0))
+    print(f"512^2 forward rel-L2 vs bf16-emulating oracle: {err:.2e}")
+    assert np.abs(ref).max() > 0.1
+    assert err <= 1e-2
+
+
+def test_full_size_gradient_parity(gpu):
+    """Loss and parameter gradient of the 512 x 512 training network (the size the benchmark
+    trains at) against the oracle."""
+    H = W = 512
+    widths = (32, 64, 128, 256)
+    th = params(widths)
+    f = fields(H, W)
+    tgt = 0.5 * (2 * S.uniform01(21, 3 * H * W).reshape(3, H, W) - 1)
+    net = make(gpu, H, W, training=True).set_params(dev(th))
+    net.zero_grad()
+    loss = net.loss_backward(dev(f), dev(tgt))
+    g = net.grads().cpu().double().numpy()
+    out, cache = U.forward(th, packed(f), widths, q=True)
+    ref_loss = U.loss(out, np.moveaxis(tgt, 0, 2))
+    ref, _ = U.backward(th, cache, out, np.moveaxis(tgt, 0, 2), widths, q=True)
+    print(f"512^2 loss {loss:.6e} vs {ref_loss:.6e}; gradient rel-L2 {rel_l2(g, ref):.2e}")
+    assert loss == pytest.approx(ref_loss, rel=2e-3)
+    assert rel_l2(g, ref) <= 3e-2
+
+
+def field_grad_ref(gx, cfg):
+    """Gradient with respect to the planar fields from the oracle's gradient with respect to the
+    packed input: the adjoint of packed() / packed_n() (T enters channels 3 and 4)."""
+    sc = cfg["in_scale"]
+    nf = 5 if gx.shape[2] == 6 else 4
+    g = np.empty((nf,) + gx.shape[:2])
+    for c in range(3):
+        g[c] = gx[..., c] * sc[c]
+    g[3] = gx[..., 3] * sc[3] + gx[..., 4] * sc[4] / cfg["Tc"]
+    if nf == 5:
+        g[4] = gx[..., 5] * sc[5]
+    return g
+
+
+@pytest.mark.parametrize("density", [False, True])
+def test_chained_backward_parity(gpu, density):
+    """lsn_loss_backward_ex: an extra output gradient E (the chain rule through a later surrogate
+    step) and the gradient with respect to the input fields, against the oracle's gradient of
+    loss + sum(E * out)."""
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    cfg, pk = (CFG_N, packed_n) if density else (CFG, packed)
+    nout = 4 if density else 3
+    th = params_n(widths) if density else params(widths)
+    f = fields_n(H, W) if density else fields(H, W)
+    tgt = 0.5 * (2 * S.uniform01(23, nout * H * W).reshape(nout, H, W) - 1)
+    E = 4e-5 * (2 * S.uniform01(24, nout * H * W).reshape(nout, H, W) - 1)
+    net = (make_n(H, W, training=True) if density else make(gpu, H, W, training=True)).set_params(dev(th))
+    fg = torch.full((f.shape[0], H, W), float("nan"), dtype=torch.float32, device="cuda")
+    net.zero_grad()
+    loss = net.loss_backward(dev(f), dev(tgt), out_grad=dev(E), field_grad=fg)
+    g = net.grads().cpu().double().numpy()
+    fgd = fg.cpu().double().numpy()
+    x = pk(f)
+    out, cache = U.forward(th, x, widths, q=True, out_ch=nout)
+    ref, gx = U.backward(th, cache, out, np.moveaxis(tgt, 0, 2), widths, q=True,
+                         g_extra=np.moveaxis(E, 0, 2))
+    ref_f = field_grad_ref(gx, cfg)
+    e_p, e_f = rel_l2(g, ref), rel_l2(fgd, ref_f)
+    print(f"density={density}: parameter gradient rel-L2 {e_p:.2e}, field gradient rel-L2 {e_f:.2e}")
+    assert loss == pytest.approx(U.loss(out, np.moveaxis(tgt, 0, 2)), rel=2e-3)
+    assert np.isfinite(fgd).all() and np.abs(ref_f).max() > 0
+    assert e_p <= 3e-2 and e_f <= 3e-2
+    for c in range(f.shape[0]):
+        assert rel_l2(fgd[c], ref_f[c]) <= 6e-2, c
+    # the extra gradient matters: without it the parameter gradient differs
+    ref0, _ = U.backward(th, cache, out, np.moveaxis(tgt, 0, 2), widths, q=True)
+    assert rel_l2(ref0, ref) > 0.05
+    # field_grad_ref is the adjoint of the packing: central differences of the FP64 oracle
+    J = lambda ff: (lambda o: U.loss(o, np.moveaxis(tgt, 0, 2)) + float(np.sum(np.moveaxis(E, 0, 2) * o)))(  # noqa: E731
+        U.forward(th, pk(ff), widths, out_ch=nout)[0])
+    o64, c64 = U.forward(th, x, widths, out_ch=nout)
+    _, gx64 = U.backward(th, c64, o64, np.moveaxis(tgt, 0, 2), widths, g_extra=np.moveaxis(E, 0, 2))
+    r64 = field_grad_ref(gx64, cfg)
+    h = 1e-5
+    for (c, yy, xx) in [(0, 0, 5), (3, 30, 100)] + ([(4, 10, 7)] if density else []):
+        fp, fm = f.copy(), f.copy()
+        fp[c, yy, xx] += h
+        fm[c, yy, xx] -= h
+        assert (J(fp) - J(fm)) / (2 * h) == pytest.approx(r64[c, yy, xx], rel=1e-4, abs=1e-12), (c, yy, xx)
+
+
+@pytest.mark.parametrize("density", [False, True])
+def test_two_step_training_gradient(gpu, density):
+    """The training driver's two-step objective (two_step_backward: advance, second pass, chained
+    backward through lsn_loss_backward_ex) against the oracle's composition of the same steps."""
+    from paper_1102_3094_amd.surrogate_train import two_step_backward
+    from tests._two_step import two_step
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    cfg, pk = (CFG_N, packed_n) if density else (CFG, packed)
+    th = params_n(widths) if density else params(widths)
+    a = fields_n(H, W) if density else fields(H, W)
+    nf = a.shape[0]
+    amp = np.array([0.03, 0.003, 0.003, 0.0, 0.001][:nf])[:, None, None]
+    b = a + amp * (2 * S.uniform01(31, nf * H * W).reshape(a.shape) - 1)
+    b[3] = a[3] + 0.01
+    c = b + amp * (2 * S.uniform01(32, nf * H * W).reshape(a.shape) - 1)
+    c[3] = b[3] + 0.01
+    b, c = (v.astype(np.float32).astype(np.float64) for v in (b, c))
+    net = (make_n(H, W, training=True) if density else make(gpu, H, W, training=True)).set_params(dev(th))
+    fg = torch.empty((nf, H, W), dtype=torch.float32, device="cuda")
+    net.zero_grad()
+    l1, l2 = two_step_backward(net, dev(a), dev(b), dev(c), fg, want_loss=True)
+    g = net.grads().cpu().double().numpy()
+    r1, r2, ref = two_step(th, a, b, c, widths, pk, lambda gx: field_grad_ref(gx, cfg), cfg["out_scale"],
+                           q=True)
+    err = rel_l2(g, ref)
+    print(f"density={density}: L1 {l1:.5e} vs {r1:.5e}, L2 {l2:.5e} vs {r2:.5e}, gradient rel-L2 {err:.2e}")
+    assert l1 == pytest.approx(r1, rel=2e-3) and l2 == pytest.approx(r2, rel=1e-2)
+    assert err <= 3e-2

@@ -129,6 +129,33 @@ def test_gradient_finite_differences():
         assert fd == pytest.approx(gx[yy, xx, c], rel=1e-5, abs=1e-9)
 
 
+def test_extra_output_gradient_finite_differences():
+    """With g_extra = E the gradient is that of J = loss + sum(E * out): central differences of J
+    for parameters of the first and last 3x3 layers and the head, and for input sites."""
+    theta, x, t, widths = small_net(seed=8)
+    E = rng(9).normal(size=t.shape)
+    J = lambda th, xx: (lambda o: U.loss(o, t) + float(np.sum(E * o)))(U.forward(th, xx, widths)[0])  # noqa: E731
+    out, cache = U.forward(theta, x, widths)
+    grad, gx = U.backward(theta, cache, out, t, widths, g_extra=E)
+    g0, gx0 = U.backward(theta, cache, out, t, widths)
+    assert np.abs(grad - g0).max() > 1e-3  # the extra term is not negligible here
+    h = 1e-6
+    n_e1a = 9 * U.IN_CH * widths[0] + widths[0]
+    lay = U.layers(widths)
+    n_last = 9 * lay[-1][1] * lay[-1][2] + lay[-1][2]
+    head0 = theta.size - (U.OUT_CH * widths[0] + U.OUT_CH)
+    for i in [0, 17, n_e1a - 1, head0 - n_last, head0 - 1, head0, theta.size - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        assert (J(tp, x) - J(tm, x)) / (2 * h) == pytest.approx(grad[i], rel=1e-5, abs=1e-9), i
+    for (yy, xx, c) in [(0, 3, 0), (7, 11, 4), (4, 0, 2)]:
+        xp, xm = x.copy(), x.copy()
+        xp[yy, xx, c] += h
+        xm[yy, xx, c] -= h
+        assert (J(theta, xp) - J(theta, xm)) / (2 * h) == pytest.approx(gx[yy, xx, c], rel=1e-5, abs=1e-9)
+
+
 def test_x_translation_equivariance():
     """The lattice is periodic in x; shifting the input by a multiple of 2^(L-1) columns (the
     pooling stride) shifts the output."""
@@ -187,4 +214,44 @@ def test_gradient_finite_differences_density_variant():
         tm[i] -= h
         fd = (U.loss(U.forward(tp, x, widths, out_ch=4)[0], t) -
               U.loss(U.forward(tm, x, widths, out_ch=4)[0], t)) / (2 * h)
+        assert fd == pytest.approx(grad[i], rel=1e-5, abs=1e-9), i
+
+
+def test_two_step_objective_finite_differences():
+    """The two-step training gradient (tests/_two_step.py; what the training driver computes on
+    the device) against central differences of L1 + L2, for parameters of the first and last
+    layers and the head; the packing is an affine map with T entering two channels."""
+    from tests._two_step import two_step
+    theta, _, _, widths = small_net(seed=10)
+    H, W = 8, 12
+    r = rng(11)
+    a = r.normal(size=(4, H, W))
+    b = a + 0.3 * r.normal(size=a.shape)
+    c = b + 0.3 * r.normal(size=a.shape)
+    sc = (1.3, 0.7, 0.9, 1.1, 0.8)
+
+    def pack(f):
+        x = np.empty((H, W, 5))
+        for k in range(4):
+            x[..., k] = f[k] * sc[k]
+        x[..., 4] = (f[3] - 1.0) * sc[4]
+        return x
+
+    def unpack(gx):
+        g = np.stack([gx[..., k] * sc[k] for k in range(4)])
+        g[3] += gx[..., 4] * sc[4]
+        return g
+
+    out_scale = (0.5, 0.2, 0.3)
+    L1, L2, grad = two_step(theta, a, b, c, widths, pack, unpack, out_scale)
+    h = 1e-6
+    lay = U.layers(widths)
+    n_last = 9 * lay[-1][1] * lay[-1][2] + lay[-1][2]
+    head0 = theta.size - (U.OUT_CH * widths[0] + U.OUT_CH)
+    for i in [3, 40, head0 - n_last + 5, head0 - 1, head0 + 2, theta.size - 2]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (sum(two_step(tp, a, b, c, widths, pack, unpack, out_scale)[:2]) -
+              sum(two_step(tm, a, b, c, widths, pack, unpack, out_scale)[:2])) / (2 * h)
         assert fd == pytest.approx(grad[i], rel=1e-5, abs=1e-9), i
