@@ -143,10 +143,11 @@ def unet_shapes(in_ch, levels=4, base=32):
 
 
 def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noise=0.0,
-                    held_out=(99, 98, 97), density=False, unroll_steps=0):
+                    held_out=(99, 98, 97), density=False, unroll_steps=1000, curves=None):
     """Train the surrogate on plain runs and compare the accelerated run with the plain solver.
     With `density` the network also reads and predicts the lattice density n; `unroll_steps`
-    Adam steps of two-step training follow the one-step rounds."""
+    Adam steps of two-step training follow the one-step rounds; `curves` (a path) receives the
+    S(k) curves of the held-out runs as JSON."""
     import numpy as np
     import torch
     import synthetic as S
@@ -212,10 +213,15 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         return [{"seed": sd, "finite": bool(q["surrogate_finite"]),
                  "S_peak_position_err": round(q["surrogate_k_peak_err"], 4),
                  "S_peak_height_err": round(q["surrogate_S_peak_err"], 4),
+                 "S_mean_k_err": round(q["surrogate_k_mean_err"], 4),
                  "no_network_S_peak_position_err": round(q["no_network_k_peak_err"], 4),
                  "no_network_S_peak_height_err": round(q["no_network_S_peak_err"], 4)}
                 for sd, q in zip(held_out, rs)]
     per_run = per(runs)
+    if curves:
+        with open(curves, "w") as fh:
+            json.dump([{"seed": sd, **{k: q[k] for k in ("plain_S", "surrogate_S", "no_network_S")}}
+                       for sd, q in zip(held_out, runs)], fh)
     # the same runs re-anchored every 5 calls (25 plain steps), same simulated time
     runs5 = [ST.evaluate(inf, p, S.phi0((side, side), seed=sd), t0=15000, cycles=20, calls=5,
                          steps_per_call=every, anchor_steps=anchor_steps // 2)
@@ -252,6 +258,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         "steps_per_call": r["steps_per_call"], "anchor_steps": r["anchor_steps"],
         "S_peak_position_err": round(r["surrogate_k_peak_err"], 4),
         "S_peak_height_err": round(r["surrogate_S_peak_err"], 4),
+        "S_mean_k_err": round(r["surrogate_k_mean_err"], 4),
         "phi_rel_l2_finite_runs": None if r["surrogate_phi_rel_l2"] is None else round(r["surrogate_phi_rel_l2"], 4),
         "no_network_S_peak_position_err": round(r["no_network_k_peak_err"], 4),
         "no_network_S_peak_height_err": round(r["no_network_S_peak_err"], 4),
@@ -308,8 +315,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the GPU, about a minute)")
     ap.add_argument("--surrogate-train-steps", type=int, default=6000)
-    ap.add_argument("--surrogate-two-step", type=int, default=0,
+    ap.add_argument("--surrogate-two-step", type=int, default=1000,
                     help="Adam steps of two-step (unrolled) training after the one-step rounds")
+    ap.add_argument("--surrogate-curves", default=None,
+                    help="file for the S(k) curves of the held-out surrogate runs (JSON)")
     ap.add_argument("--surrogate-density", type=int, default=0, choices=(0, 1),
                     help="1: the surrogate also reads and predicts the lattice density")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -338,7 +347,8 @@ def main():
     if args.surrogate_only:
         print(json.dumps({"surrogate": bench_surrogate(train_steps=args.surrogate_train_steps,
                                                        density=bool(args.surrogate_density),
-                                                       unroll_steps=args.surrogate_two_step)}),
+                                                       unroll_steps=args.surrogate_two_step,
+                                                       curves=args.surrogate_curves)}),
               flush=True)
         return
     wl = args.workload

@@ -1,15 +1,18 @@
 """Training and evaluation driver of the learned surrogate.  It only sequences calls of the two
 C-ABIs (solver runs and snapshots through lam.h; loss, gradients, Adam and rollouts through
-lam_surrogate.h); torch holds the snapshot tensors on the device.
+lam_surrogate.h); torch holds the snapshot tensors on the device and does the elementwise glue of
+the two-step gradient.
 
 Workflow:
   1. snapshots(): plain solver runs; fields (phi, u_x, u_y, T and optionally the density n)
      every `every` steps from t_start.
   2. normalisation(): input shifts/scales and output scales from the snapshot statistics.
-  3. train(): Adam on random consecutive snapshot pairs (target = normalised increment).
+  3. train(): Adam on random consecutive snapshot pairs (target = normalised increment), or on
+     snapshot triples through two surrogate steps (two_step_backward).
   4. evaluate(): the same start state advanced by the plain solver and by the surrogate-
      accelerated rollout (and by the rollout with a zero network, i.e. the method without the
-     learned part); S(k) peak position and height, phi error and wall-clock times.
+     learned part); S(k) peak position and height, its first moment <k>, phi error and
+     wall-clock times.
 """
 from __future__ import annotations
 
@@ -168,12 +171,6 @@ def validation_loss(net: Surrogate, snaps, pairs=32, seed=2):
     return tot / pairs
 
 
-def peak(sim, nbins=None):
-    nb = nbins or sim.params["nx"] // 2
-    s = sim.structure_factor(nb)
-    return s["k_peak"], s["S_peak"]
-
-
 def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=100,
              anchor_steps=100, zero_net: Surrogate | None = None, device="cuda:0", limiter=1.05):
     """Plain solver against the surrogate-accelerated rollout from the same state at step t0
@@ -208,8 +205,9 @@ def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=
     ens.synchronize()
     res["plain_graph_s"] = time.perf_counter() - t
     res["plain_best_s"] = min(res["plain_s"], res["plain_graph_s"])
-    kp, sp = peak(plain)
-    res["plain_k_peak"], res["plain_S_peak"] = kp, sp
+    sk = plain.structure_factor(params["nx"] // 2)
+    res["plain_k_peak"], res["plain_S_peak"], res["plain_k_mean"] = sk["k_peak"], sk["S_peak"], sk["k_mean"]
+    res["plain_S"] = sk["S"]
     phi_ref = plain.fields()["phi"].double()
 
     scratch = torch.empty((net.NF, params["ny"], params["nx"]), dtype=torch.float32, device=device)
@@ -228,15 +226,18 @@ def evaluate(net: Surrogate, params, phi0, t0, cycles, calls=10, steps_per_call=
         finite = not s.observables()["nonfinite"]
         res[f"{name}_finite"] = finite
         if finite:
-            kp, sp = peak(s)
+            sk = s.structure_factor(params["nx"] // 2)
+            kp, sp = sk["k_peak"], sk["S_peak"]
             phi = s.fields()["phi"].double()
             res[f"{name}_k_peak"], res[f"{name}_S_peak"] = kp, sp
+            res[f"{name}_S"] = sk["S"]
+            res[f"{name}_k_mean_err"] = abs(sk["k_mean"] - res["plain_k_mean"]) / res["plain_k_mean"]
             res[f"{name}_k_peak_err"] = abs(kp - res["plain_k_peak"]) / res["plain_k_peak"]
             res[f"{name}_S_peak_err"] = abs(sp - res["plain_S_peak"]) / res["plain_S_peak"]
             res[f"{name}_phi_rel_l2"] = float((phi - phi_ref).norm() / phi_ref.norm())
         else:  # a run that blew up counts as a 100 % error
-            res[f"{name}_k_peak"] = res[f"{name}_S_peak"] = None
-            res[f"{name}_k_peak_err"] = res[f"{name}_S_peak_err"] = 1.0
+            res[f"{name}_k_peak"] = res[f"{name}_S_peak"] = res[f"{name}_S"] = None
+            res[f"{name}_k_peak_err"] = res[f"{name}_S_peak_err"] = res[f"{name}_k_mean_err"] = 1.0
             res[f"{name}_phi_rel_l2"] = None
         res[f"{name}_speedup"] = res["plain_best_s"] / res[f"{name}_s"]
     return res
