@@ -444,7 +444,8 @@ def main():
     if not args.no_surrogate and dim == 2 and wl == WORKLOAD:
         out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
                                            density=bool(args.surrogate_density),
-                                           unroll_steps=args.surrogate_two_step)
+                                           unroll_steps=args.surrogate_two_step,
+                                           curves=args.surrogate_curves)
     print(json.dumps(out), flush=True)
 
 
