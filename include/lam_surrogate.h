@@ -125,9 +125,13 @@ int lsn_set_limiter(lsn_net* net, float factor);
  * d_fields (its own kernels, best of `reps` passes), and keeps the fastest.  The shapes change
  * the speed only: every output is summed in the same order.  Synchronises.  lsn_get_shapes
  * writes the shape codes (10 x rows per wave + 32-channel output blocks, + 100 for workgroups of
- * eight waves instead of four) of the 3x3 layers in parameter order into codes[count]. */
+ * eight waves instead of four) of the 3x3 layers in parameter order into codes[count].
+ * lsn_set_shapes sets them (count = the number of 3x3 layers, 4 levels - 2; code 0 = the layer's
+ * default), for example to reuse an earlier tuning; LAM_EINVAL, and no change, if a code is not
+ * one the layer's sizes allow. */
 int lsn_tune(lsn_net* net, const float* d_fields, int32_t reps);
 int lsn_get_shapes(const lsn_net* net, int32_t* codes, int32_t count);
+int lsn_set_shapes(lsn_net* net, const int32_t* codes, int32_t count);
 
 /* Kernel timing: with timing enabled, the next forward's kernels are bracketed by HIP events
  * and lsn_forward_time returns its duration in ms (synchronises). */

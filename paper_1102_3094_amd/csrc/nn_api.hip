@@ -779,6 +779,24 @@ int lsn_get_shapes(const lsn_net* n, int32_t* codes, int32_t count) {
   return LAM_OK;
 }
 
+int lsn_set_shapes(lsn_net* n, const int32_t* codes, int32_t count) {
+  if (!n || !codes) return fail(n, LAM_EINVAL, "null argument");
+  if (count != (int32_t)n->layers.size()) return fail(n, LAM_EINVAL, "one code per 3x3 layer");
+  for (size_t i = 0; i < n->layers.size(); ++i) {
+    if (codes[i] == 0) continue;
+    const int lev = level_of(n, (int)i);
+    int cand[16];
+    const int nc = conv_shapes(n->H >> lev, n->layers[i].cout, cand, 16);
+    bool ok = false;
+    for (int k = 0; k < nc; ++k) ok |= cand[k] == codes[i];
+    if (!ok) return fail(n, LAM_EINVAL, "tile shape " + std::to_string(codes[i]) + " not available for layer " +
+                                            std::to_string(i));
+  }
+  for (size_t i = 0; i < n->layers.size(); ++i) n->layers[i].shape = codes[i];
+  n->shapes_version++;
+  return LAM_OK;
+}
+
 int lsn_set_timing(lsn_net* n, int32_t enable) {
   if (!n) return fail(n, LAM_EINVAL, "null argument");
   hipError_t e;

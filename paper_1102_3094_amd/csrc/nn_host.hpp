@@ -34,7 +34,8 @@ struct ConvArgs {
   bf16_t* zout;         // CONV_FWD, optional: pre-activation [pixels][Cout]
   const bf16_t* zprev;  // CONV_BWD_SILU: pre-activation [pixels][Cout]; the result is multiplied by silu'
   int H, W, Cin, Cout;
-  int shape;            // tile shape 10 RW + NJ (rows per wave, 32-channel output blocks); 0: default
+  int shape;            // tile shape 10 RW + NJ (rows per wave, 32-channel output blocks), + 100:
+                        // eight waves; 0: default
   int fuse;             // FUSE_*; forward passes only
   const float* fields;  // FUSE_FIELDS: planar FP32 [4][H][W] and its normalisation
   PackArgs pk;
@@ -46,7 +47,8 @@ struct ConvArgs {
   int tiles_x, nco;     // set by the launcher
 };
 
-// Tile shapes a 3x3 layer of these sizes can use (codes 10 RW + NJ), and the default pick.
+// Tile shapes a 3x3 layer of these sizes can use (codes 10 RW + NJ, + 100 for eight waves), and
+// the default pick.
 int conv_shapes(int H, int Cout, int* codes, int max_codes);
 int conv_default_shape(int H, int W, int Cout);
 

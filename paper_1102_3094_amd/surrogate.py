@@ -10,7 +10,7 @@ from . import LAM_OK, LamError, load
 SURROGATE_EXPORTS = ("lsn_param_count", "lsn_workspace_bytes", "lsn_create", "lsn_set_params",
                      "lsn_get_params", "lsn_forward", "lsn_advance", "lsn_make_target",
                      "lsn_zero_grad", "lsn_loss_backward", "lsn_loss_backward_ex", "lsn_get_grads", "lsn_adam",
-                     "lsn_rollout", "lsn_set_limiter", "lsn_tune", "lsn_get_shapes", "lsn_set_timing", "lsn_forward_time", "lsn_last_error",
+                     "lsn_rollout", "lsn_set_limiter", "lsn_tune", "lsn_get_shapes", "lsn_set_shapes", "lsn_set_timing", "lsn_forward_time", "lsn_last_error",
                      "lsn_destroy")
 
 
@@ -45,6 +45,7 @@ def lib():
     L.lsn_set_limiter.argtypes = [vp, C.c_float]
     L.lsn_tune.argtypes = [vp, vp, C.c_int32]
     L.lsn_get_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
+    L.lsn_set_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     L.lsn_set_timing.argtypes = [vp, C.c_int32]
     L.lsn_forward_time.argtypes = [vp, C.POINTER(C.c_float)]
     L.lsn_last_error.argtypes = [vp]
@@ -230,6 +231,14 @@ class Surrogate:
         codes = (C.c_int32 * n)()
         self._chk(lib().lsn_get_shapes(self._h, codes, n))
         return list(codes)
+
+    def set_shapes(self, codes):
+        """Tile-shape codes of the 3x3 layers in parameter order (0: the layer's default)."""
+        n = 4 * self.cfg.levels - 2
+        assert len(codes) == n, (len(codes), n)
+        arr = (C.c_int32 * n)(*[int(c) for c in codes])
+        self._chk(lib().lsn_set_shapes(self._h, arr, n))
+        return self
 
     def set_timing(self, on=True):
         self._chk(lib().lsn_set_timing(self._h, int(bool(on))))

@@ -103,3 +103,4 @@ def test_null_handles_rejected(L):
     assert L.lsn_set_timing(None, 1) == lam.LAM_EINVAL
     assert L.lsn_rollout(None, None, None, 1, 1, 1, 1) == lam.LAM_EINVAL
     assert L.lsn_loss_backward_ex(None, None, None, None, None, None) == lam.LAM_EINVAL
+    assert L.lsn_set_shapes(None, None, 0) == lam.LAM_EINVAL

@@ -191,8 +191,41 @@ def test_tuned_shapes_give_identical_outputs(gpu):
     tuned = net.tune(f, reps=1)
     after = net.forward(f)
     print("default shapes", default, "tuned", tuned)
-    assert len(tuned) == 14 and all(c in (11, 12, 21, 22, 41, 42, 111, 112, 121, 122) for c in tuned)
+    assert len(tuned) == 14 and all(c in ALL_CODES for c in tuned)
     assert torch.equal(before, after)
+
+
+ALL_CODES = (11, 12, 21, 22, 41, 42, 111, 112, 121, 122)
+
+
+@pytest.mark.parametrize("training", [False, True])
+def test_every_tile_shape_gives_identical_outputs(gpu, training):
+    """Each shape code, set through lsn_set_shapes on every layer whose sizes allow it, gives the
+    bits of the default shapes; an inference network runs the fused packing, pools and head with
+    them."""
+    H, W, widths = 64, 256, (32, 64, 128, 256)
+    net = make(gpu, H, W, training=training).set_params(dev(params(widths)))
+    f = dev(fields(H, W))
+    ref = net.forward(f).clone()
+    default = net.shapes()
+    used = set()
+    for code in ALL_CODES:
+        codes = []
+        for i, d in enumerate(default):
+            trial = list(default)
+            trial[i] = code
+            try:
+                net.set_shapes(trial)
+                codes.append(code)
+            except Exception:
+                codes.append(0)
+        net.set_shapes(codes)
+        used |= {c for c in codes if c}
+        assert torch.equal(net.forward(f), ref), code
+    net.set_shapes([0] * len(default))
+    assert set(ALL_CODES) <= used
+    with pytest.raises(Exception):
+        net.set_shapes([31] + [0] * (len(default) - 1))
 
 
 @pytest.mark.parametrize("H,W,levels,base", [(64, 256, 4, 32), (32, 128, 3, 64)])
@@ -437,6 +470,15 @@ def test_full_size_forward_parity_tuned(gpu):
     print(f"512^2 forward rel-L2 vs bf16-emulating oracle: {err:.2e}")
     assert np.abs(ref).max() > 0.1
     assert err <= 1e-2
+    # one surrogate step with the tuned shapes (the fused head's per-workgroup sums give the
+    # conservation shift): phi moves by its increment minus the mean, sum phi is kept
+    g = dev(f)
+    net.advance(g)
+    dphi = (g[0].double() - dev(f)[0].double()).cpu().numpy()
+    s0 = CFG["out_scale"][0]
+    want = (out[0] - out[0].mean()) * s0
+    assert np.abs(dphi - want).max() <= 1e-5 + 1e-3 * np.abs(want).max()
+    assert abs(dphi.sum()) <= 1e-6 * f[0].size
 
 
 def test_full_size_gradient_parity(gpu):
