@@ -84,21 +84,33 @@ def traffic_from_profiles(workload, dim):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(params, phi0, budget_s=12.0):
-    from oracle import Oracle
-    o = Oracle(params).init_fields(phi0)
-    o.step(1)  # first-touch of the arrays outside the timing
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < budget_s and steps < 2000:
-        o.step(1)
-        steps += 1
-    dt = time.perf_counter() - t0
+def cpu_baseline(params, phi0, budget_s=12.0, single_s=4.0):
+    """The FP64 oracle on the host: all OpenMP threads for about budget_s, then one thread for
+    about single_s (at least one step each)."""
+    import oracle
     n = params["nx"] * params["ny"] * (params["nz"] if params["dim"] == 3 else 1)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def rate(budget):
+        o = oracle.Oracle(params).init_fields(phi0)
+        o.step(1)  # first-touch of the arrays outside the timing
+        t0 = time.perf_counter()
+        steps = 0
+        while (time.perf_counter() - t0 < budget or steps == 0) and steps < 2000:
+            o.step(1)
+            steps += 1
+        dt = time.perf_counter() - t0
+        return n * steps / dt / 1e6, steps, dt
+
+    cores = oracle.threads()
+    v, steps, dt = rate(budget_s)
+    oracle.threads(1)
+    v1, steps1, dt1 = rate(single_s)
+    oracle.threads(cores)
     shape = "x".join(str(params[k]) for k in (("nx", "ny") if params["dim"] == 2 else ("nx", "ny", "nz")))
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} steps of the {shape} workload ({dt:.1f} s, FP64, OpenMP over sites)"}
+    return {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} steps of the {shape} workload ({dt:.1f} s, FP64, OpenMP over sites); "
+                      f"one thread: {steps1} steps in {dt1:.1f} s",
+            "single_thread_value": v1}
 
 
 def bench_ensemble(args):

@@ -62,8 +62,14 @@ def lib():
         L.orc_state_bytes.restype = C.c_size_t
         L.orc_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.orc_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.orc_threads.argtypes = [C.c_int32]
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """OpenMP threads of the oracle's loops (n > 0 sets them); returns the number in use."""
+    return int(lib().orc_threads(int(n)))
 
 
 def _dp(a):

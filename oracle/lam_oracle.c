@@ -29,6 +29,7 @@
 #include "lam_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -710,4 +711,9 @@ int orc_set_state(orc_sim* s, const void* buf, size_t bytes) {
   memcpy(s->T, c, sizeof(double) * s->N);
   s->step = h.step;
   return 0;
+}
+
+int orc_threads(int32_t n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
 }

@@ -75,6 +75,9 @@ int orc_guo(int32_t dim, double tau, const double* u, const double* F, double* o
 size_t orc_state_bytes(const orc_sim* s);
 int orc_get_state(const orc_sim* s, void* buf, size_t bytes);
 int orc_set_state(orc_sim* s, const void* buf, size_t bytes);
+/* OpenMP threads of the loops over sites: n > 0 sets them for the calls that follow; returns the
+ * number in use. */
+int orc_threads(int32_t n);
 
 #ifdef __cplusplus
 }
