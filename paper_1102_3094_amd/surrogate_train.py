@@ -111,6 +111,8 @@ def train(net: Surrogate, snaps, steps, batch=4, lr=1e-3, seed=1, log=None, augm
     (two_step_backward: the gradient of the second step's error reaches the first)."""
     import torch
     M, K = snaps.shape[0], snaps.shape[1] - 1
+    if unroll and K < 2:
+        raise ValueError("two-step training needs at least three snapshots per run")
     fg = torch.empty(snaps.shape[2:], dtype=torch.float32, device=snaps.device) if unroll else None
     draws = S.uniform01(seed, steps * batch)
     flips = S.uniform01(seed + 7919, steps * batch)
