@@ -29,7 +29,7 @@ struct Layer {
   int cin, cout, cin_pad;
   size_t w_off, b_off;  // offsets in the parameter vector
   bf16_t* wf;           // [9][cout][cin_pad]
-  bf16_t* wd;           // [9][cin][cout] (training; not for e1a)
+  bf16_t* wd;           // [9][cin_pad][cout], taps mirrored (training: input gradient)
   int shape;            // tile shape of the forward convolution (0: default)
   bool pool_apart;      // first layer of a coarser level: 2x2 pool as its own kernel instead of
                         // fused into the staging (inference; chosen by the tuner, same bits)
