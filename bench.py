@@ -14,9 +14,10 @@ FP64 CPU oracle's MLUPS on a bounded sample of the same workload.  --workload se
 named workload (for example the 256^3 D3Q19 lattice) for the same measurement.
 
 The same line carries the learned-surrogate leg ("surrogate"): a U-Net (BF16 matrix-core kernels)
-trained on the GPU on snapshots of plain 512^2 runs, then a surrogate-accelerated run (10 calls of
-100 lattice steps each, then re-anchoring and plain steps, 10 cycles) against the plain solver
-from the same state: wall-clock speed-up, error of the S(k) peak position and height, and the
+trained on the GPU on snapshots of plain 512^2 runs (one-step rounds, then two-step training),
+then a surrogate-accelerated run (10 calls of 100 lattice steps each, then re-anchoring and
+--surrogate-anchor-steps plain steps, 10 cycles) against the plain solver from the same state:
+wall-clock speed-up, error of the S(k) peak position and height and of its first moment, and the
 same for the run without the network (the method with the learned steps replaced by no change).
 """
 import argparse
@@ -329,6 +330,8 @@ def main():
     ap.add_argument("--surrogate-train-steps", type=int, default=6000)
     ap.add_argument("--surrogate-two-step", type=int, default=1000,
                     help="Adam steps of two-step (unrolled) training after the one-step rounds")
+    ap.add_argument("--surrogate-anchor-steps", type=int, default=50,
+                    help="plain steps after every 10 surrogate calls (re-anchoring)")
     ap.add_argument("--surrogate-curves", default=None,
                     help="file for the S(k) curves of the held-out surrogate runs (JSON)")
     ap.add_argument("--surrogate-density", type=int, default=0, choices=(0, 1),
@@ -360,7 +363,8 @@ def main():
         print(json.dumps({"surrogate": bench_surrogate(train_steps=args.surrogate_train_steps,
                                                        density=bool(args.surrogate_density),
                                                        unroll_steps=args.surrogate_two_step,
-                                                       curves=args.surrogate_curves)}),
+                                                       curves=args.surrogate_curves,
+                                                       anchor_steps=args.surrogate_anchor_steps)}),
               flush=True)
         return
     wl = args.workload
@@ -457,7 +461,8 @@ def main():
         out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
                                            density=bool(args.surrogate_density),
                                            unroll_steps=args.surrogate_two_step,
-                                           curves=args.surrogate_curves)
+                                           curves=args.surrogate_curves,
+                                           anchor_steps=args.surrogate_anchor_steps)
     print(json.dumps(out), flush=True)
 
 
