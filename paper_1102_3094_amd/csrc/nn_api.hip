@@ -705,8 +705,6 @@ int lsn_tune(lsn_net* n, const float* d_fields, int32_t reps) {
   }
   int rc = LAM_OK;
   const bool keep = n->c.training != 0;
-  // time of the whole forward pass (best of reps after one warm-up): a layer's shape is judged
-  // in place, with its input just written by the layer before, as in a real pass
   // time of layer i's work inside a whole forward pass (best of reps after one warm-up): the
   // layer runs on the input the layer before has just written, as in a real pass
   n->tl0 = a;
