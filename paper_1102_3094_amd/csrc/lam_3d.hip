@@ -318,16 +318,17 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
 }
 
 // ------------------------------------------------------------------------------------------------
-// psi ring of 6: the load of slice z + 4 must not overwrite slice z - 1, which slower threads may
-// still read for the output slice z of the previous iteration (no barrier between them).  mu and u
-// are written after the iteration's first barrier, so rings of 3 suffice for them.
+// Two slices per iteration.  psi ring of 8: the stores of slices s + 2, s + 3 must not overwrite
+// slices s - 4 .. s - 1, which slower threads may still read for the output slices of the previous
+// iteration (no barrier between them).  mu and u are written after the iteration's first barrier
+// and read for outputs s - 3, s - 2 (slices s - 4 .. s - 1): rings of 4.
 template <bool HYDRO>
 struct Phi3dSmem {
   int rowoff[BY + 6], colx[BX + 6];
   float a[ZPH + 6];  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
-  float psi[6][BY + 6][BX + 6];
-  float mu[3][BY + 2][BX + 2];
-  float u[HYDRO ? 3 : 1][3][BY + 2][BX + 2];
+  float psi[8][BY + 6][BX + 6];
+  float mu[4][BY + 2][BX + 2];
+  float u[HYDRO ? 4 : 1][3][BY + 2][BX + 2];
 };
 
 template <bool HYDRO>
@@ -356,13 +357,13 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
     S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
   }
   __syncthreads();
-  // psi slice s and u slice s - 2 are loaded into registers two iterations before their LDS
-  // store (two register buffers, selected by the parity of the iteration): the memory counter of
-  // a wave drains in issue order, so the stores of iteration k wait only for the loads issued at
-  // k - 2 while those of k - 1 stay in flight.  Every load is unconditional (clamped index, a
-  // u slice is fetched and stored even where it goes unused, the last two iterations prefetch a
-  // slice they do not need) so that no branch forces an early wait; the per-slice a comes from
-  // LDS for the same reason.
+  // psi slice s and u slice s - 2 are loaded into registers one iteration (two slices) before
+  // their LDS store (one register buffer per slice of the pair): the memory counter of a wave
+  // drains in issue order, so the store of the first slice waits only for its own loads while
+  // those of the second stay in flight.  Every load is unconditional (clamped index, a u slice is
+  // fetched and stored even where it goes unused, the last iteration prefetches slices it does
+  // not need) so that no branch forces an early wait; the per-slice a comes from LDS for the same
+  // reason.
   constexpr int CPS = (BY + 6) * (BX + 6), IPS = (CPS + NT3 - 1) / NT3;
   constexpr int CUS = (BY + 2) * (BX + 2), IUS = (CUS + NT3 - 1) / NT3;
   float pv[2][IPS], uv[2][3][IUS];
@@ -394,74 +395,86 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
   load(T.z0 - 3, pv[0], uv[0]);
   load(T.z0 - 2, pv[1], uv[1]);
 
-  auto iteration = [&](const int k, float(&pb)[IPS], float(&ub)[3][IUS]) {
-    const int s_load = T.z0 - 3 + k, s_mu = s_load - 2, s_out = s_load - 3;
-    {  // psi slice s_load (xy halo 3)
-      float(*dst)[BX + 6] = S.psi[((s_load % 6) + 6) % 6];
+  // Two slices per iteration (one barrier per slice): store psi slices s, s + 1 and u slices
+  // s - 2, s - 1, compute mu of slices s - 2, s - 1, write the output slices s - 3, s - 2.
+  auto pair = [&](const int k) {
+    const int s0 = T.z0 - 3 + k;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // psi slices s0, s0 + 1 (xy halo 3)
+      float(*dst)[BX + 6] = S.psi[(((s0 + h) % 8) + 8) % 8];
 #pragma unroll
       for (int j = 0; j < IPS; ++j) {
         const int i = tid + j * NT3;
         if (i < CPS) {
           const int r = i / (BX + 6), c = i - r * (BX + 6);
-          dst[r][c] = pb[j];
+          dst[r][c] = pv[h][j];
         }
       }
     }
     __syncthreads();
-    if (HYDRO) {  // u slice s_mu (xy halo 1, normal component odd)
-      float(*ud)[BY + 2][BX + 2] = S.u[((s_mu % 3) + 3) % 3];
+    if (HYDRO) {  // u slices s0 - 2, s0 - 1 (xy halo 1, normal component odd)
 #pragma unroll
-      for (int j = 0; j < IUS; ++j) {
-        const int i = tid + j * NT3;
-        if (i < CUS) {
-          const int r = i / (BX + 2), c = i - r * (BX + 2);
-          ud[0][r][c] = ub[0][j];
-          ud[1][r][c] = ub[1][j];
-          ud[2][r][c] = ub[2][j];
+      for (int h = 0; h < 2; ++h) {
+        float(*ud)[BY + 2][BX + 2] = S.u[(((s0 - 2 + h) % 4) + 4) % 4];
+#pragma unroll
+        for (int j = 0; j < IUS; ++j) {
+          const int i = tid + j * NT3;
+          if (i < CUS) {
+            const int r = i / (BX + 2), c = i - r * (BX + 2);
+            ud[0][r][c] = uv[h][0][j];
+            ud[1][r][c] = uv[h][1][j];
+            ud[2][r][c] = uv[h][2][j];
+          }
         }
       }
     }
-    load(s_load + 2, pb, ub);
-    if (s_mu >= T.z0 - 1) {  // mu of slice s_mu with xy halo 1 (25-point biharmonic)
+    load(s0 + 2, pv[0], uv[0]);
+    load(s0 + 3, pv[1], uv[1]);
+    // mu of slices s0 - 2 and s0 - 1 with xy halo 1 (25-point biharmonic)
+    for (int i = tid; i < 2 * CUS; i += NT3) {
+      const int h = i >= CUS, q = i - h * CUS;
+      const int s_mu = s0 - 2 + h;
+      if (s_mu < T.z0 - 1 || s_mu > T.z1) continue;
       const float a = S.a[s_mu - (T.z0 - 3)];
-      float(*c0)[BX + 6] = S.psi[((s_mu % 6) + 6) % 6];
-      float(*m1)[BX + 6] = S.psi[(((s_mu - 1) % 6) + 6) % 6];
-      float(*p1)[BX + 6] = S.psi[(((s_mu + 1) % 6) + 6) % 6];
-      float(*m2)[BX + 6] = S.psi[(((s_mu - 2) % 6) + 6) % 6];
-      float(*p2)[BX + 6] = S.psi[(((s_mu + 2) % 6) + 6) % 6];
-      float(*dst)[BX + 2] = S.mu[((s_mu % 3) + 3) % 3];
-      for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
-        int r = i / (BX + 2), cc = i - r * (BX + 2);
-        const int R = r + 2, C = cc + 2;
-        const float v = c0[R][C];
-        const float face = ((c0[R][C + 1] + c0[R][C - 1]) + (c0[R + 1][C] + c0[R - 1][C])) +
-                           (p1[R][C] + m1[R][C]);
-        const float edge = ((c0[R + 1][C + 1] + c0[R + 1][C - 1]) + (c0[R - 1][C + 1] + c0[R - 1][C - 1])) +
-                           ((p1[R][C + 1] + p1[R][C - 1]) + (m1[R][C + 1] + m1[R][C - 1])) +
-                           ((p1[R + 1][C] + p1[R - 1][C]) + (m1[R + 1][C] + m1[R - 1][C]));
-        const float far = ((c0[R][C + 2] + c0[R][C - 2]) + (c0[R + 2][C] + c0[R - 2][C])) +
-                          (p2[R][C] + m2[R][C]);
-        const float L = face - 6.f * v;
-        const float M = 42.f * v - 12.f * face + 2.f * edge + far;
-        dst[r][cc] = a * v + P.b * v * v * v - P.kappa * L + P.c * M;
-      }
+      float(*c0)[BX + 6] = S.psi[((s_mu % 8) + 8) % 8];
+      float(*m1)[BX + 6] = S.psi[(((s_mu - 1) % 8) + 8) % 8];
+      float(*p1)[BX + 6] = S.psi[(((s_mu + 1) % 8) + 8) % 8];
+      float(*m2)[BX + 6] = S.psi[(((s_mu - 2) % 8) + 8) % 8];
+      float(*p2)[BX + 6] = S.psi[(((s_mu + 2) % 8) + 8) % 8];
+      float(*dst)[BX + 2] = S.mu[((s_mu % 4) + 4) % 4];
+      const int r = q / (BX + 2), cc = q - r * (BX + 2);
+      const int R = r + 2, C = cc + 2;
+      const float v = c0[R][C];
+      const float face = ((c0[R][C + 1] + c0[R][C - 1]) + (c0[R + 1][C] + c0[R - 1][C])) +
+                         (p1[R][C] + m1[R][C]);
+      const float edge = ((c0[R + 1][C + 1] + c0[R + 1][C - 1]) + (c0[R - 1][C + 1] + c0[R - 1][C - 1])) +
+                         ((p1[R][C + 1] + p1[R][C - 1]) + (m1[R][C + 1] + m1[R][C - 1])) +
+                         ((p1[R + 1][C] + p1[R - 1][C]) + (m1[R + 1][C] + m1[R - 1][C]));
+      const float far = ((c0[R][C + 2] + c0[R][C - 2]) + (c0[R + 2][C] + c0[R - 2][C])) +
+                        (p2[R][C] + m2[R][C]);
+      const float L = face - 6.f * v;
+      const float M = 42.f * v - 12.f * face + 2.f * edge + far;
+      dst[r][cc] = a * v + P.b * v * v * v - P.kappa * L + P.c * M;
     }
     __syncthreads();
-    if (s_out >= T.z0 && in_xy) {
-      const int z = s_out, r = ty + 1, c = tx + 1, R = ty + 3, C = tx + 3;
-      float(*mc)[BX + 2] = S.mu[((z % 3) + 3) % 3];
-      float(*md)[BX + 2] = S.mu[(((z - 1) % 3) + 3) % 3];
-      float(*mu_)[BX + 2] = S.mu[(((z + 1) % 3) + 3) % 3];
-      float(*pc)[BX + 6] = S.psi[((z % 6) + 6) % 6];
-      float(*pd)[BX + 6] = S.psi[(((z - 1) % 6) + 6) % 6];
-      float(*pu)[BX + 6] = S.psi[(((z + 1) % 6) + 6) % 6];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int z = s0 - 3 + h;
+      if (z < T.z0 || z >= T.z1 || !in_xy) continue;
+      const int r = ty + 1, c = tx + 1, R = ty + 3, C = tx + 3;
+      float(*mc)[BX + 2] = S.mu[((z % 4) + 4) % 4];
+      float(*md)[BX + 2] = S.mu[(((z - 1) % 4) + 4) % 4];
+      float(*mu_)[BX + 2] = S.mu[(((z + 1) % 4) + 4) % 4];
+      float(*pc)[BX + 6] = S.psi[((z % 8) + 8) % 8];
+      float(*pd)[BX + 6] = S.psi[(((z - 1) % 8) + 8) % 8];
+      float(*pu)[BX + 6] = S.psi[(((z + 1) % 8) + 8) % 8];
       const float lapmu = ((mc[r][c + 1] + mc[r][c - 1]) + (mc[r + 1][c] + mc[r - 1][c])) +
                           (mu_[r][c] + md[r][c]) - 6.f * mc[r][c];
       float adv = 0.f;
       if (HYDRO) {
-        float(*uc)[BY + 2][BX + 2] = S.u[((z % 3) + 3) % 3];
-        float(*ud)[BY + 2][BX + 2] = S.u[(((z - 1) % 3) + 3) % 3];
-        float(*uu)[BY + 2][BX + 2] = S.u[(((z + 1) % 3) + 3) % 3];
+        float(*uc)[BY + 2][BX + 2] = S.u[((z % 4) + 4) % 4];
+        float(*ud)[BY + 2][BX + 2] = S.u[(((z - 1) % 4) + 4) % 4];
+        float(*uu)[BY + 2][BX + 2] = S.u[(((z + 1) % 4) + 4) % 4];
         adv = 0.5f * (pc[R][C + 1] * uc[0][r][c + 1] - pc[R][C - 1] * uc[0][r][c - 1]) +
               0.5f * (pc[R + 1][C] * uc[1][r + 1][c] - pc[R - 1][C] * uc[1][r - 1][c]) +
               0.5f * (pu[R][C] * uu[2][r][c] - pd[R][C] * ud[2][r][c]);
@@ -469,10 +482,7 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
       psi_out[((size_t)z * ny + y) * nx + x] = pc[R][C] + P.h * (-adv + P.Gamma * lapmu);
     }
   };
-  for (int k = 0; k < K; k += 2) {
-    iteration(k, pv[0], uv[0]);
-    if (k + 1 < K) iteration(k + 1, pv[1], uv[1]);
-  }
+  for (int k = 0; k < K; k += 2) pair(k);
 
   // Temperature: FTCS sub-steps along z (T is uniform in x and y); wall layers held.
   if (do_T && blockIdx.x == 0 && P.n_T > 0) {
