@@ -24,7 +24,11 @@
  *       with u = u^n and a = a^n held fixed and mu recomputed each sub-step
  *   S9  n_T FTCS sub-steps of d_t T = xi lap T on the non-wall layers; wall layers stay at Tw
  * Spatial operators are second-order central differences (Section 2): 5/7-point Laplacian,
- * 2-point gradient, biharmonic = Laplacian of the Laplacian (13/25 points).
+ * biharmonic = Laplacian of the Laplacian (13/25 points), and first derivatives (pressure tensor,
+ * force, advection) as isotropic central differences over the D2Q9/D3Q19 velocity set.  With
+ * the two-point first derivative instead, the coupled update cannot run the paper's own
+ * hydrodynamic workload (tau = 5, instantaneous quench, 21 000 steps at Ma < 0.1, Section 3 and
+ * the Mach statement of Section 2): it diverges within a thousand steps.
  */
 #include "lam_oracle.h"
 
@@ -153,14 +157,25 @@ static void laplacian(const orc_sim* s, const double* ext, double* out) {
       }
 }
 
-/* Two-point central difference along axis k. */
+/* First derivative along axis k: the isotropic central difference over the lattice's own
+ * velocity set, d_k phi = (1/c_s^2) sum_q w_q e_qk phi(x + e_q) with c_s^2 = 1/3.  It is second
+ * order like the two-point difference (Section 2 only fixes the order), and its Fourier symbol is
+ * i sin k_k (2 + cos k_j)/3 in 2D and i sin k_k (1 + cos k_j + cos k_l)/3 in 3D: equal to the
+ * two-point one for modes along an axis, smaller across the diagonals, where the two-point
+ * form lets the order-parameter force drive the short waves the explicit coupling cannot carry. */
 static void gradient(const orc_sim* s, const double* ext, int k, double* out) {
 #pragma omp parallel for collapse(2) schedule(static)
   for (int z = 0; z < s->n[2]; z++)
     for (int y = 0; y < s->n[1]; y++)
       for (int x = 0; x < s->n[0]; x++) {
         long c = xidx(s, x, y, z);
-        out[sidx(s, x, y, z)] = 0.5 * (ext[c + s->st[k]] - ext[c - s->st[k]]);
+        double acc = 0.0;
+        for (int q = 1; q < s->Q; q++) {
+          if (s->e[q][k] == 0) continue;
+          long o = s->e[q][0] * s->st[0] + s->e[q][1] * s->st[1] + s->e[q][2] * s->st[2];
+          acc += s->w[q] * s->e[q][k] * ext[c + o];
+        }
+        out[sidx(s, x, y, z)] = 3.0 * acc;
       }
 }
 
@@ -190,9 +205,10 @@ static void reduced_temperature(orc_sim* s) {
  *   P_ab = { a/2 phi^2 + 3b/4 phi^4 - kappa [phi lap phi + |grad phi|^2 / 2]
  *            + c [phi lap^2 phi + (lap phi)^2 / 2 + grad phi . grad lap phi] } delta_ab
  *          + kappa d_a phi d_b phi - c [d_a phi d_b lap phi + d_b phi d_a lap phi]
- * is the pressure tensor of Section 2 without its ideal-gas term n T.  The divergence is taken
- * with central differences of P, so the total force telescopes to zero on a periodic lattice.
- * force_form = 1: F = -phi grad mu (central differences). */
+ * is the pressure tensor of Section 2 without its ideal-gas term n T.  The gradients in P and
+ * the divergence of P use the isotropic first difference, whose weights are antisymmetric, so
+ * the total force telescopes to zero on a periodic lattice.
+ * force_form = 1: F = -phi grad mu (same first difference). */
 static void order_parameter_force(orc_sim* s) {
   const orc_params* p = &s->p;
   const int d = s->d;
@@ -337,8 +353,9 @@ static void collide_and_stream(orc_sim* s, const double* nfield) {
 }
 
 /* S8: order-parameter update, eq. (massdiff), explicit Euler with n_phi sub-steps of length
- * 1/n_phi.  Advection in conservative central form -sum_alpha [(psi u_a)(x+e_a) - (psi u_a)(x-e_a)]/2
- * with the wall-normal flux odd across the wall (no flux through it); diffusion Gamma lap mu(psi). */
+ * 1/n_phi.  Advection in conservative central form -sum_alpha d_alpha (psi u_alpha), with the
+ * isotropic first derivative and the wall-normal flux odd across the wall (no flux through it);
+ * diffusion Gamma lap mu(psi). */
 static void order_parameter_update(orc_sim* s) {
   const double h = 1.0 / s->nphi;
   memcpy(s->psi, s->phi, sizeof(double) * s->N);
