@@ -8,7 +8,9 @@
 //   sites of one column).  Each thread first issues the pulls of its 36 populations (halfway
 //   bounce-back at walls), so that their latency overlaps the stencil work: phi is staged in LDS
 //   with a halo of 3, from which the Laplacian (halo 2) and the pressure tensor (halo 1) are
-//   built in LDS.  Every site then takes the discrete divergence of P, its moments, collides with
+//   built in LDS.  First derivatives (in P, its divergence and the phi advection) are the
+//   isotropic central differences over the D2Q9 set.  Every site then takes the divergence of
+//   P, its moments, collides with
 //   the BGK + forcing rule and writes 9 populations and the force-shifted velocity.
 // phi2d<S>: S explicit Euler sub-steps of the order-parameter equation on a tile with halo 3S,
 //   all in LDS (temporal blocking), reading phi and u once and writing phi once.  The workgroup
@@ -73,6 +75,26 @@ __device__ __forceinline__ void pull9(const ST* __restrict__ G, size_t N, int nx
     g[7] = ld(7, yp, xp);
     g[8] = ld(8, yp, xm);
   }
+}
+
+// The pressure tensor of Section 2 without its ideal-gas term, at one site, from phi, L = lap phi,
+// M = lap L and the first differences of phi and L.  Written with explicit fused multiply-adds and
+// contraction off, so that its rounding is fixed by this source and does not depend on how the
+// compiler schedules a particular tile shape.
+__device__ __forceinline__ void pressure_tensor_2d(const KParams& P, float a, float ph, float L,
+                                                   float M, float px, float py, float Lx,
+                                                   float Ly, float& Pxx, float& Pyy, float& Pxy) {
+#pragma clang fp contract(off)
+  const float ph2 = ph * ph;
+  const float gg = fmaf(px, px, py * py), gL = fmaf(px, Lx, py * Ly);
+  const float tk = fmaf(ph, L, 0.5f * gg);                   // phi lap phi + |grad phi|^2 / 2
+  const float tc = fmaf(ph, M, fmaf(0.5f * L, L, gL));       // phi lap^2 phi + (lap phi)^2/2 + ...
+  const float bulk = ph2 * fmaf(0.75f * P.b, ph2, 0.5f * a);  // a/2 phi^2 + 3b/4 phi^4
+  const float p0 = fmaf(P.c, tc, fmaf(-P.kappa, tk, bulk));
+  const float c2 = -2.f * P.c;
+  Pxx = fmaf(P.kappa * px, px, fmaf(c2 * px, Lx, p0));
+  Pyy = fmaf(P.kappa * py, py, fmaf(c2 * py, Ly, p0));
+  Pxy = fmaf(P.kappa * px, py, -P.c * fmaf(px, Ly, py * Lx));
 }
 
 // One workgroup of 64*TY/SPT threads (TY/SPT waves) per 64 x TY tile; every thread owns the SPT
@@ -154,17 +176,11 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
       if (P.force_form == 1) {
         S.P[0][r][c] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
       } else {
-        float px = 0.5f * (S.phi[R][C + 1] - S.phi[R][C - 1]);
-        float py = 0.5f * (S.phi[R + 1][C] - S.phi[R - 1][C]);
-        float Lx = 0.5f * (S.L[r1][c1 + 1] - S.L[r1][c1 - 1]);
-        float Ly = 0.5f * (S.L[r1 + 1][c1] - S.L[r1 - 1][c1]);
-        float ph2 = ph * ph;
-        float p0 = 0.5f * a * ph2 + 0.75f * P.b * ph2 * ph2 -
-                   P.kappa * (ph * L + 0.5f * (px * px + py * py)) +
-                   P.c * (ph * M + 0.5f * L * L + (px * Lx + py * Ly));
-        S.P[0][r][c] = p0 + P.kappa * px * px - 2.f * P.c * px * Lx;
-        S.P[1][r][c] = p0 + P.kappa * py * py - 2.f * P.c * py * Ly;
-        S.P[2][r][c] = P.kappa * px * py - P.c * (px * Ly + py * Lx);
+        auto fphi = [&](int dr, int dc) { return S.phi[R + dr][C + dc]; };
+        auto fL = [&](int dr, int dc) { return S.L[r1 + dr][c1 + dc]; };
+        const float px = iso2_x(fphi), py = iso2_y(fphi);
+        const float Lx = iso2_x(fL), Ly = iso2_y(fL);
+        pressure_tensor_2d(P, a, ph, L, M, px, py, Lx, Ly, S.P[0][r][c], S.P[1][r][c], S.P[2][r][c]);
       }
     }
     __syncthreads();
@@ -179,19 +195,20 @@ __device__ __forceinline__ void lb2d_tile(const KParams& P, const ST* __restrict
     const int row = ty + NW * j;
     const int x = x0 + tx, y = y0 + row;
     if (x >= nx || y >= ny) continue;
-    // force density: -div P (central differences) or -phi grad mu
+    // force density: -div P or -phi grad mu (isotropic first differences)
     float Fx = 0.f, Fy = 0.f;
     if (P.hydro) {
       const int r = row + 1, c = tx + 1;
+      auto f0 = [&](int dr, int dc) { return S.P[0][r + dr][c + dc]; };
       if (P.force_form == 1) {
         float ph = S.phi[row + 3][tx + 3];
-        Fx = -ph * (0.5f * (S.P[0][r][c + 1] - S.P[0][r][c - 1]));
-        Fy = -ph * (0.5f * (S.P[0][r + 1][c] - S.P[0][r - 1][c]));
+        Fx = -ph * iso2_x(f0);
+        Fy = -ph * iso2_y(f0);
       } else {
-        Fx = -(0.5f * (S.P[0][r][c + 1] - S.P[0][r][c - 1]) +
-               0.5f * (S.P[2][r + 1][c] - S.P[2][r - 1][c]));
-        Fy = -(0.5f * (S.P[2][r][c + 1] - S.P[2][r][c - 1]) +
-               0.5f * (S.P[1][r + 1][c] - S.P[1][r - 1][c]));
+        auto f1 = [&](int dr, int dc) { return S.P[1][r + dr][c + dc]; };
+        auto f2 = [&](int dr, int dc) { return S.P[2][r + dr][c + dc]; };
+        Fx = -(iso2_x(f0) + iso2_y(f2));
+        Fy = -(iso2_x(f2) + iso2_y(f1));
       }
     }
     const float g0 = g[j][0], g1 = g[j][1], g2 = g[j][2], g3 = g[j][3], g4 = g[j][4];
@@ -439,9 +456,9 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
         float lapmu = (Cm[r2][c2 + 1] + Cm[r2][c2 - 1]) + (Cm[r2 + 1][c2] + Cm[r2 - 1][c2]) -
                       4.f * Cm[r2][c2];
         float adv = 0.f;
-        if (HYDRO) {
-          adv = 0.5f * (ps[r][c + 1] * Ux[r2][c2 + 1] - ps[r][c - 1] * Ux[r2][c2 - 1]) +
-                0.5f * (ps[r + 1][c] * Uy[r2 + 1][c2] - ps[r - 1][c] * Uy[r2 - 1][c2]);
+        if (HYDRO) {  // div(psi u), isotropic first differences
+          adv = iso2_x([&](int dr, int dc) { return ps[r + dr][c + dc] * Ux[r2 + dr][c2 + dc]; }) +
+                iso2_y([&](int dr, int dc) { return ps[r + dr][c + dc] * Uy[r2 + dr][c2 + dc]; });
         }
         float v = ps[r][c] + P.h * (-adv + P.Gamma * lapmu);
         if (last) {

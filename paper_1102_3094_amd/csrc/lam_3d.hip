@@ -12,6 +12,8 @@
 // phi3d: per slice, load psi (halo 3) and u (halo 1) -> mu with the 25-point biharmonic (halo 1)
 //   -> psi' = psi + h (Gamma lap mu - div(psi u)) for the output slice.  One Euler sub-step per
 //   launch; the workgroup of tile 0 of the last launch also advances the per-layer temperature.
+// First derivatives (in P, its divergence and the advection) are the isotropic central
+// differences over the D3Q19 set, which reach the edge neighbours in the slices z +- 1.
 #include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
@@ -52,6 +54,30 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P) {
   T.z0 = bz * ZCH;
   T.z1 = min(T.z0 + ZCH, P.nz);
   return T;
+}
+
+// The pressure tensor of Section 2 without its ideal-gas term at one site (xx, yy, zz, xy, xz,
+// yz into dst[k][r][c]); explicit fused multiply-adds with contraction off, as in 2D.
+template <typename D>
+__device__ __forceinline__ void pressure_tensor_3d(const KParams& P, float a, float ph, float L,
+                                                   float M, float px, float py, float pz,
+                                                   float Lx, float Ly, float Lz, D dst, int r,
+                                                   int c) {
+#pragma clang fp contract(off)
+  const float ph2 = ph * ph;
+  const float gg = fmaf(px, px, fmaf(py, py, pz * pz));
+  const float gL = fmaf(px, Lx, fmaf(py, Ly, pz * Lz));
+  const float tk = fmaf(ph, L, 0.5f * gg);
+  const float tc = fmaf(ph, M, fmaf(0.5f * L, L, gL));
+  const float bulk = ph2 * fmaf(0.75f * P.b, ph2, 0.5f * a);
+  const float p0 = fmaf(P.c, tc, fmaf(-P.kappa, tk, bulk));
+  const float c2 = -2.f * P.c, k = P.kappa, mc = -P.c;
+  dst[0][r][c] = fmaf(k * px, px, fmaf(c2 * px, Lx, p0));
+  dst[1][r][c] = fmaf(k * py, py, fmaf(c2 * py, Ly, p0));
+  dst[2][r][c] = fmaf(k * pz, pz, fmaf(c2 * pz, Lz, p0));
+  dst[3][r][c] = fmaf(k * px, py, mc * fmaf(px, Ly, py * Lx));
+  dst[4][r][c] = fmaf(k * px, pz, mc * fmaf(px, Lz, pz * Lx));
+  dst[5][r][c] = fmaf(k * py, pz, mc * fmaf(py, Lz, pz * Ly));
 }
 
 struct Lb3dSmem {
@@ -191,22 +217,15 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
         if (P.force_form == 1) {
           dst[0][r][c] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
         } else {
-          const float px = 0.5f * (pc[R][C + 1] - pc[R][C - 1]);
-          const float py = 0.5f * (pc[R + 1][C] - pc[R - 1][C]);
-          const float pz = 0.5f * (pu[R][C] - pd[R][C]);
-          const float Lx = 0.5f * (lc[r1][c1 + 1] - lc[r1][c1 - 1]);
-          const float Ly = 0.5f * (lc[r1 + 1][c1] - lc[r1 - 1][c1]);
-          const float Lz = 0.5f * (lu[r1][c1] - ld[r1][c1]);
-          const float ph2 = ph * ph;
-          const float p0 = 0.5f * a * ph2 + 0.75f * P.b * ph2 * ph2 -
-                           P.kappa * (ph * L + 0.5f * (px * px + py * py + pz * pz)) +
-                           P.c * (ph * M + 0.5f * L * L + (px * Lx + py * Ly + pz * Lz));
-          dst[0][r][c] = p0 + P.kappa * px * px - 2.f * P.c * px * Lx;
-          dst[1][r][c] = p0 + P.kappa * py * py - 2.f * P.c * py * Ly;
-          dst[2][r][c] = p0 + P.kappa * pz * pz - 2.f * P.c * pz * Lz;
-          dst[3][r][c] = P.kappa * px * py - P.c * (px * Ly + py * Lx);
-          dst[4][r][c] = P.kappa * px * pz - P.c * (px * Lz + pz * Lx);
-          dst[5][r][c] = P.kappa * py * pz - P.c * (py * Lz + pz * Ly);
+          auto fp = [&](int dz, int dr, int dc) {
+            return (dz == 0 ? pc : (dz > 0 ? pu : pd))[R + dr][C + dc];
+          };
+          auto fl = [&](int dz, int dr, int dc) {
+            return (dz == 0 ? lc : (dz > 0 ? lu : ld))[r1 + dr][c1 + dc];
+          };
+          const float px = iso3_x(fp), py = iso3_y(fp), pz = iso3_z(fp);
+          const float Lx = iso3_x(fl), Ly = iso3_y(fl), Lz = iso3_z(fl);
+          pressure_tensor_3d(P, a, ph, L, M, px, py, pz, Lx, Ly, Lz, dst, r, c);
         }
       }
     }
@@ -218,19 +237,21 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
       float(*Pu)[BY + 2][BX + 2] = S.P[(((z + 1) % 3) + 3) % 3];
       float(*pc)[BX + 6] = S.phi[((z % 5) + 5) % 5];
       float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-      if (P.hydro) {
+      if (P.hydro) {  // isotropic first differences of P (or of mu)
+        auto fP = [&](int k) {
+          return [&, k](int dz, int dr, int dc) {
+            return (dz == 0 ? Pc : (dz > 0 ? Pu : Pd))[k][r + dr][c + dc];
+          };
+        };
         if (P.force_form == 1) {
           const float ph = pc[ty + 3][tx + 3];
-          Fx = -ph * (0.5f * (Pc[0][r][c + 1] - Pc[0][r][c - 1]));
-          Fy = -ph * (0.5f * (Pc[0][r + 1][c] - Pc[0][r - 1][c]));
-          Fz = -ph * (0.5f * (Pu[0][r][c] - Pd[0][r][c]));
+          Fx = -ph * iso3_x(fP(0));
+          Fy = -ph * iso3_y(fP(0));
+          Fz = -ph * iso3_z(fP(0));
         } else {
-          Fx = -(0.5f * (Pc[0][r][c + 1] - Pc[0][r][c - 1]) + 0.5f * (Pc[3][r + 1][c] - Pc[3][r - 1][c]) +
-                 0.5f * (Pu[4][r][c] - Pd[4][r][c]));
-          Fy = -(0.5f * (Pc[3][r][c + 1] - Pc[3][r][c - 1]) + 0.5f * (Pc[1][r + 1][c] - Pc[1][r - 1][c]) +
-                 0.5f * (Pu[5][r][c] - Pd[5][r][c]));
-          Fz = -(0.5f * (Pc[4][r][c + 1] - Pc[4][r][c - 1]) + 0.5f * (Pc[5][r + 1][c] - Pc[5][r - 1][c]) +
-                 0.5f * (Pu[2][r][c] - Pd[2][r][c]));
+          Fx = -(iso3_x(fP(0)) + iso3_y(fP(3)) + iso3_z(fP(4)));
+          Fy = -(iso3_x(fP(3)) + iso3_y(fP(1)) + iso3_z(fP(5)));
+          Fz = -(iso3_x(fP(4)) + iso3_y(fP(5)) + iso3_z(fP(2)));
         }
       }
       float dn = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -475,9 +496,14 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
         float(*uc)[BY + 2][BX + 2] = S.u[((z % 4) + 4) % 4];
         float(*ud)[BY + 2][BX + 2] = S.u[(((z - 1) % 4) + 4) % 4];
         float(*uu)[BY + 2][BX + 2] = S.u[(((z + 1) % 4) + 4) % 4];
-        adv = 0.5f * (pc[R][C + 1] * uc[0][r][c + 1] - pc[R][C - 1] * uc[0][r][c - 1]) +
-              0.5f * (pc[R + 1][C] * uc[1][r + 1][c] - pc[R - 1][C] * uc[1][r - 1][c]) +
-              0.5f * (pu[R][C] * uu[2][r][c] - pd[R][C] * ud[2][r][c]);
+        // div(psi u), isotropic first differences
+        auto flux = [&](int k) {
+          return [&, k](int dz, int dr, int dc) {
+            return (dz == 0 ? pc : (dz > 0 ? pu : pd))[R + dr][C + dc] *
+                   (dz == 0 ? uc : (dz > 0 ? uu : ud))[k][r + dr][c + dc];
+          };
+        };
+        adv = iso3_x(flux(0)) + iso3_y(flux(1)) + iso3_z(flux(2));
       }
       psi_out[((size_t)z * ny + y) * nx + x] = pc[R][C] + P.h * (-adv + P.Gamma * lapmu);
     }

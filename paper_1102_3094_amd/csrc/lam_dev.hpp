@@ -124,4 +124,46 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// First derivatives: the isotropic central difference over the lattice's velocity set,
+// d_k f(x) = 3 sum_q w_q e_qk f(x + e_q) (second order; on a mode exp(i k.x) it multiplies by
+// i sin k_x (2 + cos k_y)/3 in 2D and i sin k_x (1 + cos k_y + cos k_z)/3 in 3D).  f(dr, dc) or
+// f(dz, dr, dc) returns the value at the given offset (rows r = y, columns c = x).
+// Contraction into fused multiply-adds is off inside these sums: otherwise a product returned by
+// f (a flux psi u) is fused into the difference only where the compiler did not share it with a
+// neighbouring site, which depends on the tile shape, and the results would differ in the last
+// bit between tile shapes.
+template <typename F>
+__device__ __forceinline__ float iso2_x(F f) {
+#pragma clang fp contract(off)
+  return (1.f / 3.f) * (f(0, 1) - f(0, -1)) +
+         (1.f / 12.f) * ((f(1, 1) - f(1, -1)) + (f(-1, 1) - f(-1, -1)));
+}
+template <typename F>
+__device__ __forceinline__ float iso2_y(F f) {
+#pragma clang fp contract(off)
+  return (1.f / 3.f) * (f(1, 0) - f(-1, 0)) +
+         (1.f / 12.f) * ((f(1, 1) - f(-1, 1)) + (f(1, -1) - f(-1, -1)));
+}
+template <typename F>
+__device__ __forceinline__ float iso3_x(F f) {
+#pragma clang fp contract(off)
+  return (1.f / 6.f) * (f(0, 0, 1) - f(0, 0, -1)) +
+         (1.f / 12.f) * (((f(0, 1, 1) - f(0, 1, -1)) + (f(0, -1, 1) - f(0, -1, -1))) +
+                         ((f(1, 0, 1) - f(1, 0, -1)) + (f(-1, 0, 1) - f(-1, 0, -1))));
+}
+template <typename F>
+__device__ __forceinline__ float iso3_y(F f) {
+#pragma clang fp contract(off)
+  return (1.f / 6.f) * (f(0, 1, 0) - f(0, -1, 0)) +
+         (1.f / 12.f) * (((f(0, 1, 1) - f(0, -1, 1)) + (f(0, 1, -1) - f(0, -1, -1))) +
+                         ((f(1, 1, 0) - f(1, -1, 0)) + (f(-1, 1, 0) - f(-1, -1, 0))));
+}
+template <typename F>
+__device__ __forceinline__ float iso3_z(F f) {
+#pragma clang fp contract(off)
+  return (1.f / 6.f) * (f(1, 0, 0) - f(-1, 0, 0)) +
+         (1.f / 12.f) * (((f(1, 0, 1) - f(-1, 0, 1)) + (f(1, 0, -1) - f(-1, 0, -1))) +
+                         ((f(1, 1, 0) - f(-1, 1, 0)) + (f(1, -1, 0) - f(-1, -1, 0))));
+}
+
 }  // namespace lam

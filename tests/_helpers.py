@@ -1,5 +1,8 @@
 """Shared helpers of the GPU parity tests: run the same seeded workload through the oracle and
 through the C-ABI, and compare."""
+import json
+import os
+
 import numpy as np
 
 import synthetic as S
@@ -34,3 +37,16 @@ def workload(name, **over):
     p = S.model_params(name, **over)
     phi0 = S.initial_phi(name, **{k: v for k, v in over.items() if k in ("nx", "ny", "nz")})
     return p, phi0
+
+
+def horizon_tol(case, steps, bar=1e-5):
+    """The parity bar (rel-L2(phi) <= 1e-5 after 1000 steps) carried to a longer horizon by the
+    scheme's own amplification of an error between step 1000 and `steps`: the ratio of the oracle's
+    sensitivity to a 2^-24 perturbation of phi0 at the two times (tests/golden/sensitivity_floor.json,
+    written from the oracle alone by tests/golden/make_sensitivity.py)."""
+    if steps <= 1000:
+        return bar
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sensitivity_floor.json")
+    with open(path) as f:
+        fl = json.load(f)[case]
+    return bar * fl[str(steps)] / fl["1000"]

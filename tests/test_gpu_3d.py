@@ -41,6 +41,30 @@ def test_parity_3d(gpu, shape, walls):
     assert np.abs(fg["T"] - fo["T"]).max() < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(70, 12, 37), (40, 9, 70)])
+def test_parity_3d_1000_steps(gpu, shape):
+    """The spec bar in 3D with hydrodynamics: 1000 steps at 0.9 Tc walls, rel-L2(phi)
+    <= 1e-5, mass and sum(phi) drift < 1e-6.  (70, 12, 37) spans five chunks of the step kernel
+    (16 slices, ragged last) and two of the phi kernel (64 slices), with a ragged x tile;
+    (40, 9, 70) spans two x tiles and two y tiles (the second one row high)."""
+    nz, ny, nx = shape
+    p = params3(nx=nx, ny=ny, nz=nz, Tw=0.9)
+    phi0 = S.phi0(shape, seed=7)
+    o, g = run_pair(gpu, p, phi0, 0)
+    ob0 = g.observables()
+    o.step(1000)
+    g.step(1000)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert np.abs(fo["phi"]).max() > 0.5
+    err = rel_l2(fg["phi"], fo["phi"])
+    print(f"3d {shape} 1000 steps: rel-L2(phi) {err:.3e} rel-L2(u) {rel_l2(fg['u'], fo['u']):.3e}")
+    assert err <= 1e-5
+    ob = g.observables()
+    N = phi0.size
+    assert abs(ob["mass_dev"] - ob0["mass_dev"]) / N < 1e-6
+    assert abs(ob["phi_sum"] - ob0["phi_sum"]) / N < 1e-6
+
+
 def test_parity_3d_without_hydrodynamics(gpu):
     """The paper's 3D runs solve phi and T only (Section 3, Fig. 3)."""
     p = S.model_params("paper_3d_nohydro", nx=16, ny=16, nz=48)

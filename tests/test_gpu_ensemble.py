@@ -70,3 +70,32 @@ def test_c4_recipe_runs(gpu):
     ens.synchronize()
     obs = [v.observables() for v in ens.sims[:4]]
     assert all(o["step"] == 20 and not o["nonfinite"] for o in obs)
+
+
+def test_c4_extreme_members_against_fp32_and_oracle(gpu):
+    """The smallest and the largest member of the 64-run ensemble workload (FP16 populations, in
+    the ensemble launch) against the same lattice run alone in FP32 and against the FP64 oracle,
+    over 300 steps (with walls at 0.7 Tc the oracle itself goes non-finite between steps 400 and
+    500 on the smallest member).  FP16 storage: rel-L2(phi) <= 1e-3 against both; FP32 solo run:
+    <= 1e-5 against the oracle."""
+    import torch
+    members, phis = S.ensemble_members(seed=1, count=64)
+    sides = [m["nx"] for m in members]
+    picks = [int(np.argmin(sides)), int(np.argmax(sides))]
+    ens = gpu.Ensemble(members).init_fields(phis).step(300)
+    ens.synchronize()
+    for i in picks:
+        m, phi0 = members[i], phis[i]
+        view = gpu_fields(ens.sims[i])
+        solo = gpu.Sim(dict(m, pop_storage=0)).init_fields(torch.tensor(phi0, dtype=torch.float32))
+        solo.step(300)
+        f32 = gpu_fields(solo)
+        o = Oracle(dict(m, pop_storage=0)).init_fields(phi0).step(300)
+        fo = o.fields()
+        assert np.abs(fo["phi"]).max() > 1.0
+        e16_o, e16_32 = rel_l2(view["phi"], fo["phi"]), rel_l2(view["phi"], f32["phi"])
+        e32_o = rel_l2(f32["phi"], fo["phi"])
+        print(f"member {i} side {m['nx']} tau {m['tau']:.3f}: fp16 vs oracle {e16_o:.2e}, "
+              f"fp16 vs fp32 {e16_32:.2e}, fp32 vs oracle {e32_o:.2e}")
+        assert e16_o <= 1e-3 and e16_32 <= 1e-3
+        assert e32_o <= 1e-5

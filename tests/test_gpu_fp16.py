@@ -30,7 +30,7 @@ def test_fp16_parity(gpu, dim):
     else:
         p = S.model_params("c3_256cube_xi0.1", nx=24, ny=16, nz=20, Tw=0.9, pop_storage=1)
         phi0 = S.phi0((20, 16, 24), seed=7)
-        steps = 100
+        steps = 1000
     o, g = run_pair(gpu, p, phi0, 0)
     ob0 = g.observables()
     o.step(steps)

@@ -15,7 +15,7 @@ import pytest
 
 import synthetic as S
 from oracle import Oracle, spectra
-from tests._helpers import gpu_fields, rel_l2, run_pair, workload
+from tests._helpers import gpu_fields, horizon_tol, rel_l2, run_pair, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -56,10 +56,10 @@ def test_parity_1000_steps_lamellar(gpu, steps):
     g.step(steps)
     fo, fg = o.fields(), gpu_fields(g)
     assert np.abs(fo["phi"]).max() > 0.5  # lamellae have formed near the walls
-    # 1e-5 at 1000 steps; FP32 rounding accumulates about linearly (measured ~1e-8 per step), so
-    # longer horizons get 1e-5 per 1000 steps plus a 50% margin
-    tol = 1e-5 if steps <= 1000 else 1.5e-5 * steps / 1000
-    assert rel_l2(fg["phi"], fo["phi"]) <= tol
+    err = rel_l2(fg["phi"], fo["phi"])
+    tol = horizon_tol("c1_64sq_Tw0.9", steps)
+    print(f"0.9 Tc 64^2 {steps} steps: rel-L2(phi) {err:.3e} (bar {tol:.2e})")
+    assert err <= tol
     assert rel_l2(fg["u"], fo["u"]) <= 1e-4
     ob = g.observables()
     N = phi0.size
@@ -69,13 +69,38 @@ def test_parity_1000_steps_lamellar(gpu, steps):
 
 def test_parity_deep_quench_before_breakdown(gpu):
     """The 64x64 workload with walls at 0.7 Tc: compared at 200 steps, while the lamellae grow
-    at the walls; the coupled scheme loses stability near step 250 for these coefficients in the
-    oracle as well."""
+    at the walls.  With these coefficients the ordered bulk state (phi = sqrt 3) is linearly
+    unstable under the explicit coupling, and the oracle itself goes non-finite between steps 400
+    and 500, so no longer horizon can be compared."""
     p, phi0 = workload("c1_64sq")
     o, g = run_pair(gpu, p, phi0, 200)
     fo, fg = o.fields(), gpu_fields(g)
     assert np.abs(fo["phi"]).max() > 1.0
     assert rel_l2(fg["phi"], fo["phi"]) <= 1e-5
+
+
+@pytest.mark.parametrize("steps", [1000, 2000])
+def test_parity_paper_hydrodynamic_quench(gpu, steps):
+    """The paper's own hydrodynamic workload (Section 3): 256^2, b = 0.1, kappa = -c = -0.03,
+    Gamma = 0.1, tau = 5, phi0 in +-0.01, instantaneous quench to 0.9 Tc (the Fig. 2 run with
+    xi = infinity).  rel-L2(phi) <= 1e-5 after 1000 steps, carried to 2000 steps by the oracle's
+    own amplification over that interval; mass and sum(phi) drift < 1e-6; Ma < 0.1 as Section 2
+    states."""
+    p, phi0 = workload("paper_2d_tau5", xi=-1.0)
+    o, g = run_pair(gpu, p, phi0, 0)
+    ob0 = g.observables()
+    o.step(steps)
+    g.step(steps)
+    fo, fg = o.fields(), gpu_fields(g)
+    assert np.abs(fo["phi"]).max() > 0.8  # ordered domains have formed
+    err = rel_l2(fg["phi"], fo["phi"])
+    print(f"paper quench {steps} steps: rel-L2(phi) {err:.3e}, rel-L2(u) {rel_l2(fg['u'], fo['u']):.3e}")
+    assert err <= horizon_tol("paper_2d_tau5_instant", steps)
+    ob = g.observables()
+    N = phi0.size
+    assert abs(ob["mass_dev"] - ob0["mass_dev"]) / N < 1e-6
+    assert abs(ob["phi_sum"] - ob0["phi_sum"]) / N < 1e-6
+    assert ob["mach"] < 0.1 and not ob["nonfinite"]
 
 
 def test_parity_without_hydrodynamics(gpu):
