@@ -120,6 +120,23 @@ int lam_observables(lam_sim* s, lam_obs* h_out);
 int lam_structure_factor(lam_sim* s, double* h_S, int32_t nbins, double* k_peak, double* S_peak,
                          double* k_mean);
 
+/* No-allocation variant of lam_structure_factor, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * structure factor, computed by the same kernels, of a caller-given FP32 field d_phi [ny][nx]
+ * (device memory, row-major) on the stream hip_stream (NULL: default stream), which must belong
+ * to the device current on the calling thread.  Outputs as lam_structure_factor (host memory);
+ * synchronises the stream.  Its scratch (transposed spectrum and per-row shell sums, about
+ * 8 nx ny + 16 nx max(nx, ny) bytes: 24 MiB at 1024^2) lives in a static device array of
+ * LAM_SK_STATIC_BYTES bytes that each GPU holds from the library's first use on it until the
+ * process ends; lattices needing more return LAM_ESIZE, with nothing launched.  It allocates and
+ * frees nothing.  All calls on one GPU share that array: calls that overlap in time on one GPU
+ * (other threads, or other streams of the same device) race and give wrong results; calls made
+ * one after another are safe.  Errors are reported through lam_last_error(NULL). */
+#define LAM_SK_STATIC_BYTES (32u << 20)
+int lam_structure_factor_static(const float* d_phi, int32_t nx, int32_t ny, void* hip_stream,
+                                double* h_S, int32_t nbins, double* k_peak, double* S_peak,
+                                double* k_mean);
+
 /* Orientation of phi gradients (2D only): h_hist[nbins] holds the fraction of sum |grad phi|^2
  * whose gradient angle atan2(g_y, g_x) mod pi falls in each of nbins equal bins of [0, pi);
  * Q = sum(g_y^2 - g_x^2) / sum |grad phi|^2 (+1: lamellae parallel to the walls); h_Qrow[ny]

@@ -41,7 +41,7 @@ EXPORTS = ("lam_workspace_bytes", "lam_create", "lam_substeps", "lam_init_fields
            "lam_observables", "lam_structure_factor", "lam_orientation", "lam_get_fields",
            "lam_state_bytes", "lam_get_state", "lam_set_state", "lam_set_timing",
            "lam_kernel_times", "lam_last_error", "lam_destroy", "lam_set_fields",
-           "lam_advance_temperature",
+           "lam_advance_temperature", "lam_structure_factor_static",
            "lam_ensemble_workspace_bytes", "lam_ensemble_create", "lam_ensemble_member",
            "lam_ensemble_init_fields", "lam_ensemble_step", "lam_ensemble_tune",
            "lam_ensemble_sites", "lam_ensemble_last_error", "lam_ensemble_destroy")
@@ -68,6 +68,8 @@ def load():
     L.lam_observables.argtypes = [vp, C.POINTER(lam_obs)]
     L.lam_structure_factor.argtypes = [vp, dp, C.c_int32, dp, dp, dp]
     L.lam_orientation.argtypes = [vp, dp, C.c_int32, dp, dp]
+    L.lam_structure_factor_static.argtypes = [vp, C.c_int32, C.c_int32, vp, dp, C.c_int32, dp,
+                                              dp, dp]
     L.lam_get_fields.argtypes = [vp, vp, vp, vp, vp]
     L.lam_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.lam_get_state.argtypes = [vp, vp, C.c_size_t]
@@ -127,6 +129,26 @@ def workspace_bytes(params: dict) -> int:
     q = make_params(params)
     _check(load().lam_workspace_bytes(C.byref(q), C.byref(n)))
     return n.value
+
+
+LAM_SK_STATIC_BYTES = 32 << 20
+
+
+def structure_factor_static(phi, nbins: int, stream=None) -> dict:
+    """S(k) of a 2D FP32 device field phi (ny, nx) through lam_structure_factor_static: no
+    device memory is allocated; the scratch is the library's static device array.  The stream
+    defaults to torch's current stream of phi's device."""
+    import torch
+    assert phi.is_cuda and phi.dtype == torch.float32 and phi.dim() == 2 and phi.is_contiguous()
+    ny, nx = phi.shape
+    with torch.cuda.device(phi.device):
+        st = stream if stream is not None else torch.cuda.current_stream(phi.device)
+        S = (C.c_double * nbins)()
+        kp, Sp, km = C.c_double(), C.c_double(), C.c_double()
+        _check(load().lam_structure_factor_static(C.c_void_p(phi.data_ptr()), nx, ny,
+                                                  C.c_void_p(st.cuda_stream), S, nbins,
+                                                  C.byref(kp), C.byref(Sp), C.byref(km)))
+    return dict(S=list(S), k_peak=kp.value, S_peak=Sp.value, k_mean=km.value)
 
 
 class Sim:

@@ -55,6 +55,8 @@ hipError_t structure_factor_2d(const KParams& P, const float* phi, void* scratch
                                hipStream_t st);
 hipError_t orientation_2d(const KParams& P, const float* phi, void* scratch, int nbins,
                           double* h_hist, double* h_Q, double* h_Qrow, hipStream_t st);
+size_t static_scratch_capacity();
+hipError_t static_scratch(int device, void** out);
 }  // namespace lam
 
 using namespace lam;
@@ -485,6 +487,40 @@ int lam_structure_factor(lam_sim* s, double* h_S, int32_t nbins, double* k_peak,
   if (nbins > std::max(s->p.nx, s->p.ny)) return fail(s, LAM_EINVAL, "nbins > max(nx, ny)");
   HIPCHK(s, structure_factor_2d(s->k, s->phi[s->step & 1], s->spec, nbins, h_S, k_peak, S_peak,
                                 k_mean, s->st));
+  return LAM_OK;
+}
+
+int lam_structure_factor_static(const float* d_phi, int32_t nx, int32_t ny, void* hip_stream,
+                                double* h_S, int32_t nbins, double* k_peak, double* S_peak,
+                                double* k_mean) {
+  if (!d_phi || !h_S || nbins < 3 || nx < 1 || ny < 1)
+    return fail(nullptr, LAM_EINVAL, "bad arguments (need d_phi, h_S, nbins >= 3)");
+  if (nbins > std::max(nx, ny)) return fail(nullptr, LAM_EINVAL, "nbins > max(nx, ny)");
+  const size_t need = spectra_scratch_bytes(nx, ny);
+  if (need > static_scratch_capacity())
+    return fail(nullptr, LAM_ESIZE,
+                "lattice needs " + std::to_string(need) + " bytes of scratch; the static array "
+                "holds " + std::to_string(static_scratch_capacity()) + " (LAM_SK_STATIC_BYTES)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (st) {
+    hipDevice_t sdev = -1;
+    e = hipStreamGetDevice(st, &sdev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipStreamGetDevice");
+    if (sdev != dev)
+      return fail(nullptr, LAM_EINVAL, "the stream belongs to another device than the current one");
+  }
+  void* scr = nullptr;
+  e = static_scratch(dev, &scr);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+  KParams k{};
+  k.nx = nx;
+  k.ny = ny;
+  k.nz = 1;
+  e = structure_factor_2d(k, d_phi, scr, nbins, h_S, k_peak, S_peak, k_mean, st);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "structure factor");
   return LAM_OK;
 }
 

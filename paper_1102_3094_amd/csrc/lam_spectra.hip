@@ -8,6 +8,9 @@
 // twiddles are evaluated in FP64 and rounded once.  Each shell of a transposed row is summed by one thread over its own
 // contiguous range of |m_y| (the shell index is monotone in |m_y|), so the sums have a fixed order;
 // rows are then combined in a fixed order.
+#include <mutex>
+
+#include "../../include/lam.h"
 #include "lam_dev.hpp"
 
 namespace lam {
@@ -328,6 +331,35 @@ hipError_t structure_factor_2d(const KParams& P, const float* phi, void* scratch
   if (h_kpeak) *h_kpeak = tail[0];
   if (h_Speak) *h_Speak = tail[1];
   if (h_kmean) *h_kmean = tail[2];
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Static scratch of the no-allocation structure factor (lam_structure_factor_static).  Each GPU
+// the library runs on holds its own copy of this array until the process ends.  In host code
+// its name is not a device address: the address comes from hipGetSymbolAddress, looked up once
+// per device with that device current and kept below; only that address reaches the kernels.
+// No part of it needs clearing: every value the structure-factor kernels read was written
+// earlier in the same call.
+static __device__ __align__(256) unsigned char scratch[LAM_SK_STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+size_t static_scratch_capacity() { return sizeof(scratch); }
+
+hipError_t static_scratch(int device, void** out) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
   return hipSuccess;
 }
 
