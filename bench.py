@@ -10,8 +10,12 @@ histogram are taken every 1000 steps inside the timed region.
 Prints one JSON line: MLUPS (million lattice-site updates per second), the roofline of the
 dominant kernel (fused force/stream/collide kernel; algorithmic bytes per site: populations read
 and written, 2 x 9 x 4 B, plus phi read, 4 B = 76 B in 2D; 2 x 19 x 4 + 4 = 156 B in 3D), and the
-FP64 CPU oracle's MLUPS on a bounded sample of the same workload.  --workload selects another
-named workload (for example the 256^3 D3Q19 lattice) for the same measurement.
+FP64 CPU oracle's MLUPS on a bounded sample of the same workload (built with gcc -O3
+-march=native on the host at run time; CPU model recorded).  The 1024^2 working set (about
+100 MB) stays in the 256 MB Infinity Cache, so its bandwidth is a past-L2 figure; the line
+therefore also carries "hbm_legs": the 4096^2 D2Q9 and 256^3 D3Q19 workloads (1.4 and 3.3 GB),
+each with its MLUPS, dominant-kernel and whole-step roofline fractions and its own CPU
+baseline.  --workload selects another named workload for the headline measurement.
 
 The same line carries the learned-surrogate leg ("surrogate"): a U-Net (BF16 matrix-core kernels)
 trained on the GPU on snapshots of plain 512^2 runs (one-step rounds, then two-step training),
@@ -31,6 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "c2_1024sq_tau0.6"
+# working sets far above the 256 MB Infinity Cache: the HBM figures (steps timed per leg)
+HBM_LEGS = (("m1_4096sq", 200), ("c3_256cube_xi0.1", 60))
 HBM_PEAK_GBS = 8000.0
 OBS_EVERY = 1000
 
@@ -85,9 +91,44 @@ def traffic_from_profiles(workload, dim):
     return d.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """(CPU model name, threads this process may run on)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+_ORACLE_BUILD = []
+
+
+def native_oracle():
+    """Build the oracle with gcc -O3 -march=native for this host (once per process, into a
+    temporary directory) and load it for the CPU baseline; falls back to the -O2 build."""
+    if not _ORACLE_BUILD:
+        import subprocess
+        import tempfile
+        import oracle
+        from oracle.build import build_native
+        try:
+            d = tempfile.mkdtemp(prefix="lam_oracle_")
+            oracle.use_library(build_native(os.path.join(d, "liblam_oracle_native.so")))
+            _ORACLE_BUILD.append("gcc -O3 -march=native -fopenmp")
+        except (OSError, subprocess.CalledProcessError, RuntimeError):
+            _ORACLE_BUILD.append("gcc -O2 -fopenmp (native build failed)")
+    return _ORACLE_BUILD[0]
+
+
 def cpu_baseline(params, phi0, budget_s=12.0, single_s=4.0):
-    """The FP64 oracle on the host: all OpenMP threads for about budget_s, then one thread for
-    about single_s (at least one step each)."""
+    """The FP64 oracle on the host: all OpenMP threads for about budget_s, then (unless single_s
+    is None) one thread for about single_s; at least one step each, after one untimed step."""
+    build = native_oracle()
     import oracle
     n = params["nx"] * params["ny"] * (params["nz"] if params["dim"] == 3 else 1)
 
@@ -100,18 +141,25 @@ def cpu_baseline(params, phi0, budget_s=12.0, single_s=4.0):
             o.step(1)
             steps += 1
         dt = time.perf_counter() - t0
+        del o
         return n * steps / dt / 1e6, steps, dt
 
     cores = oracle.threads()
     v, steps, dt = rate(budget_s)
-    oracle.threads(1)
-    v1, steps1, dt1 = rate(single_s)
-    oracle.threads(cores)
     shape = "x".join(str(params[k]) for k in (("nx", "ny") if params["dim"] == 2 else ("nx", "ny", "nz")))
-    return {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} steps of the {shape} workload ({dt:.1f} s, FP64, OpenMP over sites); "
-                      f"one thread: {steps1} steps in {dt1:.1f} s",
-            "single_thread_value": v1}
+    sample = f"{steps} steps of the {shape} workload ({dt:.1f} s, FP64, OpenMP over sites)"
+    out = {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle", "sample": sample,
+           "build": build}
+    if single_s is not None:
+        oracle.threads(1)
+        v1, steps1, dt1 = rate(single_s)
+        oracle.threads(cores)
+        out["sample"] += f"; one thread: {steps1} steps in {dt1:.1f} s"
+        out["single_thread_value"] = v1
+    model, avail = host_cpu()
+    out["cpu_model"] = model
+    out["host_threads_available"] = avail
+    return out
 
 
 def bench_ensemble(args):
@@ -325,6 +373,8 @@ def main():
                     help="the batched ensemble instead: 64 uneven 2D lattices, FP16 populations")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named workload of synthetic.WORKLOADS (default: the 1024^2 lattice)")
+    ap.add_argument("--no-hbm-legs", action="store_true",
+                    help="skip the 4096^2 and 256^3 legs (working sets above the last-level cache)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the GPU, about a minute)")
     ap.add_argument("--surrogate-train-steps", type=int, default=6000)
@@ -368,48 +418,112 @@ def main():
               flush=True)
         return
     wl = args.workload
+    if args.profile_pass:
+        return profile_pass(lam, S, wl, args)
+    head = measure(lam, S, wl, args.steps, args.warmup, args.pop_storage, OBS_EVERY)
+    out = {
+        "metric": "MLUPS + % HBM roofline; surrogate vs plain wall-time at equal S(k) peak error",
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if not args.pop_storage else "f32 (populations stored f16)",
+        "data": "synthetic",
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "step_effective_roofline_frac": head["step_effective_roofline_frac"],
+        "kernel_avg_us": head["kernel_avg_us"],
+        "state_finite_at_end": head["state_finite_at_end"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(head["params"], head["phi0"])
+    del head
+    torch.cuda.empty_cache()
+    if not args.no_hbm_legs and wl == WORKLOAD:
+        legs = []
+        for name, steps in HBM_LEGS:
+            leg = measure(lam, S, name, steps, 10, args.pop_storage, None)
+            rec = {k: leg[k] for k in ("config", "roofline", "step_effective_roofline_frac",
+                                        "kernel_avg_us", "state_finite_at_end", "ms_per_step")}
+            rec["value"] = leg["mlups"]
+            rec["unit"] = "MLUPS"
+            rec["steps"] = steps
+            if not args.no_cpu_baseline:
+                rec["cpu_baseline"] = cpu_baseline(leg["params"], leg["phi0"], budget_s=6.0,
+                                                   single_s=3.0 if leg["params"]["dim"] == 2 else None)
+            legs.append(rec)
+            del leg
+            torch.cuda.empty_cache()
+        out["hbm_legs"] = legs
+    if not args.no_surrogate and wl == WORKLOAD:
+        out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
+                                           density=bool(args.surrogate_density),
+                                           unroll_steps=args.surrogate_two_step,
+                                           curves=args.surrogate_curves,
+                                           anchor_steps=args.surrogate_anchor_steps)
+    print(json.dumps(out), flush=True)
+
+
+def profile_pass(lam, S, wl, args):
+    """For rocprofv3 counter runs: warmup + steps steps of the workload, then one plain device
+    copy of 512 MiB whose counters calibrate the byte counts."""
+    import torch
     p = S.model_params(wl, pop_storage=args.pop_storage)
+    sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(S.initial_phi(wl), dtype=torch.float32))
+    sim.step(args.warmup)
+    sim.step(args.steps)
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_pass": True, "workload": wl, "steps": args.steps,
+                      "copy_bytes": src.numel() * 4}))
+
+
+def measure(lam, S, wl, steps, warmup, pop_storage, obs_every):
+    """Time `steps` steps of workload `wl` (after `warmup`), then the same number again with HIP
+    events on every kernel launch for the per-kernel durations.  With obs_every, the structure
+    factor and the orientation histogram are taken every obs_every steps (2D) inside the timed
+    region."""
+    import torch
+    p = S.model_params(wl, pop_storage=pop_storage)
     phi0 = S.initial_phi(wl)
     dim = p["dim"]
     n_sites = p["nx"] * p["ny"] * (p["nz"] if dim == 3 else 1)
-    lb_bytes, step_bytes = byte_model(dim, 2 if args.pop_storage else 4)
+    lb_bytes, step_bytes = byte_model(dim, 2 if pop_storage else 4)
     sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(phi0, dtype=torch.float32))
     n_phi, n_T = sim.substeps
-    if args.profile_pass:
-        sim.step(args.warmup)
-        sim.step(args.steps)
-        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_pass": True, "steps": args.steps, "copy_bytes": src.numel() * 4}))
-        return
-
     sim_step = [0]
 
     def run(k):
         done = 0
         while done < k:
-            chunk = min(OBS_EVERY - (sim_step[0] % OBS_EVERY), k - done)
+            chunk = k - done
+            if obs_every:
+                chunk = min(obs_every - (sim_step[0] % obs_every), chunk)
             sim.step(chunk)
             done += chunk
             sim_step[0] += chunk
-            if sim_step[0] % OBS_EVERY == 0 and dim == 2:
+            if obs_every and sim_step[0] % obs_every == 0 and dim == 2:
                 sim.structure_factor(min(p["nx"], p["ny"]) // 2)
                 sim.orientation(18)
 
-    run(args.warmup)
+    run(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(args.steps)
+    run(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    mlups = n_sites * args.steps / dt / 1e6
-
+    mlups = n_sites * steps / dt / 1e6
     # second pass of the same length; every kernel launch carries HIP events (kernel timestamps)
     # on the library's stream
     sim.set_timing(True)
-    run(args.steps)
+    run(steps)
     kt = sim.kernel_times()
     sim.set_timing(False)
     lb_ms, lb_n = kt["lb"]
@@ -417,53 +531,38 @@ def main():
     lb_avg_s = lb_ms / max(lb_n, 1) / 1e3
     achieved = lb_bytes * n_sites / lb_avg_s / 1e9
     q = 9 if dim == 2 else 19
-    copy_gbps = copy_ceiling_gbps(q * n_sites * (2 if args.pop_storage else 4))
+    copy_gbps = copy_ceiling_gbps(q * n_sites * (2 if pop_storage else 4))
     ob = sim.observables()
     kname = "lb2d" if dim == 2 else "lb3d"
     shape = "x".join(str(p[k]) for k in (("nx", "ny") if dim == 2 else ("nx", "ny", "nz")))
     lattice = "D2Q9" if dim == 2 else "D3Q19"
-    extras = f", S(k)+orientation every {OBS_EVERY} steps" if dim == 2 else ""
-
-    out = {
-        "metric": "MLUPS + % HBM roofline; surrogate vs plain wall-time at equal S(k) peak error",
-        "value": round(mlups, 1),
-        "unit": "MLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if not args.pop_storage else "f32 (populations stored f16)",
-        "data": "synthetic",
+    extras = f", S(k)+orientation every {obs_every} steps" if (obs_every and dim == 2) else ""
+    ws = (2 * q * (2 if pop_storage else 4) + 4 * 4 + 4 * dim) * n_sites
+    resident = ws < 256e6
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(wl, dim),
+            "kernel": f"{kname} (force + stream + collide)",
+            "copy_ceiling": round(copy_gbps, 1),
+            "frac_of_copy_ceiling": round(achieved / copy_gbps, 4),
+            "bytes_per_site": lb_bytes, "avg_launch_us": lb_avg_s * 1e6, "launches": lb_n,
+            "working_set_MB": round(ws / 1e6, 1),
+            "level": ("past-L2: the working set fits the 256 MB Infinity Cache, so this is not an "
+                      "HBM figure" if resident else "HBM: the working set exceeds the 256 MB "
+                      "Infinity Cache")}
+    return {
+        "params": p, "phi0": phi0, "mlups": round(mlups, 1), "ms_per_step": dt / steps * 1e3,
         "config": {"workload": f"{lattice} {shape} cold walls, tau={p['tau']}, xi={p['xi']}, "
                                f"n_phi={n_phi}, n_T={n_T}{extras}",
                    "name": wl, "lattice": lattice, "shape": shape, "tau": p["tau"],
-                   "pop_storage": "fp16" if args.pop_storage else "fp32",
+                   "pop_storage": "fp16" if pop_storage else "fp32",
                    "xi": p["xi"], "n_phi_sub": n_phi, "seed": 1},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(wl, dim),
-                     "kernel": f"{kname} (force + stream + collide)",
-                     "copy_ceiling": round(copy_gbps, 1),
-                     "frac_of_copy_ceiling": round(achieved / copy_gbps, 4),
-                     "bytes_per_site": lb_bytes, "avg_launch_us": lb_avg_s * 1e6,
-                     "launches": lb_n},
+        "roofline": roof,
         "step_effective_roofline_frac": round(mlups * 1e6 * step_bytes / 8e12, 4),
         "kernel_avg_us": {kname: lb_avg_s * 1e6,
                           ("phi2d" if dim == 2 else "phi3d"): phi_ms / max(phi_n, 1) * 1e3},
         "state_finite_at_end": not ob["nonfinite"],
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, phi0)
-    if not args.no_surrogate and dim == 2 and wl == WORKLOAD:
-        out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
-                                           density=bool(args.surrogate_density),
-                                           unroll_steps=args.surrogate_two_step,
-                                           curves=args.surrogate_curves,
-                                           anchor_steps=args.surrogate_anchor_steps)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -19,6 +19,16 @@ from .build import LIB_PATH, build as _build
 from .spectra import orientation, structure_factor  # noqa: F401
 
 _lib = None
+_lib_path = LIB_PATH
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (the CPU baseline's -O3
+    -march=native build); only before the first use in the process."""
+    global _lib_path
+    if _lib is not None and path != _lib_path:
+        raise RuntimeError("the oracle library is already loaded from " + _lib_path)
+    _lib_path = path
 
 
 class orc_params(C.Structure):
@@ -40,9 +50,9 @@ class orc_obs(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if _lib_path == LIB_PATH and not os.path.exists(LIB_PATH):
             _build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(_lib_path)
         dp = C.POINTER(C.c_double)
         L.orc_create.argtypes = [C.POINTER(orc_params), C.POINTER(C.c_void_p)]
         L.orc_destroy.argtypes = [C.c_void_p]
