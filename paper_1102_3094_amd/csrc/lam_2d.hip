@@ -417,6 +417,11 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
   }
   __syncthreads();
 
+  // Both phases work on vertical strips of KS cells: a thread keeps the column values its strip
+  // shares in registers (the 13-point biharmonic reads 7 instead of 13 LDS values per cell, the
+  // update 15.5 instead of 30).  Consecutive lanes take consecutive columns.  Rows beyond a
+  // plane's valid depth are clamped into the array and only feed cells that are not computed.
+  constexpr int KS = 4;
   float(*ps)[W] = A;   // current psi
   float(*nx_)[W] = B;  // next psi
 #pragma unroll
@@ -424,16 +429,39 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
     const int d = 3 * s;
     {  // mu at depth d + 2: lap^2 as the 13-point square of the 5-point Laplacian
       const int dd = d + 2, hh = H - 2 * dd, ww = W - 2 * dd;
-#pragma unroll 2
-      for (int i = tid; i < hh * ww; i += NTH) {
-        int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
-        const float v = ps[r][c];
-        const float e = ps[r][c + 1], w = ps[r][c - 1], n = ps[r + 1][c], so = ps[r - 1][c];
-        const float L = (e + w) + (n + so) - 4.f * v;
-        const float diag = (ps[r + 1][c + 1] + ps[r + 1][c - 1]) + (ps[r - 1][c + 1] + ps[r - 1][c - 1]);
-        const float far = (ps[r][c + 2] + ps[r][c - 2]) + (ps[r + 2][c] + ps[r - 2][c]);
-        const float M = 20.f * v - 8.f * ((e + w) + (n + so)) + 2.f * diag + far;
-        Cm[r - 2][c - 2] = sa[r] * v + P.b * v * v * v - P.kappa * L + P.c * M;
+      const int nst = ww * ((hh + KS - 1) / KS);
+      for (int t = tid; t < nst; t += NTH) {
+        const int rb = t / ww;
+        const int c = dd + (t - rb * ww), r0 = dd + KS * rb;
+        const int kk = min(KS, H - dd - r0);
+        float cC[KS + 4], cL[KS + 2], cR[KS + 2], cLL[KS], cRR[KS];
+#pragma unroll
+        for (int j = 0; j < KS + 4; ++j) cC[j] = ps[min(r0 - 2 + j, H - 1)][c];
+#pragma unroll
+        for (int j = 0; j < KS + 2; ++j) {
+          const int rr = min(r0 - 1 + j, H - 1);
+          cL[j] = ps[rr][c - 1];
+          cR[j] = ps[rr][c + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          const int rr = min(r0 + j, H - 1);
+          cLL[j] = ps[rr][c - 2];
+          cRR[j] = ps[rr][c + 2];
+        }
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+          if (i < kk) {
+            const int r = r0 + i;
+            const float v = cC[i + 2];
+            const float e = cR[i + 1], w = cL[i + 1], n = cC[i + 3], so = cC[i + 1];
+            const float L = (e + w) + (n + so) - 4.f * v;
+            const float diag = (cR[i + 2] + cL[i + 2]) + (cR[i] + cL[i]);
+            const float far = (cRR[i] + cLL[i]) + (cC[i + 4] + cC[i]);
+            const float M = 20.f * v - 8.f * ((e + w) + (n + so)) + 2.f * diag + far;
+            Cm[r - 2][c - 2] = sa[r] * v + P.b * v * v * v - P.kappa * L + P.c * M;
+          }
+        }
       }
     }
     if (HYDRO && s == 0) {
@@ -449,23 +477,60 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
     {  // psi' at depth d + 3
       const int dd = d + 3, hh = H - 2 * dd, ww = W - 2 * dd;
       const bool last = s == S_ - 1;
-#pragma unroll 2
-      for (int i = tid; i < hh * ww; i += NTH) {
-        int r = dd + i / ww, c = dd + (i - (i / ww) * ww);
-        const int r2 = r - 2, c2 = c - 2;
-        float lapmu = (Cm[r2][c2 + 1] + Cm[r2][c2 - 1]) + (Cm[r2 + 1][c2] + Cm[r2 - 1][c2]) -
-                      4.f * Cm[r2][c2];
-        float adv = 0.f;
-        if (HYDRO) {  // div(psi u), isotropic first differences
-          adv = iso2_x([&](int dr, int dc) { return ps[r + dr][c + dc] * Ux[r2 + dr][c2 + dc]; }) +
-                iso2_y([&](int dr, int dc) { return ps[r + dr][c + dc] * Uy[r2 + dr][c2 + dc]; });
+      const int nst = ww * ((hh + KS - 1) / KS);
+      for (int t = tid; t < nst; t += NTH) {
+        const int rb = t / ww;
+        const int c = dd + (t - rb * ww), r0 = dd + KS * rb;
+        const int kk = min(KS, H - dd - r0);
+        const int c2 = c - 2;  // column in the planes that start at depth 2 (mu, velocity)
+        // mu: column c rows r0 - 1 .. r0 + KS, columns c +- 1 rows r0 .. r0 + KS - 1
+        float mC[KS + 2], mL[KS], mR[KS];
+#pragma unroll
+        for (int j = 0; j < KS + 2; ++j) mC[j] = Cm[min(r0 - 3 + j, HU - 1)][c2];
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          const int rr = min(r0 - 2 + j, HU - 1);
+          mL[j] = Cm[rr][c2 - 1];
+          mR[j] = Cm[rr][c2 + 1];
         }
-        float v = ps[r][c] + P.h * (-adv + P.Gamma * lapmu);
-        if (last) {
-          int y = y0 - R + r, x = x0 - R + c;
-          if (x < nx && y < ny) psi_out[(size_t)y * nx + x] = v;
-        } else {
-          nx_[r][c] = v;
+        // psi in columns c - 1, c, c + 1, rows r0 - 1 .. r0 + KS, and the fluxes psi u there
+        float pC[KS + 2], pL[KS + 2], pR[KS + 2];
+        float jxL[KS + 2], jxR[KS + 2], jyL[KS + 2], jyC[KS + 2], jyR[KS + 2];
+#pragma unroll
+        for (int j = 0; j < KS + 2; ++j) {
+          const int rr = min(r0 - 1 + j, H - 1);
+          pC[j] = ps[rr][c];
+          pL[j] = ps[rr][c - 1];
+          pR[j] = ps[rr][c + 1];
+          if (HYDRO) {
+            const int ru = min(r0 - 3 + j, HU - 1);
+            jxL[j] = pL[j] * Ux[ru][c2 - 1];
+            jxR[j] = pR[j] * Ux[ru][c2 + 1];
+            jyL[j] = pL[j] * Uy[ru][c2 - 1];
+            jyC[j] = pC[j] * Uy[ru][c2];
+            jyR[j] = pR[j] * Uy[ru][c2 + 1];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+          if (i < kk) {
+            const int r = r0 + i;
+            const float lapmu = (mR[i] + mL[i]) + (mC[i + 2] + mC[i]) - 4.f * mC[i + 1];
+            float adv = 0.f;
+            if (HYDRO) {  // div(psi u), isotropic first differences
+              adv = iso2_x([&](int dr, int dc) { return dc > 0 ? jxR[i + 1 + dr] : jxL[i + 1 + dr]; }) +
+                    iso2_y([&](int dr, int dc) {
+                      return dc == 0 ? jyC[i + 1 + dr] : (dc > 0 ? jyR[i + 1 + dr] : jyL[i + 1 + dr]);
+                    });
+            }
+            const float v = pC[i + 1] + P.h * (-adv + P.Gamma * lapmu);
+            if (last) {
+              const int y = y0 - R + r, x = x0 - R + c;
+              if (x < nx && y < ny) psi_out[(size_t)y * nx + x] = v;
+            } else {
+              nx_[r][c] = v;
+            }
+          }
         }
       }
     }
