@@ -163,8 +163,9 @@ def cpu_baseline(params, phi0, budget_s=12.0, single_s=4.0):
 
 
 def bench_ensemble(args):
-    """64 independent lattices (sides 128-512, xi and tau swept) in one launch per kernel,
-    autotuned tile height, step pairs replayed from a HIP graph."""
+    """64 independent lattices (sides 128-512, xi and tau swept) in one persistent launch per
+    kernel (work queues over the members' tiles), autotuned tile height and grid size, step pairs
+    replayed from a HIP graph."""
     import torch
     import paper_1102_3094_amd as lam
     import synthetic as S
@@ -187,7 +188,8 @@ def bench_ensemble(args):
            "vs_baseline": None, "dtype": "f32 (populations stored f16)", "data": "synthetic",
            "config": {"workload": "64 D2Q9 lattices, sides log-uniform 128-512, xi log-uniform "
                                   "1e-3..1, tau uniform 0.55..3.0, cold walls, seed 1",
-                      "sites": sites, "tile_height": tile},
+                      "sites": sites, "tile_height": tile,
+                      "persistent_workgroups": ens.workgroups},
            "step_effective_roofline_frac": round(mlups * 1e6 * step_bytes / 8e12, 4)}
     print(json.dumps(out), flush=True)
 

@@ -180,11 +180,12 @@ const char* lam_last_error(const lam_sim* s);
 void lam_destroy(lam_sim* s);
 
 /* Ensembles: independent 2D simulations of different sizes and parameters (for example sweeps in
- * xi and viscosity, Section 3) advanced together.  Every time step is one launch of the LB kernel
- * and one launch of the phi kernel over the tiles of all members (workgroups map to
- * (member, tile) through a tile table), so small lattices fill the GPU together; with a non-NULL
- * stream, pairs of steps are captured once in a HIP graph and replayed.  Each member computes
- * exactly what it computes alone (bit for bit, at the same tile height).
+ * xi and viscosity, Section 3) advanced together.  Every time step is one persistent launch of the
+ * LB kernel and one of the phi kernel: a grid of a few workgroups per compute unit takes
+ * (member, tile) work items from per-XCD queues until none is left (no workgroup waits for
+ * another; the last one to finish resets the queues), so small lattices fill the GPU together;
+ * with a non-NULL stream, pairs of steps are captured once in a HIP graph and replayed.  Each
+ * member computes exactly what it computes alone (bit for bit, at the same tile height).
  * Requirements: all members 2D with the same hydro flag, pop_storage and phi sub-step count.
  * Memory: one caller workspace of lam_ensemble_workspace_bytes() bytes holds every member. */
 typedef struct lam_ensemble lam_ensemble;
@@ -197,9 +198,12 @@ int lam_ensemble_member(lam_ensemble* e, int32_t i, lam_sim** out);
 /* d_phi0: host array of count device pointers to each member's initial phi. */
 int lam_ensemble_init_fields(lam_ensemble* e, const float* const* d_phi0);
 int lam_ensemble_step(lam_ensemble* e, int64_t nsteps);
-/* Autotuner: times `steps` steps at each tile height (16, 32, 64), keeps the fastest and
- * returns it.  It advances the members' state: call it before lam_ensemble_init_fields. */
-int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height);
+/* Autotuner: times `steps` steps for every tile height (8, 16, 32, 64) and grid (one workgroup
+ * per tile without a queue, reported as 0 workgroups, or a persistent grid of 1, 2 or 4
+ * workgroups per compute unit), keeps the fastest and returns it (either output may be NULL).
+ * It must come before lam_ensemble_init_fields (LAM_EINVAL otherwise): it times a fixed state
+ * (phi = 0, fluid at rest) and leaves the members uninitialised. */
+int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height, int32_t* workgroups);
 int lam_ensemble_sites(const lam_ensemble* e, int64_t* sites);
 const char* lam_ensemble_last_error(const lam_ensemble* e);
 void lam_ensemble_destroy(lam_ensemble* e);

@@ -87,7 +87,7 @@ def load():
     L.lam_ensemble_member.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     L.lam_ensemble_init_fields.argtypes = [vp, C.POINTER(vp)]
     L.lam_ensemble_step.argtypes = [vp, C.c_int64]
-    L.lam_ensemble_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+    L.lam_ensemble_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lam_ensemble_sites.argtypes = [vp, C.POINTER(C.c_int64)]
     L.lam_ensemble_last_error.argtypes = [vp]
     L.lam_ensemble_last_error.restype = C.c_char_p
@@ -377,8 +377,12 @@ class Ensemble:
         return self
 
     def tune(self, steps: int = 20) -> int:
-        th = C.c_int32()
-        _check_ens(load().lam_ensemble_tune(self._h, int(steps), C.byref(th)), self._h)
+        """Autotune before init_fields; returns the tile height (the persistent grid size is
+        kept in self.workgroups)."""
+        th, wg = C.c_int32(), C.c_int32()
+        _check_ens(load().lam_ensemble_tune(self._h, int(steps), C.byref(th), C.byref(wg)),
+                   self._h)
+        self.workgroups = wg.value
         return th.value
 
     def synchronize(self):

@@ -301,19 +301,84 @@ __global__ __launch_bounds__(lb2d_threads(TY)) void lb2d_kernel(KParams P, const
                           (t / nbx) * TY, S);
 }
 
-// Ensemble: workgroup b takes tile xcd_tile(b, ntiles) of the concatenated tile lists of all
-// members; the member's tiles are then processed exactly as in a single simulation.
+// Ensembles: a persistent launch.  The grid is a few workgroups per compute unit; each takes work
+// items (a member's tile) from a queue until none is left.  The items of the concatenated tile
+// lists are split into eight contiguous ranges, one per XCD (workgroup b runs on XCD b mod 8), so
+// that tiles sharing halo lines run under the same L2, and each range has its own counter in
+// q[0..7].  A workgroup asks for its next item when it starts a tile, so the atomic's latency is
+// hidden behind the tile.  No workgroup waits for another: the last one to finish (counter q[8])
+// resets the counters for the next launch, so a replayed graph needs no reset node.  With q null
+// the launch has one workgroup per item instead (no queue).  A tile computes the same values
+// whichever workgroup takes it.
+constexpr int ENS_QUEUE_WORDS = 9;
+
+struct EnsQueue {
+  unsigned* q;
+  int ntiles, base, count;  // this workgroup's XCD range
+  int ticket;               // thread 0: the ticket of the next item, fetched ahead
+
+  __device__ __forceinline__ EnsQueue(unsigned* q_, int ntiles_) : q(q_), ntiles(ntiles_) {
+    const int k = blockIdx.x & 7;
+    const int qq = ntiles >> 3, rr = ntiles & 7;
+    base = k < rr ? k * (qq + 1) : rr * (qq + 1) + (k - rr) * qq;
+    count = qq + (k < rr ? 1 : 0);
+    ticket = 0;
+  }
+  __device__ __forceinline__ void request() {
+    if (q && threadIdx.x == 0) ticket = (int)atomicAdd(&q[blockIdx.x & 7], 1u);
+  }
+  // The item of the ticket requested last (-1: none left), broadcast to the workgroup.
+  __device__ __forceinline__ int take(int* slot) {
+    if (!q) return -1;
+    if (threadIdx.x == 0) *slot = ticket < count ? base + ticket : -1;
+    __syncthreads();
+    const int t = *slot;
+    __syncthreads();  // every thread has read it before thread 0 writes the next one
+    return t;
+  }
+  __device__ __forceinline__ void finish() {
+    if (q && threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(&q[8], 1u) == gridDim.x - 1) {  // every workgroup has taken its last ticket
+        for (int k = 0; k < ENS_QUEUE_WORDS; ++k) atomicExch(&q[k], 0u);
+        __threadfence();
+      }
+    }
+  }
+};
+
+// Runs body(t) for every item this workgroup gets.
+template <typename Body>
+__device__ __forceinline__ void ens_for_each_item(unsigned* q, int ntiles, Body body) {
+  __shared__ int slot;
+  if (!q) {
+    if ((int)blockIdx.x < ntiles) body(xcd_tile(blockIdx.x, ntiles));
+    return;
+  }
+  EnsQueue Q(q, ntiles);
+  Q.request();
+  int t = Q.take(&slot);
+  while (t >= 0) {
+    Q.request();   // the next item, fetched while this one is computed
+    body(t);
+    __syncthreads();  // the next tile rewrites the LDS tables
+    t = Q.take(&slot);
+  }
+  Q.finish();
+}
+
 template <int TY, typename ST>
 __global__ __launch_bounds__(lb2d_threads(TY)) void lb2d_ens_kernel(const EnsMember* __restrict__ mem,
                                                            const int* __restrict__ tile_member,
-                                                           int ntiles, int cur) {
+                                                           int ntiles, int cur, unsigned* q) {
   __shared__ Lb2dSmem<TY> S;
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  const EnsMember& M = mem[tile_member[t]];
-  const KParams P = M.P;
-  const int lt = t - M.tile0, nbx = (P.nx + TX - 1) / TX;
-  lb2d_tile<TY, MODE_STEP, ST>(P, (const ST*)M.g[cur], (ST*)M.g[cur ^ 1], M.phi[cur], M.T[cur],
-                               M.u, nullptr, nullptr, (lt % nbx) * TX, (lt / nbx) * TY, S);
+  ens_for_each_item(q, ntiles, [&](int t) {
+    const EnsMember& M = mem[tile_member[t]];
+    const KParams P = M.P;
+    const int lt = t - M.tile0, nbx = (P.nx + TX - 1) / TX;
+    lb2d_tile<TY, MODE_STEP, ST>(P, (const ST*)M.g[cur], (ST*)M.g[cur ^ 1], M.phi[cur], M.T[cur],
+                                 M.u, nullptr, nullptr, (lt % nbx) * TX, (lt / nbx) * TY, S);
+  });
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -574,22 +639,24 @@ __global__ __launch_bounds__(16 * TY) void phi2d_kernel(KParams P, const float* 
                             (t / nbx) * TY, Sm);
 }
 
-// Ensemble: one launch over the tiles of all members; pass > 0 selects the member's phi scratch
-// buffers for chained launches (more sub-steps than one launch fuses).
+// Ensemble: a persistent launch over the tiles of all members (work queue as for the LB kernel);
+// pass > 0 selects the member's phi scratch buffers for chained launches (more sub-steps than one
+// launch fuses).
 template <int S_, int TY, bool HYDRO>
 __global__ __launch_bounds__(16 * TY) void phi2d_ens_kernel(const EnsMember* __restrict__ mem,
                                                             const int* __restrict__ tile_member,
                                                             int ntiles, int cur, int pass,
-                                                            int last) {
+                                                            int last, unsigned* q) {
   __shared__ Phi2dSmem<S_, TY, HYDRO> Sm;
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  const EnsMember& M = mem[tile_member[t]];
-  const KParams P = M.P;
-  const int lt = t - M.tile0, nbx = (P.nx + TX - 1) / TX;
-  const float* in = pass == 0 ? M.phi[cur] : M.psi[(pass - 1) & 1];
-  float* out = last ? M.phi[cur ^ 1] : M.psi[pass & 1];
-  phi2d_tile<S_, TY, HYDRO>(P, in, out, M.u, M.T[cur], M.T[cur ^ 1], M.T[2],
-                            last && P.n_T > 0, lt, (lt % nbx) * TX, (lt / nbx) * TY, Sm);
+  ens_for_each_item(q, ntiles, [&](int t) {
+    const EnsMember& M = mem[tile_member[t]];
+    const KParams P = M.P;
+    const int lt = t - M.tile0, nbx = (P.nx + TX - 1) / TX;
+    const float* in = pass == 0 ? M.phi[cur] : M.psi[(pass - 1) & 1];
+    float* out = last ? M.phi[cur ^ 1] : M.psi[pass & 1];
+    phi2d_tile<S_, TY, HYDRO>(P, in, out, M.u, M.T[cur], M.T[cur ^ 1], M.T[2],
+                              last && P.n_T > 0, lt, (lt % nbx) * TX, (lt / nbx) * TY, Sm);
+  });
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -684,22 +751,26 @@ hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, flo
   return hipGetLastError();
 }
 
-// Ensemble launchers: one LB launch and ceil(n_phi / 2) phi launches per step, all members.
+// Ensemble launchers: one LB launch and ceil(n_phi / 2) phi launches per step, all members, each a
+// persistent grid of `grid` workgroups (grid 0: one workgroup per tile, no queue).  q: two queues
+// of ENS_QUEUE_WORDS counters (LB, phi), zero before the first launch.
 template <int TY>
 static void ens_step_ty(const EnsMember* mem, const int* tile_member, int ntiles, int cur,
-                        int half, int hydro, int nphi, hipStream_t st) {
-  dim3 grid(ntiles), block(16 * TY), lb_block(lb2d_threads(TY));
+                        int half, int hydro, int nphi, int grid, unsigned* q, hipStream_t st) {
+  if (grid == 0) q = nullptr;
+  dim3 g(grid ? grid : ntiles), block(16 * TY), lb_block(lb2d_threads(TY));
   if (hydro) {
-    if (half) hipLaunchKernelGGL((lb2d_ens_kernel<TY, __half>), grid, lb_block, 0, st, mem, tile_member, ntiles, cur);
-    else hipLaunchKernelGGL((lb2d_ens_kernel<TY, float>), grid, lb_block, 0, st, mem, tile_member, ntiles, cur);
+    if (half) hipLaunchKernelGGL((lb2d_ens_kernel<TY, __half>), g, lb_block, 0, st, mem, tile_member, ntiles, cur, q);
+    else hipLaunchKernelGGL((lb2d_ens_kernel<TY, float>), g, lb_block, 0, st, mem, tile_member, ntiles, cur, q);
   }
+  unsigned* qp = q ? q + ENS_QUEUE_WORDS : nullptr;
   int remaining = nphi, pass = 0;
   while (remaining > 0) {
     const int sub = remaining >= 2 ? 2 : 1;
     const int last = remaining == sub;
 #define ENS_PHI(S_, H_)                                                                          \
-  hipLaunchKernelGGL((phi2d_ens_kernel<S_, TY, H_>), grid, block, 0, st, mem, tile_member, ntiles, \
-                     cur, pass, last)
+  hipLaunchKernelGGL((phi2d_ens_kernel<S_, TY, H_>), g, block, 0, st, mem, tile_member, ntiles,  \
+                     cur, pass, last, qp)
     if (sub == 2) {
       if (hydro) ENS_PHI(2, true);
       else ENS_PHI(2, false);
@@ -713,11 +784,16 @@ static void ens_step_ty(const EnsMember* mem, const int* tile_member, int ntiles
   }
 }
 
+int ens_queue_words() { return 2 * ENS_QUEUE_WORDS; }
+
 hipError_t launch_ens_step(const EnsMember* mem, const int* tile_member, int ntiles, int ty,
-                           int cur, int half, int hydro, int nphi, hipStream_t st) {
-  if (ty == 16) ens_step_ty<16>(mem, tile_member, ntiles, cur, half, hydro, nphi, st);
-  else if (ty == 32) ens_step_ty<32>(mem, tile_member, ntiles, cur, half, hydro, nphi, st);
-  else if (ty == 64) ens_step_ty<64>(mem, tile_member, ntiles, cur, half, hydro, nphi, st);
+                           int cur, int half, int hydro, int nphi, int grid, unsigned* q,
+                           hipStream_t st) {
+  if (grid != 0 && (grid < 8 || (grid & 7))) return hipErrorInvalidValue;
+  if (ty == 8) ens_step_ty<8>(mem, tile_member, ntiles, cur, half, hydro, nphi, grid, q, st);
+  else if (ty == 16) ens_step_ty<16>(mem, tile_member, ntiles, cur, half, hydro, nphi, grid, q, st);
+  else if (ty == 32) ens_step_ty<32>(mem, tile_member, ntiles, cur, half, hydro, nphi, grid, q, st);
+  else if (ty == 64) ens_step_ty<64>(mem, tile_member, ntiles, cur, half, hydro, nphi, grid, q, st);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

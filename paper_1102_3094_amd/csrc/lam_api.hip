@@ -32,7 +32,9 @@ hipError_t launch_phi3d(const KParams& P, const float* in, float* out, const flo
                         const float* T, float* Tn, float* Ts, int do_T, hipStream_t st,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_ens_step(const EnsMember* mem, const int* tile_member, int ntiles, int ty,
-                           int cur, int half, int hydro, int nphi, hipStream_t st);
+                           int cur, int half, int hydro, int nphi, int grid, unsigned* q,
+                           hipStream_t st);
+int ens_queue_words();
 // lam_util.hip
 hipError_t launch_init(const KParams& P, int dim, const float* n0, const float* u0, void* g,
                        hipStream_t st);
@@ -621,7 +623,9 @@ struct lam_ensemble {
   std::vector<int> host_tiles;
   EnsMember* d_members = nullptr;
   int* d_tile_member = nullptr;
+  unsigned* d_queue = nullptr;  // work-queue counters of the persistent kernels
   int ntiles = 0, ty = 32, nphi = 1, hydro = 1, half = 0;
+  int cus = 256, grid = 512;  // compute units; workgroups of the persistent launches
   hipStream_t st = nullptr;
   hipGraphExec_t graph = nullptr;
   int64_t sites = 0;
@@ -638,7 +642,7 @@ int efail(lam_ensemble* e, int code, const std::string& msg) {
 
 struct EnsLayout {
   std::vector<size_t> off, bytes;
-  size_t members, tiles, total;
+  size_t members, tiles, queue, total;
 };
 
 int ens_layout(const lam_params* m, int count, EnsLayout& L, std::string& why) {
@@ -657,12 +661,14 @@ int ens_layout(const lam_params* m, int count, EnsLayout& L, std::string& why) {
     L.off.push_back(off);
     L.bytes.push_back(b);
     off = align256(off + b);
-    maxtiles += (size_t)((m[i].nx + 63) / 64) * ((m[i].ny + 15) / 16);
+    maxtiles += (size_t)((m[i].nx + 63) / 64) * ((m[i].ny + 7) / 8);  // smallest tile height
   }
   L.members = off;
   off = align256(off + sizeof(EnsMember) * count);
   L.tiles = off;
   off = align256(off + sizeof(int) * maxtiles);
+  L.queue = off;
+  off = align256(off + sizeof(unsigned) * ens_queue_words());
   L.total = off;
   return LAM_OK;
 }
@@ -694,7 +700,7 @@ int ens_build_tiles(lam_ensemble* e, int ty) {
 
 hipError_t ens_one_step(lam_ensemble* e, int cur) {
   return launch_ens_step(e->d_members, e->d_tile_member, e->ntiles, e->ty, cur, e->half, e->hydro,
-                         e->nphi, e->st);
+                         e->nphi, e->grid, e->d_queue, e->st);
 }
 
 }  // namespace
@@ -751,6 +757,19 @@ int lam_ensemble_create(const lam_params* members, int32_t count, void* d_worksp
   e->half = members[0].pop_storage == 1;
   e->d_members = (EnsMember*)(ws + L.members);
   e->d_tile_member = (int*)(ws + L.tiles);
+  e->d_queue = (unsigned*)(ws + L.queue);
+  {  // the queues start at zero; afterwards every launch leaves them at zero
+    int dev = 0, cus = 0;
+    hipError_t r = hipGetDevice(&dev);
+    if (r == hipSuccess) r = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (r == hipSuccess) r = hipMemsetAsync(e->d_queue, 0, sizeof(unsigned) * ens_queue_words(), e->st);
+    if (r != hipSuccess) {
+      lam_ensemble_destroy(e);
+      return efail(nullptr, LAM_EHIP, std::string("ensemble queues: ") + hipGetErrorString(r));
+    }
+    e->cus = std::max(8, (cus + 7) / 8 * 8);
+    e->grid = 2 * e->cus;  // persistent, two workgroups per compute unit, until tuned
+  }
   rc = ens_build_tiles(e, 32);
   if (rc) {
     std::string msg = e->err;
@@ -822,43 +841,63 @@ int lam_ensemble_step(lam_ensemble* e, int64_t nsteps) {
   return LAM_OK;
 }
 
-int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height) {
+int lam_ensemble_tune(lam_ensemble* e, int32_t steps, int32_t* tile_height,
+                      int32_t* workgroups) {
   if (!e || steps < 1) return efail(e, LAM_EINVAL, "bad arguments");
-  for (lam_sim* s : e->sims) s->initialised = true;  // timing does not depend on the values
+  for (lam_sim* s : e->sims)
+    if (s->initialised)
+      return efail(e, LAM_EINVAL, "lam_ensemble_tune must come before lam_ensemble_init_fields");
+  // a fixed state to time (phi = 0, fluid at rest, T as at the start); the members are left
+  // uninitialised again afterwards
+  for (lam_sim* s : e->sims) {
+    hipError_t r = hipMemsetAsync(s->psi[0], 0, sizeof(float) * s->N, s->st);
+    if (r != hipSuccess) return efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(r));
+    int rc = lam_init_fields(s, s->psi[0], nullptr, nullptr);
+    if (rc) return efail(e, rc, "tuning: " + s->err);
+  }
   hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-    if (a) (void)hipEventDestroy(a);
-    return efail(e, LAM_EHIP, "event creation");
-  }
-  const int cand[3] = {16, 32, 64};
-  int best = 32;
-  float best_ms = 1e30f;
   int rc = LAM_OK;
-  for (int c : cand) {
-    if ((rc = ens_build_tiles(e, c)) || (rc = lam_ensemble_step(e, 2))) break;
-    hipError_t h;
-    if ((h = hipEventRecord(a, e->st))) {
-      rc = efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(h));
-      break;
-    }
-    if ((rc = lam_ensemble_step(e, steps))) break;
-    float ms = 0.f;
-    if ((h = hipEventRecord(b, e->st)) || (h = hipEventSynchronize(b)) ||
-        (h = hipEventElapsedTime(&ms, a, b))) {
-      rc = efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(h));
-      break;
-    }
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    rc = efail(e, LAM_EHIP, "event creation");
+  // grids: one workgroup per tile (0), or 1, 2, 4 persistent workgroups per compute unit
+  const int heights[4] = {8, 16, 32, 64}, per_cu[4] = {0, 1, 2, 4};
+  int best_ty = 32, best_grid = 0;
+  float best_ms = 1e30f;
+  for (int hi = 0; hi < 4 && !rc; ++hi) {
+    for (int gi = 0; gi < 4 && !rc; ++gi) {
+      e->grid = per_cu[gi] * e->cus;
+      if ((rc = ens_build_tiles(e, heights[hi])) || (rc = lam_ensemble_step(e, 2))) break;
+      hipError_t h;
+      if ((h = hipEventRecord(a, e->st))) {
+        rc = efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(h));
+        break;
+      }
+      if ((rc = lam_ensemble_step(e, steps))) break;
+      float ms = 0.f;
+      if ((h = hipEventRecord(b, e->st)) || (h = hipEventSynchronize(b)) ||
+          (h = hipEventElapsedTime(&ms, a, b))) {
+        rc = efail(e, LAM_EHIP, std::string("tuning: ") + hipGetErrorString(h));
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_ty = heights[hi];
+        best_grid = e->grid;
+      }
     }
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  for (lam_sim* s : e->sims) {
+    s->initialised = false;
+    s->step = 0;
+  }
   if (rc) return rc;
-  rc = ens_build_tiles(e, best);
+  e->grid = best_grid;
+  rc = ens_build_tiles(e, best_ty);
   if (rc) return rc;
-  if (tile_height) *tile_height = best;
+  if (tile_height) *tile_height = best_ty;
+  if (workgroups) *workgroups = best_grid;
   return LAM_OK;
 }
 

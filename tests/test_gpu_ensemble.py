@@ -49,12 +49,20 @@ def test_members_match_oracle(gpu):
 
 
 def test_tuner_then_parity(gpu):
+    """The tuner picks a tile height and a persistent grid, leaves the members uninitialised,
+    refuses to run after init_fields, and the tuned ensemble still matches solo runs bit for bit."""
     import torch
     members, phis = small_members(1)
     ens = gpu.Ensemble(members)
     th = ens.tune(4)
-    assert th in (16, 32, 64)
-    ens.init_fields(phis).step(12)
+    assert th in (8, 16, 32, 64)
+    assert ens.workgroups == 0 or (ens.workgroups >= 8 and ens.workgroups % 8 == 0)
+    with pytest.raises(gpu.LamError):
+        ens.step(1)  # the tuner leaves the fields uninitialised
+    ens.init_fields(phis)
+    with pytest.raises(gpu.LamError):
+        ens.tune(2)  # tuning would overwrite the initialised state
+    ens.step(12)
     ens.synchronize()
     m, phi0, view = members[2], phis[2], ens.sims[2]
     solo = gpu.Sim(dict(m, tile_hint=th)).init_fields(torch.tensor(phi0, dtype=torch.float32))
