@@ -498,7 +498,9 @@ def measure(lam, S, wl, steps, warmup, pop_storage, obs_every):
     dim = p["dim"]
     n_sites = p["nx"] * p["ny"] * (p["nz"] if dim == 3 else 1)
     lb_bytes, step_bytes = byte_model(dim, 2 if pop_storage else 4)
-    sim = lam.Sim(p, device="cuda:0").init_fields(torch.tensor(phi0, dtype=torch.float32))
+    # a stream of its own: lam_step then replays captured pairs of steps from a HIP graph
+    sim = lam.Sim(p, device="cuda:0", stream=torch.cuda.Stream(device="cuda:0"))
+    sim.init_fields(torch.tensor(phi0, dtype=torch.float32))
     n_phi, n_T = sim.substeps
     sim_step = [0]
 

@@ -105,8 +105,18 @@ int lam_substeps(const lam_sim* s, int32_t* n_phi, int32_t* n_T);
  * xi < 0).  Device pointers; the data are copied.  Resets the step counter to 0. */
 int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const float* d_n0);
 
-/* Advance nsteps time steps; asynchronous on the simulation's stream. */
+/* Advance nsteps time steps; asynchronous on the simulation's stream.  On a stream of the caller
+ * (not the legacy default stream), with timing off and outside a capture the caller runs on that
+ * stream, pairs of steps can be replayed from a HIP graph captured on first use.  The first call
+ * of at least 24 steps measures 8 directly launched steps against 4 replayed pairs (that call
+ * waits for them) and keeps the faster way for the simulation's life; the fields are bit-identical
+ * either way.  The roctx range "lam_step" marks every call. */
 int lam_step(lam_sim* s, int64_t nsteps);
+
+/* The launch mode lam_step settled on: *graphs = -1 (not measured yet), 0 (direct launches) or 1
+ * (graph replays), and the measured microseconds per step of each (0 before the measurement). Any
+ * output pointer may be NULL. */
+int lam_launch_mode(const lam_sim* s, int32_t* graphs, float* direct_us, float* graph_us);
 
 /* Conserved totals and monitors of the current state (FP64 reductions); synchronises. Returns
  * LAM_ENONFINITE (with *h_out filled) if the state holds NaN or infinite values. */

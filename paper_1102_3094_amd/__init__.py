@@ -41,7 +41,7 @@ EXPORTS = ("lam_workspace_bytes", "lam_create", "lam_substeps", "lam_init_fields
            "lam_observables", "lam_structure_factor", "lam_orientation", "lam_get_fields",
            "lam_state_bytes", "lam_get_state", "lam_set_state", "lam_set_timing",
            "lam_kernel_times", "lam_last_error", "lam_destroy", "lam_set_fields",
-           "lam_advance_temperature", "lam_structure_factor_static",
+           "lam_advance_temperature", "lam_structure_factor_static", "lam_launch_mode",
            "lam_ensemble_workspace_bytes", "lam_ensemble_create", "lam_ensemble_member",
            "lam_ensemble_init_fields", "lam_ensemble_step", "lam_ensemble_tune",
            "lam_ensemble_sites", "lam_ensemble_last_error", "lam_ensemble_destroy")
@@ -75,6 +75,8 @@ def load():
     L.lam_get_state.argtypes = [vp, vp, C.c_size_t]
     L.lam_set_state.argtypes = [vp, vp, C.c_size_t]
     L.lam_set_timing.argtypes = [vp, C.c_int32]
+    L.lam_launch_mode.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float),
+                                  C.POINTER(C.c_float)]
     L.lam_kernel_times.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.lam_last_error.argtypes = [vp]
     L.lam_set_fields.argtypes = [vp, vp, vp, vp]
@@ -301,6 +303,13 @@ class Sim:
     def set_state(self, buf):
         self._chk(load().lam_set_state(self._h, C.c_void_p(buf.data_ptr()), buf.numel()))
         return self
+
+    def launch_mode(self) -> dict:
+        """How lam_step launches: graphs -1 (not measured yet), 0 direct, 1 graph replays; the
+        measured microseconds per step of each."""
+        g, d, r = C.c_int32(), C.c_float(), C.c_float()
+        self._chk(load().lam_launch_mode(self._h, C.byref(g), C.byref(d), C.byref(r)))
+        return dict(graphs=g.value, direct_us=d.value, graph_us=r.value)
 
     def set_timing(self, enable: bool = True):
         self._chk(load().lam_set_timing(self._h, int(enable)))

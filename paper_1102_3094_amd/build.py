@@ -19,7 +19,9 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
     tmp = LIB_PATH + ".tmp"
-    cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-o", tmp, *srcs]
+    # roctx ranges around lam_step (visible with rocprofv3 --marker-trace)
+    cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-o", tmp, *srcs, "-L/opt/rocm/lib",
+           "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/lam.h"
 #include "lam_dev.hpp"
 
@@ -92,6 +94,11 @@ struct lam_sim {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_cls;
   size_t ev_used = 0;
+  // two time steps (even then odd) captured once and replayed by lam_step, when that measured
+  // faster than direct launches (graph_mode: -1 not yet measured, 0 direct, 1 graph)
+  hipGraphExec_t pair_graph = nullptr;
+  int graph_mode = -1;
+  float direct_us = 0.f, graph_us = 0.f;  // per step, as measured
 };
 
 namespace {
@@ -409,43 +416,148 @@ int lam_kernel_times(lam_sim* s, double* h_ms, int64_t* h_launches, int32_t nk) 
   return LAM_OK;
 }
 
-int lam_step(lam_sim* s, int64_t nsteps) {
-  if (!s || nsteps < 0) return fail(s, LAM_EINVAL, "bad arguments");
-  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+}  // extern "C"
+
+namespace {
+
+// The launches of one time step from parity cur (every argument depends only on the parity).
+int one_step(lam_sim* s, int cur) {
   const KParams& k = s->k;
   const bool d3 = s->p.dim == 3;
   const int maxsub = d3 ? 1 : phi2d_max_sub();
-  for (int64_t t = 0; t < nsteps; ++t) {
-    const int cur = (int)(s->step & 1), nxt = cur ^ 1;
-    if (k.hydro) {
-      EvPair ev = timing_slot(s, LAM_K_LB);
-      if (d3)
-        HIPCHK(s, launch_lb3d(k, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur], s->u,
-                              nullptr, nullptr, s->st, ev.a, ev.b));
-      else
-        HIPCHK(s, launch_lb2d(k, s->ty_lb, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur],
-                              s->T[cur], s->u, nullptr, nullptr, s->st, ev.a, ev.b));
-    }
-    int remaining = s->nphi, which = 0;
-    const float* src = s->phi[cur];
-    while (remaining > 0) {
-      int sub = std::min(remaining, maxsub);
-      bool last = remaining == sub;
-      float* dst = last ? s->phi[nxt] : s->psi[which];
-      which ^= 1;
-      EvPair ev = timing_slot(s, LAM_K_PHI);
-      const int do_T = last && k.n_T > 0;
-      if (d3)
-        HIPCHK(s, launch_phi3d(k, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2], do_T, s->st,
-                               ev.a, ev.b));
-      else
-        HIPCHK(s, launch_phi2d(k, s->ty_phi, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
-                               do_T, s->st, ev.a, ev.b));
-      src = dst;
-      remaining -= sub;
-    }
-    s->step++;
+  const int nxt = cur ^ 1;
+  if (k.hydro) {
+    EvPair ev = timing_slot(s, LAM_K_LB);
+    if (d3)
+      HIPCHK(s, launch_lb3d(k, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur], s->T[cur], s->u,
+                            nullptr, nullptr, s->st, ev.a, ev.b));
+    else
+      HIPCHK(s, launch_lb2d(k, s->ty_lb, MODE_STEP, s->g[cur], s->g[nxt], s->phi[cur],
+                            s->T[cur], s->u, nullptr, nullptr, s->st, ev.a, ev.b));
   }
+  int remaining = s->nphi, which = 0;
+  const float* src = s->phi[cur];
+  while (remaining > 0) {
+    int sub = std::min(remaining, maxsub);
+    bool last = remaining == sub;
+    float* dst = last ? s->phi[nxt] : s->psi[which];
+    which ^= 1;
+    EvPair ev = timing_slot(s, LAM_K_PHI);
+    const int do_T = last && k.n_T > 0;
+    if (d3)
+      HIPCHK(s, launch_phi3d(k, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2], do_T, s->st,
+                             ev.a, ev.b));
+    else
+      HIPCHK(s, launch_phi2d(k, s->ty_phi, sub, src, dst, s->u, s->T[cur], s->T[nxt], s->T[2],
+                             do_T, s->st, ev.a, ev.b));
+    src = dst;
+    remaining -= sub;
+  }
+  return LAM_OK;
+}
+
+// Captures the step pair (parity 0, then 1) on the simulation's stream into s->pair_graph.
+int capture_pair(lam_sim* s) {
+  hipGraph_t g = nullptr;
+  hipError_t r = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+  if (r != hipSuccess) return hip_fail(s, r, "hipStreamBeginCapture");
+  int rc = one_step(s, 0);
+  if (rc == LAM_OK) rc = one_step(s, 1);
+  hipError_t r2 = hipStreamEndCapture(s->st, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (r2 != hipSuccess) return hip_fail(s, r2, "hipStreamEndCapture");
+  r = hipGraphInstantiate(&s->pair_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (r != hipSuccess) {
+    s->pair_graph = nullptr;
+    return hip_fail(s, r, "hipGraphInstantiate");
+  }
+  return LAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lam_step(lam_sim* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return fail(s, LAM_EINVAL, "bad arguments");
+  if (!s->initialised) return fail(s, LAM_EINVAL, "fields not initialised");
+  roctxRangePushA("lam_step");
+  int rc = LAM_OK;
+  int64_t done = 0;
+  auto direct = [&](int64_t n) {
+    for (int64_t i = 0; i < n && rc == LAM_OK; ++i) {
+      rc = one_step(s, (int)(s->step & 1));
+      if (rc == LAM_OK) {
+        s->step++;
+        done++;
+      }
+    }
+  };
+  auto replay = [&](int64_t pairs) {
+    for (int64_t i = 0; i < pairs && rc == LAM_OK; ++i) {
+      hipError_t r = hipGraphLaunch(s->pair_graph, s->st);
+      if (r != hipSuccess) {
+        rc = hip_fail(s, r, "hipGraphLaunch");
+        break;
+      }
+      s->step += 2;
+      done += 2;
+    }
+  };
+  // Graph replays of step pairs are possible on a stream of the caller (not the legacy default
+  // stream) with timing off, when the stream is not itself being captured by the caller (then the
+  // launches go into that capture).  Whether they are faster than direct launches is measured
+  // once, on the first call long enough for it: 8 direct steps against 4 replayed pairs, timed
+  // with events (these are steps of the call; that call waits for them).
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool graphs = s->st != nullptr && !s->timing && s->graph_mode != 0 && nsteps >= 3 &&
+                      hipStreamIsCapturing(s->st, &cs) == hipSuccess &&
+                      cs == hipStreamCaptureStatusNone;
+  if (graphs && (s->graph_mode == 1 || nsteps >= 24)) {
+    if (s->step & 1) direct(1);  // reach an even step first
+    if (rc == LAM_OK && !s->pair_graph) rc = capture_pair(s);
+    if (rc == LAM_OK && s->graph_mode < 0) {
+      hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+      hipError_t r = hipSuccess;
+      for (int i = 0; i < 3 && r == hipSuccess; ++i) r = hipEventCreate(&e[i]);
+      if (r == hipSuccess) r = hipEventRecord(e[0], s->st);
+      if (r == hipSuccess) direct(8);
+      if (r == hipSuccess && rc == LAM_OK) r = hipEventRecord(e[1], s->st);
+      if (r == hipSuccess && rc == LAM_OK) replay(4);
+      if (r == hipSuccess && rc == LAM_OK) r = hipEventRecord(e[2], s->st);
+      float t_direct = 0.f, t_graph = 0.f;
+      if (r == hipSuccess && rc == LAM_OK) r = hipEventSynchronize(e[2]);
+      if (r == hipSuccess && rc == LAM_OK) r = hipEventElapsedTime(&t_direct, e[0], e[1]);
+      if (r == hipSuccess && rc == LAM_OK) r = hipEventElapsedTime(&t_graph, e[1], e[2]);
+      for (int i = 0; i < 3; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+      if (r != hipSuccess && rc == LAM_OK) rc = hip_fail(s, r, "graph timing");
+      if (rc == LAM_OK) {
+        s->direct_us = t_direct * 1e3f / 8.f;
+        s->graph_us = t_graph * 1e3f / 8.f;
+        s->graph_mode = t_graph < t_direct ? 1 : 0;
+      }
+    }
+    if (rc == LAM_OK && s->graph_mode == 1) {
+      roctxRangePushA("lam_step graph replays");
+      replay((nsteps - done) / 2);
+      roctxRangePop();
+    }
+  }
+  direct(nsteps - done);
+  roctxRangePop();
+  return rc;
+}
+
+int lam_launch_mode(const lam_sim* s, int32_t* graphs, float* direct_us, float* graph_us) {
+  if (!s) return fail(nullptr, LAM_EINVAL, "null simulation");
+  if (graphs) *graphs = s->graph_mode;
+  if (direct_us) *direct_us = s->direct_us;
+  if (graph_us) *graph_us = s->graph_us;
   return LAM_OK;
 }
 
@@ -610,6 +722,7 @@ const char* lam_last_error(const lam_sim* s) {
 void lam_destroy(lam_sim* s) {
   if (!s) return;
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  if (s->pair_graph) (void)hipGraphExecDestroy(s->pair_graph);
   delete s;
 }
 

@@ -105,6 +105,19 @@ def test_checkpoint_and_roll_3d(gpu):
     assert np.array_equal(np.roll(gpu_fields(ref)["phi"], (3, 5), axis=(1, 2)), gpu_fields(c)["phi"])
 
 
+def test_graph_replay_matches_direct_launches_3d(gpu):
+    """As in 2D: graph-replayed step pairs and direct launches give bit-identical fields."""
+    import torch
+    p = params3(nx=24, ny=16, nz=40)
+    t = torch.tensor(S.phi0((40, 16, 24), seed=6), dtype=torch.float32)
+    a = gpu.Sim(p, stream=torch.cuda.Stream()).init_fields(t).step(27).step(6)
+    assert a.launch_mode()["graphs"] in (0, 1)  # the first call measured both ways
+    b = gpu.Sim(p, stream=torch.cuda.Stream()).init_fields(t).set_timing(True).step(33)
+    fa, fb = gpu_fields(a), gpu_fields(b)
+    for k in ("phi", "u", "n", "T"):
+        assert np.array_equal(fa[k], fb[k]), k
+
+
 def test_full_size_3d_one_step(gpu):
     """The 256^3 workload in the launch configuration of the benchmark line, one step, every
     site compared with the oracle."""

@@ -214,6 +214,28 @@ def test_tile_height_invariance_bitwise(gpu):
             assert np.array_equal(out[0][k], o[k]), k
 
 
+def test_graph_replay_matches_direct_launches(gpu):
+    """On a caller stream lam_step measures graph replays of step pairs against direct launches
+    (its first call of at least 24 steps runs both) and keeps the faster; with timing on, or on
+    the legacy default stream, it launches every kernel directly.  The results must be
+    bit-identical, also for an odd number of steps and when stepping resumes from an odd step."""
+    import torch
+    p, phi0 = workload("c1_64sq", Tw=0.9, nx=100, ny=70)
+    t = torch.tensor(phi0, dtype=torch.float32)
+    a = gpu.Sim(p, stream=torch.cuda.Stream()).init_fields(t).step(57).step(44).step(2)
+    b = gpu.Sim(p, stream=torch.cuda.Stream()).init_fields(t).set_timing(True).step(103)
+    c = gpu.Sim(p).init_fields(t).step(103)
+    fa, fb, fc = gpu_fields(a), gpu_fields(b), gpu_fields(c)
+    for k in ("phi", "u", "n", "T"):
+        assert np.array_equal(fa[k], fb[k]), k
+        assert np.array_equal(fa[k], fc[k]), k
+    assert a.observables()["step"] == 103
+    m = a.launch_mode()
+    print("launch mode", m)
+    assert m["graphs"] in (0, 1) and m["direct_us"] > 0 and m["graph_us"] > 0
+    assert c.launch_mode()["graphs"] == -1
+
+
 def test_deterministic_repeat(gpu):
     p, phi0 = workload("c1_64sq", Tw=0.9)
     import torch
