@@ -147,11 +147,16 @@ int lam_structure_factor_static(const float* d_phi, int32_t nx, int32_t ny, void
                                 double* h_S, int32_t nbins, double* k_peak, double* S_peak,
                                 double* k_mean);
 
-/* Orientation of phi gradients (2D only): h_hist[nbins] holds the fraction of sum |grad phi|^2
- * whose gradient angle atan2(g_y, g_x) mod pi falls in each of nbins equal bins of [0, pi);
- * Q = sum(g_y^2 - g_x^2) / sum |grad phi|^2 (+1: lamellae parallel to the walls); h_Qrow[ny]
- * (nullable) is the same ratio per row.  Central differences, even reflection at walls.  Host
- * outputs; synchronises. */
+/* Orientation of phi gradients, the measure of lamellar order relative to the walls that the
+ * paper reads off its snapshots (Section 3, Figs 1-3); 1 <= nbins <= 36.
+ * 2D: h_hist[nbins] holds the fraction of sum |grad phi|^2 whose gradient angle
+ * atan2(g_y, g_x) mod pi falls in each of nbins equal bins of [0, pi);
+ * Q = sum(g_y^2 - g_x^2) / sum |grad phi|^2 (+1: lamellae parallel to the walls, -1
+ * perpendicular); h_Qrow[ny] (nullable) is the same ratio per row.
+ * 3D: the angle theta = arccos(|g_z| / |grad phi|) to the wall normal in nbins equal bins of
+ * [0, pi/2]; Q = sum(g_z^2 - (g_x^2 + g_y^2)/2) / sum |grad phi|^2 (+1: parallel to the walls,
+ * -1/2 perpendicular, 0 isotropic); h_Qrow[nz] per layer.
+ * Central differences, even reflection at walls.  Host outputs; synchronises. */
 int lam_orientation(lam_sim* s, double* h_hist, int32_t nbins, double* Q, double* h_Qrow);
 
 /* Fields of the current state into caller device buffers (any may be NULL): phi [N],

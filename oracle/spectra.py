@@ -86,7 +86,45 @@ def gradients(phi: np.ndarray, walls: bool):
     return gx, gy
 
 
+def gradients3(phi: np.ndarray, walls: bool):
+    """Central differences of a 3D field [z][y][x]: x and y periodic, z reflected evenly across
+    the wall planes (or periodic)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    gx = 0.5 * (np.roll(phi, -1, axis=2) - np.roll(phi, 1, axis=2))
+    gy = 0.5 * (np.roll(phi, -1, axis=1) - np.roll(phi, 1, axis=1))
+    if walls:
+        ext = np.concatenate([phi[:1], phi, phi[-1:]], axis=0)
+        gz = 0.5 * (ext[2:] - ext[:-2])
+    else:
+        gz = 0.5 * (np.roll(phi, -1, axis=0) - np.roll(phi, 1, axis=0))
+    return gx, gy, gz
+
+
+def orientation3(phi: np.ndarray, nbins: int, walls: bool = True) -> dict:
+    """Orientation of grad phi in 3D relative to the wall normal z: theta = arccos(|g_z| / |g|) in
+    [0, pi/2], histogram of nbins equal bins weighted by |g|^2 (fractions of the total);
+    Q = sum(g_z^2 - (g_x^2 + g_y^2)/2) / sum |g|^2, the weighted second Legendre polynomial of
+    cos theta: +1 for lamellae parallel to the walls, -1/2 perpendicular, 0 isotropic; Q per layer
+    along z."""
+    gx, gy, gz = gradients3(phi, walls)
+    w = gx * gx + gy * gy + gz * gz
+    num = gz * gz - 0.5 * (gx * gx + gy * gy)
+    c = np.where(w > 0, np.abs(gz) / np.sqrt(np.where(w > 0, w, 1.0)), 1.0)
+    theta = np.arccos(np.clip(c, 0.0, 1.0))
+    b = np.minimum((theta / (0.5 * math.pi / nbins)).astype(np.int64), nbins - 1)
+    hist = np.zeros(nbins)
+    np.add.at(hist, b.ravel(), w.ravel())
+    tot = w.sum()
+    Q = float(num.sum() / tot) if tot > 0 else 0.0
+    lw = w.sum(axis=(1, 2))
+    Qrow = np.where(lw > 0, num.sum(axis=(1, 2)) / np.where(lw > 0, lw, 1.0), 0.0)
+    return dict(hist=hist / tot if tot > 0 else hist, Q=Q, Q_row=Qrow, theta=theta, weight=w,
+                total_weight=float(tot))
+
+
 def orientation(phi: np.ndarray, nbins: int, walls: bool = True) -> dict:
+    if np.ndim(phi) == 3:
+        return orientation3(phi, nbins, walls)
     gx, gy = gradients(phi, walls)
     w = gx * gx + gy * gy
     theta = np.mod(np.arctan2(gy, gx), math.pi)

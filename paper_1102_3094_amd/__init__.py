@@ -273,7 +273,7 @@ class Sim:
     def orientation(self, nbins: int = 18) -> dict:
         h = (C.c_double * nbins)()
         q = C.c_double()
-        rows = (C.c_double * self.params["ny"])()
+        rows = (C.c_double * (self.params["ny"] if self.dim == 2 else self.params["nz"]))()
         self._chk(load().lam_orientation(self._h, h, nbins, C.byref(q), rows))
         return dict(hist=list(h), Q=q.value, Q_row=list(rows))
 

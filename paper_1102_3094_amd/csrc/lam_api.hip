@@ -59,6 +59,9 @@ hipError_t structure_factor_2d(const KParams& P, const float* phi, void* scratch
                                hipStream_t st);
 hipError_t orientation_2d(const KParams& P, const float* phi, void* scratch, int nbins,
                           double* h_hist, double* h_Q, double* h_Qrow, hipStream_t st);
+size_t orientation3_scratch_bytes(int ny, int nz);
+hipError_t orientation_3d(const KParams& P, const float* phi, void* scratch, int nbins,
+                          double* h_hist, double* h_Q, double* h_Qrow, hipStream_t st);
 size_t static_scratch_capacity();
 hipError_t static_scratch(int device, void** out);
 }  // namespace lam
@@ -131,7 +134,7 @@ Layout layout(const lam_params& p) {
   L.nblk = (int)((size_t)((p.nx + 63) / 64) * ((p.ny + 7) / 8) * (p.dim == 3 ? p.nz : 1) + 1);
   L.partials = take(sizeof(double) * R_N * L.nblk);
   L.result = take(sizeof(double) * R_N);
-  L.spec = take(p.dim == 2 ? spectra_scratch_bytes(p.nx, p.ny) : 256);
+  L.spec = take(p.dim == 2 ? spectra_scratch_bytes(p.nx, p.ny) : orientation3_scratch_bytes(p.ny, p.nz));
   L.total = off;
   return L;
 }
@@ -639,9 +642,11 @@ int lam_structure_factor_static(const float* d_phi, int32_t nx, int32_t ny, void
 }
 
 int lam_orientation(lam_sim* s, double* h_hist, int32_t nbins, double* Q, double* h_Qrow) {
-  if (!s || !h_hist || nbins < 1 || nbins > 360) return fail(s, LAM_EINVAL, "bad arguments");
-  if (s->p.dim != 2) return fail(s, LAM_EINVAL, "orientation is 2D only");
-  HIPCHK(s, orientation_2d(s->k, s->phi[s->step & 1], s->spec, nbins, h_hist, Q, h_Qrow, s->st));
+  if (!s || !h_hist || nbins < 1 || nbins > 36) return fail(s, LAM_EINVAL, "bad arguments (1 <= nbins <= 36)");
+  if (s->p.dim == 3)
+    HIPCHK(s, orientation_3d(s->k, s->phi[s->step & 1], s->spec, nbins, h_hist, Q, h_Qrow, s->st));
+  else
+    HIPCHK(s, orientation_2d(s->k, s->phi[s->step & 1], s->spec, nbins, h_hist, Q, h_Qrow, s->st));
   return LAM_OK;
 }
 

@@ -429,6 +429,113 @@ __global__ void orient_final_kernel(const double* __restrict__ rowpart,
   }
 }
 
+// 3D: angle of grad phi to the wall normal z, theta = arccos(|g_z| / |g|) in [0, pi/2], in nbins
+// equal bins weighted by |g|^2, and the weighted second Legendre polynomial
+// Q = sum(g_z^2 - (g_x^2 + g_y^2)/2) / sum |g|^2.  One workgroup per (y, z) line; the line
+// partials are summed per layer and then over layers, each in a fixed order.
+__global__ __launch_bounds__(OR_NT) void orient3_row_kernel(const float* __restrict__ phi, int nx,
+                                                            int ny, int nz, int walls, int nbins,
+                                                            double* __restrict__ rowpart) {
+  __shared__ double hist[OR_MAXBINS][OR_NT];
+  __shared__ double sa[OR_NT], sb[OR_NT];
+  const int row = blockIdx.x, t = threadIdx.x;
+  const int y = row % ny, z = row / ny;
+  for (int b = 0; b < nbins; ++b) hist[b][t] = 0.0;
+  bool f;
+  const int zm = wall_axis(z - 1, nz, walls, f), zp = wall_axis(z + 1, nz, walls, f);
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const size_t plane = (size_t)nx * ny;
+  const float* rc = phi + (size_t)z * plane + (size_t)y * nx;
+  const float* ryp = phi + (size_t)z * plane + (size_t)yp * nx;
+  const float* rym = phi + (size_t)z * plane + (size_t)ym * nx;
+  const float* rzp = phi + (size_t)zp * plane + (size_t)y * nx;
+  const float* rzm = phi + (size_t)zm * plane + (size_t)y * nx;
+  double sw = 0.0, sq = 0.0;
+  const float binw = 1.57079632679490f / nbins;
+  for (int x = t; x < nx; x += OR_NT) {
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const float gx = 0.5f * (rc[xp] - rc[xm]);
+    const float gy = 0.5f * (ryp[x] - rym[x]);
+    const float gz = 0.5f * (rzp[x] - rzm[x]);
+    const float w = gx * gx + gy * gy + gz * gz;
+    if (w > 0.f) {
+      const float th = acosf(fminf(fabsf(gz) / sqrtf(w), 1.f));
+      int b = (int)(th / binw);
+      b = b < 0 ? 0 : (b >= nbins ? nbins - 1 : b);
+      hist[b][t] += (double)w;
+    }
+    sw += (double)w;
+    sq += (double)(gz * gz) - 0.5 * ((double)(gx * gx) + (double)(gy * gy));
+  }
+  sa[t] = sw;
+  sb[t] = sq;
+  __syncthreads();
+  for (int o = OR_NT / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      sa[t] += sa[t + o];
+      sb[t] += sb[t + o];
+      for (int b = 0; b < nbins; ++b) hist[b][t] += hist[b][t + o];
+    }
+    __syncthreads();
+  }
+  double* out = rowpart + (size_t)row * (nbins + 2);
+  if (t == 0) {
+    out[0] = sa[0];
+    out[1] = sb[0];
+  }
+  if (t < nbins) out[2 + t] = hist[t][0];
+}
+
+// Per-layer sums of the line partials: block (column, layer) sums the ny lines of its layer.
+__global__ void layer_sum_kernel(const double* __restrict__ rowpart, int ny, int ld,
+                                 double* __restrict__ layerpart) {
+  __shared__ double sm[256];
+  const int col = blockIdx.x, z = blockIdx.y;
+  const double* M = rowpart + (size_t)z * ny * ld;
+  double v = 0.0;
+  for (int r = threadIdx.x; r < ny; r += 256) v += M[(size_t)r * ld + col];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) layerpart[(size_t)z * ld + col] = sm[0];
+}
+
+size_t orientation3_scratch_bytes(int ny, int nz) {
+  const size_t ld = OR_MAXBINS + 2;
+  return 8 * (ld * ((size_t)ny * nz + nz + 1) + 1 + OR_MAXBINS + nz) + 256;
+}
+
+hipError_t orientation_3d(const KParams& P, const float* phi, void* scratch, int nbins,
+                          double* h_hist, double* h_Q, double* h_Qrow, hipStream_t st) {
+  if (nbins > OR_MAXBINS) return hipErrorInvalidValue;
+  const int ld = nbins + 2;
+  double* rowpart = (double*)scratch;                      // [nz ny][nbins + 2]
+  double* layerpart = rowpart + (size_t)P.ny * P.nz * ld;  // [nz][nbins + 2]
+  double* tot = layerpart + (size_t)P.nz * ld;             // [nbins + 2]
+  double* res = tot + ld;                                  // Q, bins, Q per layer
+  hipLaunchKernelGGL(orient3_row_kernel, dim3(P.ny * P.nz), dim3(OR_NT), 0, st, phi, P.nx, P.ny,
+                     P.nz, P.walls, nbins, rowpart);
+  hipLaunchKernelGGL(layer_sum_kernel, dim3(ld, P.nz), dim3(256), 0, st, rowpart, P.ny, ld,
+                     layerpart);
+  hipLaunchKernelGGL(colsum_kernel, dim3(ld), dim3(256), 0, st, layerpart, P.nz, ld, tot);
+  hipLaunchKernelGGL(orient_final_kernel, dim3(1), dim3(256), 0, st, layerpart, tot, P.nz, nbins,
+                     res);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double Q;
+  e = hipMemcpyAsync(&Q, res, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h_hist, res + 1, sizeof(double) * nbins, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && h_Qrow)
+    e = hipMemcpyAsync(h_Qrow, res + 1 + nbins, sizeof(double) * P.nz, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && h_Q) *h_Q = Q;
+  return e;
+}
+
 hipError_t orientation_2d(const KParams& P, const float* phi, void* scratch, int nbins,
                           double* h_hist, double* h_Q, double* h_Qrow, hipStream_t st) {
   if (nbins > OR_MAXBINS) return hipErrorInvalidValue;

@@ -118,6 +118,36 @@ def test_graph_replay_matches_direct_launches_3d(gpu):
         assert np.array_equal(fa[k], fb[k]), k
 
 
+def test_orientation_3d_parity(gpu):
+    """The 3D orientation observable (angle of grad phi to the wall normal, Q = weighted second
+    Legendre polynomial, Q per layer) of a developed field against the oracle's definition, on
+    the same FP32 field.  A site whose angle lies within 1e-4 rad of a bin edge may land on either
+    side in FP32: its weight may move to the neighbour bin."""
+    import math
+    import torch
+    from oracle import spectra
+    p = S.model_params("paper_3d_nohydro", nx=24, ny=20, nz=48, xi=1.0)
+    g = gpu.Sim(p).init_fields(torch.tensor(S.phi0((48, 20, 24), seed=8, amplitude=0.01),
+                                            dtype=torch.float32))
+    g.step(600)
+    phi = gpu_fields(g)["phi"]
+    nb = 9
+    ref = spectra.orientation(phi, nb, walls=True)
+    got = g.orientation(nb)
+    assert ref["total_weight"] > 0 and abs(ref["Q"]) > 0.05
+    assert got["Q"] == pytest.approx(ref["Q"], abs=1e-5)
+    np.testing.assert_allclose(got["Q_row"], ref["Q_row"], atol=1e-5)
+    width = 0.5 * math.pi / nb
+    th, w = ref["theta"].ravel(), ref["weight"].ravel() / ref["total_weight"]
+    frac = th / width - np.floor(th / width)
+    amb = (frac < 1e-4 / width) | (frac > 1 - 1e-4 / width)
+    slack = np.zeros(nb)
+    b = np.minimum((th / width).astype(int), nb - 1)
+    for d in (-1, 0, 1):
+        np.add.at(slack, np.clip(b[amb] + d, 0, nb - 1), w[amb])
+    assert np.all(np.abs(np.array(got["hist"]) - ref["hist"]) <= slack + 1e-5)
+
+
 def test_full_size_3d_one_step(gpu):
     """The 256^3 workload in the launch configuration of the benchmark line, one step, every
     site compared with the oracle."""

@@ -181,3 +181,26 @@ def test_orientation_of_stripes():
     diag = spectra.orientation(np.cos(2 * np.pi * 4 * (x + y) / nx), 18, walls=False)
     assert diag["Q"] == pytest.approx(0.0, abs=1e-12)
     assert diag["hist"][4] == pytest.approx(1.0, abs=1e-12)
+
+
+def test_orientation_3d_stripes_and_isotropy():
+    """3D orientation: lamellae normal to z (parallel to the walls) give Q = +1 and all weight in
+    the first angle bin; lamellae normal to x or y give Q = -1/2 and all weight in the last bin;
+    a field whose gradients point along the three axes in equal measure gives Q = 0 (the second
+    Legendre polynomial averages to zero over directions)."""
+    nz, ny, nx = 24, 16, 20
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    par = np.cos(2 * np.pi * 3 * (z + 0.5) / (2 * nz))       # even across the wall planes
+    r = spectra.orientation(par, 9, walls=True)
+    assert r["Q"] == pytest.approx(1.0, abs=1e-12)
+    assert r["hist"][0] == pytest.approx(1.0, abs=1e-12)
+    np.testing.assert_allclose(r["Q_row"][r["weight"].sum(axis=(1, 2)) > 0], 1.0, atol=1e-12)
+    for perp in (np.sin(2 * np.pi * 2 * x / nx) + 0 * z, np.cos(2 * np.pi * 3 * y / ny) + 0 * z):
+        r = spectra.orientation(perp, 9, walls=True)
+        assert r["Q"] == pytest.approx(-0.5, abs=1e-12)
+        assert r["hist"][-1] == pytest.approx(1.0, abs=1e-12)
+    z, y, x = np.mgrid[0:16, 0:16, 0:16]
+    k = 2 * np.pi * 3 / 16
+    iso = np.sin(k * x) + np.sin(k * y + 0.3) + np.sin(k * z + 0.7)
+    r = spectra.orientation(iso, 9, walls=False)
+    assert abs(r["Q"]) < 1e-12
