@@ -17,6 +17,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "lam_dev.hpp"
 
 namespace lam {
@@ -57,12 +59,11 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P) {
 }
 
 // The pressure tensor of Section 2 without its ideal-gas term at one site (xx, yy, zz, xy, xz,
-// yz into dst[k][r][c]); explicit fused multiply-adds with contraction off, as in 2D.
-template <typename D>
+// yz into dst[k * stride]); explicit fused multiply-adds with contraction off, as in 2D.
 __device__ __forceinline__ void pressure_tensor_3d(const KParams& P, float a, float ph, float L,
                                                    float M, float px, float py, float pz,
-                                                   float Lx, float Ly, float Lz, D dst, int r,
-                                                   int c) {
+                                                   float Lx, float Ly, float Lz, float* dst,
+                                                   int stride) {
 #pragma clang fp contract(off)
   const float ph2 = ph * ph;
   const float gg = fmaf(px, px, fmaf(py, py, pz * pz));
@@ -72,27 +73,68 @@ __device__ __forceinline__ void pressure_tensor_3d(const KParams& P, float a, fl
   const float bulk = ph2 * fmaf(0.75f * P.b, ph2, 0.5f * a);
   const float p0 = fmaf(P.c, tc, fmaf(-P.kappa, tk, bulk));
   const float c2 = -2.f * P.c, k = P.kappa, mc = -P.c;
-  dst[0][r][c] = fmaf(k * px, px, fmaf(c2 * px, Lx, p0));
-  dst[1][r][c] = fmaf(k * py, py, fmaf(c2 * py, Ly, p0));
-  dst[2][r][c] = fmaf(k * pz, pz, fmaf(c2 * pz, Lz, p0));
-  dst[3][r][c] = fmaf(k * px, py, mc * fmaf(px, Ly, py * Lx));
-  dst[4][r][c] = fmaf(k * px, pz, mc * fmaf(px, Lz, pz * Lx));
-  dst[5][r][c] = fmaf(k * py, pz, mc * fmaf(py, Lz, pz * Ly));
+  dst[0] = fmaf(k * px, px, fmaf(c2 * px, Lx, p0));
+  dst[stride] = fmaf(k * py, py, fmaf(c2 * py, Ly, p0));
+  dst[2 * stride] = fmaf(k * pz, pz, fmaf(c2 * pz, Lz, p0));
+  dst[3 * stride] = fmaf(k * px, py, mc * fmaf(px, Ly, py * Lx));
+  dst[4 * stride] = fmaf(k * px, pz, mc * fmaf(px, Lz, pz * Lx));
+  dst[5 * stride] = fmaf(k * py, pz, mc * fmaf(py, Lz, pz * Ly));
 }
+
+// LDS row lengths and cell counts of the halo-3 (phi), halo-2 (L) and halo-1 (P) xy tiles.
+constexpr int W3 = BX + 6, W2 = BX + 4, W1 = BX + 2;
+constexpr int C3 = (BY + 6) * W3, C2 = (BY + 4) * W2, C1 = (BY + 2) * W1;
 
 struct Lb3dSmem {
   int rowoff[BY + 6], colx[BX + 6];  // y * nx and x of the halo-3 xy tile (periodic)
   float a[ZLB + 6];                  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
-  float phi[5][BY + 6][BX + 6];
+  float phi[5][C3];
   // L and P rings of 3: a slice's slot is rewritten only after the barrier that follows the last
   // phase reading it, so three slots suffice and the workgroup fits four to a compute unit
-  float L[3][BY + 4][BX + 4];
-  float P[3][6][BY + 2][BX + 2];  // xx, yy, zz, xy, xz, yz (or mu in [0] for -phi grad mu)
+  float L[3][C2];
+  float P[3][6][C1];  // xx, yy, zz, xy, xz, yz (or mu in [0] for -phi grad mu)
   double red[NT3 / 64][R_N];
 };
 
+// e_q . (vx, vy, vz) with the zero components of e_q left out (a product with 0.f would stay).
+template <int Q>
+__device__ __forceinline__ float edot19(float vx, float vy, float vz) {
+  float r = 0.f;
+  bool any = false;
+  const float v[3] = {vx, vy, vz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (E19[Q][k] == 0) continue;
+    const float t = E19[Q][k] > 0 ? v[k] : -v[k];
+    r = any ? r + t : t;
+    any = true;
+  }
+  return r;
+}
+
+// The next population plane, base + stride bytes.  The empty asm makes the address opaque, so
+// the compiler forms the 19 plane addresses by scalar adds where they are used instead of
+// keeping them all live in (and spilling them from) scalar registers.
+// The operand is a global-address-space pointer, so the accesses stay global (not flat) ones.
+template <typename T>
+__device__ __forceinline__ T* next_plane(T* p, size_t stride) {
+  typedef __attribute__((address_space(1))) char gchar;
+  gchar* r = (gchar*)((char*)p) + stride;
+  asm volatile("" : "+s"(r));
+  return (T*)r;
+}
+
+// Slot of the slice k - j in a ring of R slots, given m = k mod R (0 <= j < 2R).
+template <int R>
+__device__ __forceinline__ int ring_back(int m, int j) {
+  int v = m - j;
+  v += v < 0 ? R : 0;
+  v += v < 0 ? R : 0;
+  return v;
+}
+
 template <int MODE, typename ST>
-__global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restrict__ gin,
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4, 4))) void lb3d_kernel(KParams P, const ST* __restrict__ gin,
                                                    ST* __restrict__ gout,
                                                    const float* __restrict__ phi,
                                                    const float* __restrict__ Trow,
@@ -101,13 +143,12 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
                                                    double* __restrict__ partials) {
   __shared__ Lb3dSmem S;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const uint32_t plane = (uint32_t)nx * ny;
+  const size_t N = (size_t)plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
   const Tile3 T = tile3<ZLB>(P);
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x >= nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y >= ny - 1 ? 0 : y + 1;
 
   double acc[R_N];
 #pragma unroll
@@ -115,6 +156,8 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
   float g2[2][19];  // populations of the output slice, pulled one iteration ahead
 
   static_assert(NT3 >= (BY + 6) + (BX + 6) + ZLB + 6, "one pass fills the tables");
+  static_assert(C3 <= 2 * NT3 && C2 <= 2 * NT3 && C1 <= 2 * NT3 && C1 >= NT3 && C2 >= NT3,
+                "every thread owns one or two cells of each halo tile");
   if (tid < BY + 6) {
     S.rowoff[tid] = wrap(T.y0 - 3 + tid, ny) * nx;
   } else if (tid < (BY + 6) + (BX + 6)) {
@@ -124,127 +167,155 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
     bool f;
     S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
   }
+  // Per-thread offsets, the same for every slice: the in-plane source of a pull along (ex, ey)
+  // ((y - ey) * nx + x - ex, periodic; xys[ey + 1][ex + 1]), the lattice cell of each of the
+  // thread's halo-3 cells, and for its cells of the L and P stages the flat LDS index of the
+  // centre in the halo-3 (phi) and halo-2 (L) tiles.
+  uint32_t xys[3][3];
+  {
+    const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+    const int sx[3] = {xc == nx - 1 ? 0 : xc + 1, xc, xc == 0 ? nx - 1 : xc - 1};
+    const int sy[3] = {yc == ny - 1 ? 0 : yc + 1, yc, yc == 0 ? ny - 1 : yc - 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) xys[a][b] = (uint32_t)(sy[a] * nx + sx[b]);
+  }
+  int lph[2], pph[2], pL[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int i2 = min(tid + j * NT3, C2 - 1), r2 = i2 / W2;
+    lph[j] = i2 + 2 * r2 + W3 + 1;  // (r + 1) * W3 + c + 1
+    const int i1 = min(tid + j * NT3, C1 - 1), r1 = i1 / W1;
+    pph[j] = i1 + 4 * r1 + 2 * W3 + 2;  // (r + 2) * W3 + c + 2
+    pL[j] = i1 + 2 * r1 + W2 + 1;       // (r + 1) * W2 + c + 1
+  }
   __syncthreads();
+  constexpr int IPH = (C3 + NT3 - 1) / NT3;
+  uint32_t hxy[IPH];
+#pragma unroll
+  for (int j = 0; j < IPH; ++j) {
+    const int i = min(tid + j * NT3, C3 - 1);
+    const int r = i / W3, c = i - r * W3;
+    hxy[j] = (uint32_t)(S.rowoff[r] + S.colx[c]);
+  }
   // phi slices are loaded into registers two iterations before they are stored to LDS (two
   // register buffers by iteration parity).  The memory counter drains in issue order: the pulls
   // of an iteration are issued before its phi prefetch, so the collision waits for the pulls
   // only, and the phi store of the next iteration only for the prefetch issued two iterations
   // back.  The phi loads are unconditional (clamped index) and a comes from LDS so that no
   // branch or late load forces an earlier wait.
-  constexpr int CPH = (BY + 6) * (BX + 6), IPH = (CPH + NT3 - 1) / NT3;
   float pv[2][IPH];
   auto load_phi = [&](int sl, float(&pb)[IPH]) {
     bool f;
-    const size_t zoff = (size_t)wall_axis(sl, nz, P.walls, f) * plane;
+    const uint32_t zoff = (uint32_t)wall_axis(sl, nz, P.walls, f) * plane;
 #pragma unroll
-    for (int j = 0; j < IPH; ++j) {
-      const int i = min(tid + j * NT3, CPH - 1);
-      const int r = i / (BX + 6), c = i - r * (BX + 6);
-      pb[j] = phi[zoff + S.rowoff[r] + S.colx[c]];
-    }
+    for (int j = 0; j < IPH; ++j) pb[j] = *plane_at(phi, zoff + hxy[j]);
   };
   const int K = T.z1 - T.z0 + 6;
   load_phi(T.z0 - 3, pv[0]);
   load_phi(T.z0 - 2, pv[1]);
 
-  auto iteration = [&](const int k, float(&pb)[IPH], float(&g)[19], float(&gn)[19]) {
-    const int s_load = T.z0 - 3 + k, s_L = s_load - 1, s_P = s_load - 2, s_out = s_load - 3;
-    {  // phi slice s_load (loaded two iterations ago) into its ring slot
-      float(*dst)[BX + 6] = S.phi[((s_load % 5) + 5) % 5];
+  // Iteration k loads slice z0 - 3 + k and works on the slices behind it: L of k - 1, P of
+  // k - 2, the output slice k - 3.  A slice's ring slot is its index relative to z0 - 3 modulo
+  // the ring length; m5 = k mod 5 and m3 = k mod 3 are carried by the loop.
+  auto iteration = [&](const int k, const int m5, const int m3, float(&pb)[IPH], float(&g)[19],
+                       float(&gn)[19]) {
+    const int s_out = T.z0 - 3 + k - 3;
+    {  // phi slice k (loaded two iterations ago) into its ring slot
+      float* dst = S.phi[m5];
 #pragma unroll
       for (int j = 0; j < IPH; ++j) {
         const int i = tid + j * NT3;
-        if (i < CPH) {
-          const int r = i / (BX + 6), c = i - r * (BX + 6);
-          dst[r][c] = pb[j];
-        }
+        if (i < C3) dst[i] = pb[j];
       }
     }
-    const bool do_out = s_out >= T.z0 && in_xy;
+    const bool do_out = k >= 6 && in_xy;
     // pulls of the next iteration's output slice, issued before this iteration's phi prefetch
-    // so that they have a whole iteration to arrive: f_q(x) = f*_q(x - e_q), bounce-back across
-    // a wall
-    if (s_out + 1 >= T.z0 && s_out + 1 < T.z1 && in_xy) {
-      const int z = s_out + 1;
+    // so that they have a whole iteration to arrive: f_q(x) = f*_q(x - e_q), halfway bounce-back
+    // across a wall (the opposite population of the site itself)
+    const int zn = s_out + 1;
+    if (zn >= T.z0 && zn < T.z1 && in_xy) {
+      const bool bot = P.walls && zn == 0, top = P.walls && zn == nz - 1;
+      const uint32_t zc = (uint32_t)zn * plane;
+      const uint32_t zlo = (uint32_t)(zn == 0 ? nz - 1 : zn - 1) * plane;  // source of ez = +1
+      const uint32_t zhi = (uint32_t)(zn == nz - 1 ? 0 : zn + 1) * plane;  // source of ez = -1
+      const size_t Nb = N * sizeof(ST);
+      const ST* gq = gin;
 #pragma unroll
       for (int q = 0; q < 19; ++q) {
         const int ex = E19[q][0], ey = E19[q][1], ez = E19[q][2];
-        const int sz = z - ez;
-        uint32_t idx;
-        int qq = q;
-        if (P.walls && (sz < 0 || sz >= nz)) {  // uniform: z is the workgroup's slice
-          qq = opp19(q);
-          idx = (uint32_t)((z * ny + y) * nx + x);
-        } else {
-          const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
-          const int sy = ey == 1 ? ym : (ey == -1 ? yp : y);
-          const int zz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
-          idx = (uint32_t)((zz * ny + sy) * nx + sx);
+        const ST* src = gq;
+        uint32_t idx = xys[ey + 1][ex + 1] + (ez == 0 ? zc : (ez > 0 ? zlo : zhi));
+        if (ez != 0 && (ez > 0 ? bot : top)) {
+          src = (q % 2) ? plane_at(gq, (uint32_t)N) : plane_at(gq, (uint32_t)0) - N;
+          idx = xys[1][1] + zc;
         }
-        gn[q] = to_f32(*plane_at(gin + (size_t)qq * N, idx));
+        gn[q] = to_f32(*plane_at(src, idx));
+        if (q < 18) gq = next_plane(gq, Nb);
       }
     }
-    load_phi(s_load + 2, pb);
+    load_phi(T.z0 - 3 + k + 2, pb);
     __syncthreads();
-    if (s_L >= T.z0 - 2) {  // L slice s_L with xy halo 2
-      float(*pc)[BX + 6] = S.phi[((s_L % 5) + 5) % 5];
-      float(*pd)[BX + 6] = S.phi[(((s_L - 1) % 5) + 5) % 5];
-      float(*pu)[BX + 6] = S.phi[(((s_L + 1) % 5) + 5) % 5];
-      float(*dst)[BX + 4] = S.L[((s_L % 3) + 3) % 3];
-      for (int i = tid; i < (BY + 4) * (BX + 4); i += NT3) {
-        int r = i / (BX + 4), c = i - r * (BX + 4);
-        const int R = r + 1, C = c + 1;
-        dst[r][c] = ((pc[R][C + 1] + pc[R][C - 1]) + (pc[R + 1][C] + pc[R - 1][C])) +
-                    (pu[R][C] + pd[R][C]) - 6.f * pc[R][C];
-      }
+    if (k >= 2) {  // L slice k - 1 with xy halo 2
+      const float* pc = S.phi[ring_back<5>(m5, 1)];
+      const float* pd = S.phi[ring_back<5>(m5, 2)];
+      const float* pu = S.phi[m5];
+      float* dst = S.L[ring_back<3>(m3, 1)];
+      auto lap = [&](int o) {
+        return ((pc[o + 1] + pc[o - 1]) + (pc[o + W3] + pc[o - W3])) + (pu[o] + pd[o]) -
+               6.f * pc[o];
+      };
+      dst[tid] = lap(lph[0]);
+      if (tid < C2 - NT3) dst[tid + NT3] = lap(lph[1]);
     }
     __syncthreads();
-    if (P.hydro && s_P >= T.z0 - 1) {  // pressure tensor (or mu) of slice s_P with xy halo 1
-      const float a = S.a[s_P - (T.z0 - 3)];
-      float(*pc)[BX + 6] = S.phi[((s_P % 5) + 5) % 5];
-      float(*pd)[BX + 6] = S.phi[(((s_P - 1) % 5) + 5) % 5];
-      float(*pu)[BX + 6] = S.phi[(((s_P + 1) % 5) + 5) % 5];
-      float(*lc)[BX + 4] = S.L[((s_P % 3) + 3) % 3];
-      float(*ld)[BX + 4] = S.L[(((s_P - 1) % 3) + 3) % 3];
-      float(*lu)[BX + 4] = S.L[(((s_P + 1) % 3) + 3) % 3];
-      float(*dst)[BY + 2][BX + 2] = S.P[((s_P % 3) + 3) % 3];
-      for (int i = tid; i < (BY + 2) * (BX + 2); i += NT3) {
-        int r = i / (BX + 2), c = i - r * (BX + 2);
-        const int R = r + 2, C = c + 2, r1 = r + 1, c1 = c + 1;
-        const float ph = pc[R][C], L = lc[r1][c1];
-        const float M = ((lc[r1][c1 + 1] + lc[r1][c1 - 1]) + (lc[r1 + 1][c1] + lc[r1 - 1][c1])) +
-                        (lu[r1][c1] + ld[r1][c1]) - 6.f * L;
+    if (P.hydro && k >= 4) {  // pressure tensor (or mu) of slice k - 2 with xy halo 1
+      const float a = S.a[k - 2];
+      const float* pc = S.phi[ring_back<5>(m5, 2)];
+      const float* pd = S.phi[ring_back<5>(m5, 3)];
+      const float* pu = S.phi[ring_back<5>(m5, 1)];
+      const float* lc = S.L[ring_back<3>(m3, 2)];
+      const float* ld = S.L[ring_back<3>(m3, 3)];
+      const float* lu = S.L[ring_back<3>(m3, 1)];
+      float* dst = &S.P[ring_back<3>(m3, 2)][0][0];
+      auto item = [&](int i, int op, int ol) {
+        const float ph = pc[op], L = lc[ol];
+        const float M = ((lc[ol + 1] + lc[ol - 1]) + (lc[ol + W2] + lc[ol - W2])) +
+                        (lu[ol] + ld[ol]) - 6.f * L;
         if (P.force_form == 1) {
-          dst[0][r][c] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
+          dst[i] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
         } else {
           auto fp = [&](int dz, int dr, int dc) {
-            return (dz == 0 ? pc : (dz > 0 ? pu : pd))[R + dr][C + dc];
+            return (dz == 0 ? pc : (dz > 0 ? pu : pd))[op + dr * W3 + dc];
           };
           auto fl = [&](int dz, int dr, int dc) {
-            return (dz == 0 ? lc : (dz > 0 ? lu : ld))[r1 + dr][c1 + dc];
+            return (dz == 0 ? lc : (dz > 0 ? lu : ld))[ol + dr * W2 + dc];
           };
           const float px = iso3_x(fp), py = iso3_y(fp), pz = iso3_z(fp);
           const float Lx = iso3_x(fl), Ly = iso3_y(fl), Lz = iso3_z(fl);
-          pressure_tensor_3d(P, a, ph, L, M, px, py, pz, Lx, Ly, Lz, dst, r, c);
+          pressure_tensor_3d(P, a, ph, L, M, px, py, pz, Lx, Ly, Lz, dst + i, C1);
         }
-      }
+      };
+      item(tid, pph[0], pL[0]);
+      if (tid < C1 - NT3) item(tid + NT3, pph[1], pL[1]);
     }
     __syncthreads();
     if (do_out) {
-      const int z = s_out, r = ty + 1, c = tx + 1;
-      float(*Pc)[BY + 2][BX + 2] = S.P[((z % 3) + 3) % 3];
-      float(*Pd)[BY + 2][BX + 2] = S.P[(((z - 1) % 3) + 3) % 3];
-      float(*Pu)[BY + 2][BX + 2] = S.P[(((z + 1) % 3) + 3) % 3];
-      float(*pc)[BX + 6] = S.phi[((z % 5) + 5) % 5];
+      const int z = s_out, o = (ty + 1) * W1 + tx + 1, oc = (ty + 3) * W3 + tx + 3;
+      const float* Pc = &S.P[ring_back<3>(m3, 3)][0][0];
+      const float* Pd = &S.P[ring_back<3>(m3, 4)][0][0];
+      const float* Pu = &S.P[ring_back<3>(m3, 2)][0][0];
+      const float* pc = S.phi[ring_back<5>(m5, 3)];
       float Fx = 0.f, Fy = 0.f, Fz = 0.f;
       if (P.hydro) {  // isotropic first differences of P (or of mu)
-        auto fP = [&](int k) {
-          return [&, k](int dz, int dr, int dc) {
-            return (dz == 0 ? Pc : (dz > 0 ? Pu : Pd))[k][r + dr][c + dc];
+        auto fP = [&](int kk) {
+          return [&, kk](int dz, int dr, int dc) {
+            return (dz == 0 ? Pc : (dz > 0 ? Pu : Pd))[kk * C1 + o + dr * W1 + dc];
           };
         };
         if (P.force_form == 1) {
-          const float ph = pc[ty + 3][tx + 3];
+          const float ph = pc[oc];
           Fx = -ph * iso3_x(fP(0));
           Fy = -ph * iso3_y(fP(0));
           Fz = -ph * iso3_z(fP(0));
@@ -254,13 +325,22 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
           Fz = -(iso3_x(fP(4)) + iso3_y(fP(5)) + iso3_z(fP(2)));
         }
       }
-      float dn = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+      // moments over the pairs of opposite velocities (q odd and its opposite q + 1):
+      // even parts sum to the density, odd parts to the momentum
+      float ev[10], od[10];
 #pragma unroll
-      for (int q = 0; q < 19; ++q) {
-        dn += g[q];
-        if (E19[q][0]) jx += E19[q][0] > 0 ? g[q] : -g[q];
-        if (E19[q][1]) jy += E19[q][1] > 0 ? g[q] : -g[q];
-        if (E19[q][2]) jz += E19[q][2] > 0 ? g[q] : -g[q];
+      for (int j = 1; j < 10; ++j) {
+        ev[j] = g[2 * j - 1] + g[2 * j];
+        od[j] = g[2 * j - 1] - g[2 * j];
+      }
+      float dn = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+      for (int j = 1; j < 10; ++j) {
+        const int q = 2 * j - 1;
+        dn += ev[j];
+        if (E19[q][0]) jx += E19[q][0] > 0 ? od[j] : -od[j];
+        if (E19[q][1]) jy += E19[q][1] > 0 ? od[j] : -od[j];
+        if (E19[q][2]) jz += E19[q][2] > 0 ? od[j] : -od[j];
       }
       const float n = 1.f + dn;
       Fx += n * P.gx;
@@ -273,20 +353,39 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
         uy = (jy + 0.5f * Fy) * inv;
         uz = (jz + 0.5f * Fz) * inv;
       }
-      const uint32_t s = (uint32_t)((z * ny + y) * nx + x);
+      const uint32_t s = (uint32_t)z * plane + (uint32_t)(y * nx + x);
       if (MODE == MODE3_STEP) {
+        // BGK with the forcing term, g' = (1 - omega) g + omega geq + frc, per pair of opposite
+        // velocities: with e.u and e.F odd under e -> -e, geq and frc split into a part shared by
+        // the pair, w [omega (dn - n 1.5 u.u + 4.5 n (e.u)^2) + kf (9 (e.u)(e.F) - 3 u.F)], and
+        // an odd part, 3 w (omega n e.u + kf e.F).
+        const float om = P.omega, kf = P.kforce, om1 = 1.f - om;
         const float usq = 1.5f * (ux * ux + uy * uy + uz * uz);
         const float uF = ux * Fx + uy * Fy + uz * Fz;
-        const float om = P.omega, kf = P.kforce;
-#pragma unroll
-        for (int q = 0; q < 19; ++q) {
+        const float e0 = dn - n * usq;
+        const size_t Nb = N * sizeof(ST);
+        ST* go = gout;
+        *plane_at(go, s) = from_f32<ST>(om1 * g[0] + w19(0) * (om * e0 - 3.f * kf * uF));
+        auto pair = [&](auto qc) {
+          constexpr int q = decltype(qc)::value;
           const float w = w19(q);
-          const float eu = E19[q][0] * ux + E19[q][1] * uy + E19[q][2] * uz;
-          const float eF = E19[q][0] * Fx + E19[q][1] * Fy + E19[q][2] * Fz;
-          const float geq = w * (dn + n * (eu * (3.f + 4.5f * eu) - usq));
-          const float frc = kf * w * (3.f * (eF - uF) + 9.f * eu * eF);
-          *plane_at(gout + (size_t)q * N, s) = from_f32<ST>(g[q] + om * (geq - g[q]) + frc);
-        }
+          const float eu = edot19<q>(ux, uy, uz), eF = edot19<q>(Fx, Fy, Fz);
+          const float even = w * (om * (e0 + 4.5f * n * eu * eu) + kf * (9.f * eu * eF - 3.f * uF));
+          const float odd = 3.f * w * (om * n * eu + kf * eF);
+          go = next_plane(go, Nb);
+          *plane_at(go, s) = from_f32<ST>(om1 * g[q] + (even + odd));
+          go = next_plane(go, Nb);
+          *plane_at(go, s) = from_f32<ST>(om1 * g[q + 1] + (even - odd));
+        };
+        pair(std::integral_constant<int, 1>{});
+        pair(std::integral_constant<int, 3>{});
+        pair(std::integral_constant<int, 5>{});
+        pair(std::integral_constant<int, 7>{});
+        pair(std::integral_constant<int, 9>{});
+        pair(std::integral_constant<int, 11>{});
+        pair(std::integral_constant<int, 13>{});
+        pair(std::integral_constant<int, 15>{});
+        pair(std::integral_constant<int, 17>{});
         *plane_at(uout, s) = ux;
         *plane_at(uout + N, s) = uy;
         *plane_at(uout + 2 * N, s) = uz;
@@ -296,12 +395,11 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
         *plane_at(uout + 2 * N, s) = uz;
         if (nout) *plane_at(nout, s) = n;
       } else {
-        const float a = S.a[z - (T.z0 - 3)];
-        float(*pu)[BX + 6] = S.phi[(((z + 1) % 5) + 5) % 5];
-        const float ph = pc[ty + 3][tx + 3];
-        const float L = S.L[((z % 3) + 3) % 3][ty + 2][tx + 2];
-        const float dx = pc[ty + 3][tx + 4] - ph, dy = pc[ty + 4][tx + 3] - ph,
-                    dz = pu[ty + 3][tx + 3] - ph;
+        const float a = S.a[k - 3];
+        const float* pu = S.phi[ring_back<5>(m5, 2)];
+        const float ph = pc[oc];
+        const float L = S.L[ring_back<3>(m3, 3)][(ty + 2) * W2 + tx + 2];
+        const float dx = pc[oc + 1] - ph, dy = pc[oc + W3] - ph, dz = pu[oc] - ph;
         const float fe = 0.5f * a * ph * ph + 0.25f * P.b * ph * ph * ph * ph +
                          0.5f * P.kappa * (dx * dx + dy * dy + dz * dz) + 0.5f * P.c * L * L;
         acc[R_MASS] += (double)dn;
@@ -316,9 +414,14 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
       }
     }
   };
+  int m5 = 0, m3 = 0;
   for (int k = 0; k < K; k += 2) {
-    iteration(k, pv[0], g2[0], g2[1]);
-    if (k + 1 < K) iteration(k + 1, pv[1], g2[1], g2[0]);
+    iteration(k, m5, m3, pv[0], g2[0], g2[1]);
+    m5 = m5 == 4 ? 0 : m5 + 1;
+    m3 = m3 == 2 ? 0 : m3 + 1;
+    if (k + 1 < K) iteration(k + 1, m5, m3, pv[1], g2[1], g2[0]);
+    m5 = m5 == 4 ? 0 : m5 + 1;
+    m3 = m3 == 2 ? 0 : m3 + 1;
   }
 
   if (MODE == MODE3_OBS) {
@@ -345,14 +448,34 @@ __global__ __launch_bounds__(NT3) void lb3d_kernel(KParams P, const ST* __restri
 // barrier and read for outputs s - 3, s - 2 (slices s - 4 .. s - 1): rings of 4.  psi is the same
 // for the whole launch (one Euler sub-step), so the ring holds the fluxes psi u (formed once per
 // cell when the velocity is staged) rather than u: the advection reads 30 instead of 60 values.
+// Ring slots are the slice index relative to z0 - 3 masked to the ring length.
+// The rings read most per output (fluxes, mu) come first, so that their reads fit the 16-bit
+// immediate offset of the LDS instructions.
 template <bool HYDRO>
 struct Phi3dSmem {
-  int rowoff[BY + 6], colx[BX + 6];
+  float u[HYDRO ? 4 : 1][3][C1];  // fluxes psi u_x, psi u_y, psi u_z
+  float mu[4][C1];
+  float psi[8][C3];
   float a[ZPH + 6];  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
-  float psi[8][BY + 6][BX + 6];
-  float mu[4][BY + 2][BX + 2];
-  float u[HYDRO ? 4 : 1][3][BY + 2][BX + 2];  // fluxes psi u_x, psi u_y, psi u_z
+  int rowoff[BY + 6], colx[BX + 6];
 };
+
+// mu = a psi + b psi^3 - kappa lap psi + c lap lap psi at the halo-3 tile cell o of slice c0, with
+// slices m2, m1 below and p1, p2 above (the 25-point biharmonic is the 7-point Laplacian applied
+// twice).
+__device__ __forceinline__ float mu_at(const KParams& P, float a, const float* m2,
+                                       const float* m1, const float* c0, const float* p1,
+                                       const float* p2, int o) {
+  const float v = c0[o];
+  const float face = ((c0[o + 1] + c0[o - 1]) + (c0[o + W3] + c0[o - W3])) + (p1[o] + m1[o]);
+  const float edge = ((c0[o + W3 + 1] + c0[o + W3 - 1]) + (c0[o - W3 + 1] + c0[o - W3 - 1])) +
+                     ((p1[o + 1] + p1[o - 1]) + (m1[o + 1] + m1[o - 1])) +
+                     ((p1[o + W3] + p1[o - W3]) + (m1[o + W3] + m1[o - W3]));
+  const float far = ((c0[o + 2] + c0[o - 2]) + (c0[o + 2 * W3] + c0[o - 2 * W3])) + (p2[o] + m2[o]);
+  const float L = face - 6.f * v;
+  const float M = 42.f * v - 12.f * face + 2.f * edge + far;
+  return a * v + P.b * v * v * v - P.kappa * L + P.c * M;
+}
 
 template <bool HYDRO>
 __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __restrict__ psi_in,
@@ -363,7 +486,8 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
                                                     float* __restrict__ Tscr, int do_T) {
   __shared__ Phi3dSmem<HYDRO> S;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const uint32_t plane = (uint32_t)nx * ny;
+  const size_t N = (size_t)plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
   const Tile3 T = tile3<ZPH>(P);
   const int x = T.x0 + tx, y = T.y0 + ty;
@@ -379,38 +503,60 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
     bool f;
     S.a[i] = (Trow[wall_axis(T.z0 - 3 + i, nz, P.walls, f)] - P.Tc) / P.Tc;
   }
+  // Cells of the halo-1 tile (mu and the fluxes): every thread owns the interior cell above its
+  // own site, threads below NH one cell of the ring around it (rows 0 and BY + 1, then columns 0
+  // and BX + 1 of rows 1 .. BY).  o* index the halo-1 tile, p* the halo-3 tile.
+  constexpr int NH = 2 * W1 + 2 * BY;
+  static_assert(NH <= NT3 && C1 == NT3 + NH && C3 <= 2 * NT3, "cell ownership");
+  const bool has_h = tid < NH;
+  int hr, hc;
+  if (tid < W1) {
+    hr = 0;
+    hc = tid;
+  } else if (tid < 2 * W1) {
+    hr = BY + 1;
+    hc = tid - W1;
+  } else {
+    const int t = min(tid - 2 * W1, 2 * BY - 1);
+    hr = 1 + t / 2;
+    hc = (t % 2) ? BX + 1 : 0;
+  }
+  const int oi = (ty + 1) * W1 + tx + 1, pi = (ty + 3) * W3 + tx + 3;
+  const int oh = hr * W1 + hc, ph = (hr + 2) * W3 + hc + 2;
   __syncthreads();
+  // in-plane lattice offsets of the thread's halo-3 cells (psi) and of its two halo-1 cells (u)
+  uint32_t gp[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int i = min(tid + j * NT3, C3 - 1);
+    const int r = i / W3, c = i - r * W3;
+    gp[j] = (uint32_t)(S.rowoff[r] + S.colx[c]);
+  }
+  const uint32_t gu[2] = {(uint32_t)(S.rowoff[ty + 3] + S.colx[tx + 3]),
+                          (uint32_t)(S.rowoff[hr + 2] + S.colx[hc + 2])};
+
   // psi slice s and u slice s - 2 are loaded into registers one iteration (two slices) before
   // their LDS store (one register buffer per slice of the pair): the memory counter of a wave
   // drains in issue order, so the store of the first slice waits only for its own loads while
-  // those of the second stay in flight.  Every load is unconditional (clamped index, a u slice is
+  // those of the second stay in flight.  Every load is unconditional (clamped cell, a u slice is
   // fetched and stored even where it goes unused, the last iteration prefetches slices it does
   // not need) so that no branch forces an early wait; the per-slice a comes from LDS for the same
   // reason.
-  constexpr int CPS = (BY + 6) * (BX + 6), IPS = (CPS + NT3 - 1) / NT3;
-  constexpr int CUS = (BY + 2) * (BX + 2), IUS = (CUS + NT3 - 1) / NT3;
-  float pv[2][IPS], uv[2][3][IUS];
-  auto load = [&](int sl, float(&pb)[IPS], float(&ub)[3][IUS]) {
+  float pv[2][2], uv[2][2][3];
+  auto load = [&](int sl, float(&pb)[2], float(&ub)[2][3]) {
     bool f;
-    const size_t zoff = (size_t)wall_axis(sl, nz, P.walls, f) * plane;
-#pragma unroll
-    for (int j = 0; j < IPS; ++j) {
-      const int i = min(tid + j * NT3, CPS - 1);
-      const int r = i / (BX + 6), c = i - r * (BX + 6);
-      pb[j] = psi_in[zoff + S.rowoff[r] + S.colx[c]];
-    }
+    const uint32_t zoff = (uint32_t)wall_axis(sl, nz, P.walls, f) * plane;
+    pb[0] = *plane_at(psi_in, zoff + gp[0]);
+    pb[1] = *plane_at(psi_in, zoff + gp[1]);
     if (HYDRO) {
       bool fl;
-      const size_t uoff = (size_t)wall_axis(sl - 2, nz, P.walls, fl) * plane;
+      const uint32_t uoff = (uint32_t)wall_axis(sl - 2, nz, P.walls, fl) * plane;
       const float sg = fl ? -1.f : 1.f;
 #pragma unroll
-      for (int j = 0; j < IUS; ++j) {
-        const int i = min(tid + j * NT3, CUS - 1);
-        const int r = i / (BX + 2), c = i - r * (BX + 2);
-        const size_t s = uoff + S.rowoff[r + 2] + S.colx[c + 2];
-        ub[0][j] = u[s];
-        ub[1][j] = u[N + s];
-        ub[2][j] = sg * u[2 * N + s];
+      for (int j = 0; j < 2; ++j) {
+        ub[j][0] = *plane_at(u, uoff + gu[j]);
+        ub[j][1] = *plane_at(u + N, uoff + gu[j]);
+        ub[j][2] = sg * *plane_at(u + 2 * N, uoff + gu[j]);
       }
     }
   };
@@ -418,97 +564,86 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
   load(T.z0 - 3, pv[0], uv[0]);
   load(T.z0 - 2, pv[1], uv[1]);
 
-  // Two slices per iteration (one barrier per slice): store psi slices s, s + 1 and u slices
-  // s - 2, s - 1, compute mu of slices s - 2, s - 1, write the output slices s - 3, s - 2.
+  // Iteration k (even): store psi slices k, k + 1 (relative to z0 - 3) and the fluxes of slices
+  // k - 2, k - 1, compute mu of slices k - 2, k - 1, write the output slices k - 3, k - 2.
   auto pair = [&](const int k) {
-    const int s0 = T.z0 - 3 + k;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {  // psi slices s0, s0 + 1 (xy halo 3)
-      float(*dst)[BX + 6] = S.psi[(((s0 + h) % 8) + 8) % 8];
-#pragma unroll
-      for (int j = 0; j < IPS; ++j) {
-        const int i = tid + j * NT3;
-        if (i < CPS) {
-          const int r = i / (BX + 6), c = i - r * (BX + 6);
-          dst[r][c] = pv[h][j];
-        }
-      }
-    }
-    __syncthreads();
-    if (HYDRO) {  // fluxes psi u of slices s0 - 2, s0 - 1 (xy halo 1; normal component odd)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        float(*jd)[BY + 2][BX + 2] = S.u[(((s0 - 2 + h) % 4) + 4) % 4];
-        float(*pp)[BX + 6] = S.psi[(((s0 - 2 + h) % 8) + 8) % 8];
-#pragma unroll
-        for (int j = 0; j < IUS; ++j) {
-          const int i = tid + j * NT3;
-          if (i < CUS) {
-            const int r = i / (BX + 2), c = i - r * (BX + 2);
-            const float ps = pp[r + 2][c + 2];
-            jd[0][r][c] = ps * uv[h][0][j];
-            jd[1][r][c] = ps * uv[h][1][j];
-            jd[2][r][c] = ps * uv[h][2][j];
-          }
-        }
-      }
-    }
-    load(s0 + 2, pv[0], uv[0]);
-    load(s0 + 3, pv[1], uv[1]);
-    // mu of slices s0 - 2 and s0 - 1 with xy halo 1 (25-point biharmonic)
-    for (int i = tid; i < 2 * CUS; i += NT3) {
-      const int h = i >= CUS, q = i - h * CUS;
-      const int s_mu = s0 - 2 + h;
-      if (s_mu < T.z0 - 1 || s_mu > T.z1) continue;
-      const float a = S.a[s_mu - (T.z0 - 3)];
-      float(*c0)[BX + 6] = S.psi[((s_mu % 8) + 8) % 8];
-      float(*m1)[BX + 6] = S.psi[(((s_mu - 1) % 8) + 8) % 8];
-      float(*p1)[BX + 6] = S.psi[(((s_mu + 1) % 8) + 8) % 8];
-      float(*m2)[BX + 6] = S.psi[(((s_mu - 2) % 8) + 8) % 8];
-      float(*p2)[BX + 6] = S.psi[(((s_mu + 2) % 8) + 8) % 8];
-      float(*dst)[BX + 2] = S.mu[((s_mu % 4) + 4) % 4];
-      const int r = q / (BX + 2), cc = q - r * (BX + 2);
-      const int R = r + 2, C = cc + 2;
-      const float v = c0[R][C];
-      const float face = ((c0[R][C + 1] + c0[R][C - 1]) + (c0[R + 1][C] + c0[R - 1][C])) +
-                         (p1[R][C] + m1[R][C]);
-      const float edge = ((c0[R + 1][C + 1] + c0[R + 1][C - 1]) + (c0[R - 1][C + 1] + c0[R - 1][C - 1])) +
-                         ((p1[R][C + 1] + p1[R][C - 1]) + (m1[R][C + 1] + m1[R][C - 1])) +
-                         ((p1[R + 1][C] + p1[R - 1][C]) + (m1[R + 1][C] + m1[R - 1][C]));
-      const float far = ((c0[R][C + 2] + c0[R][C - 2]) + (c0[R + 2][C] + c0[R - 2][C])) +
-                        (p2[R][C] + m2[R][C]);
-      const float L = face - 6.f * v;
-      const float M = 42.f * v - 12.f * face + 2.f * edge + far;
-      dst[r][cc] = a * v + P.b * v * v * v - P.kappa * L + P.c * M;
-    }
-    __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int z = s0 - 3 + h;
+      float* dst = S.psi[(k + h) & 7];
+      dst[tid] = pv[h][0];
+      if (tid < C3 - NT3) dst[tid + NT3] = pv[h][1];
+    }
+    __syncthreads();
+    if (HYDRO) {  // fluxes psi u of slices k - 2, k - 1 (xy halo 1; normal component odd)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float* jd = S.u[(k - 2 + h) & 3][0];
+        const float* pp = S.psi[(k - 2 + h) & 7];
+        const float ps = pp[pi];
+        jd[oi] = ps * uv[h][0][0];
+        jd[C1 + oi] = ps * uv[h][0][1];
+        jd[2 * C1 + oi] = ps * uv[h][0][2];
+        if (has_h) {
+          const float pq = pp[ph];
+          jd[oh] = pq * uv[h][1][0];
+          jd[C1 + oh] = pq * uv[h][1][1];
+          jd[2 * C1 + oh] = pq * uv[h][1][2];
+        }
+      }
+    }
+    load(T.z0 - 3 + k + 2, pv[0], uv[0]);
+    load(T.z0 - 3 + k + 3, pv[1], uv[1]);
+    if (k >= 4) {  // mu of slices k - 2 and k - 1 (from slice z0 - 1 on), sharing their reads
+      const float a0 = S.a[k - 2], a1 = S.a[k - 1];
+      const float* q0 = S.psi[(k - 4) & 7];
+      const float* q1 = S.psi[(k - 3) & 7];
+      const float* q2 = S.psi[(k - 2) & 7];
+      const float* q3 = S.psi[(k - 1) & 7];
+      const float* q4 = S.psi[k & 7];
+      const float* q5 = S.psi[(k + 1) & 7];
+      float* m0 = S.mu[(k - 2) & 3];
+      float* m1 = S.mu[(k - 1) & 3];
+      m0[oi] = mu_at(P, a0, q0, q1, q2, q3, q4, pi);
+      m1[oi] = mu_at(P, a1, q1, q2, q3, q4, q5, pi);
+      if (has_h) {
+        m0[oh] = mu_at(P, a0, q0, q1, q2, q3, q4, ph);
+        m1[oh] = mu_at(P, a1, q1, q2, q3, q4, q5, ph);
+      }
+    }
+    __syncthreads();
+    // output slices k - 3 + h read mu and the fluxes of slices k - 4 + h .. k - 2 + h
+    const float* mr[4];
+    const float* jr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      mr[i] = S.mu[(k - 4 + i) & 3];
+      jr[i] = S.u[(k - 4 + i) & 3][0];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = k - 3 + h, z = T.z0 - 3 + j;
       if (z < T.z0 || z >= T.z1 || !in_xy) continue;
-      const int r = ty + 1, c = tx + 1, R = ty + 3, C = tx + 3;
-      float(*mc)[BX + 2] = S.mu[((z % 4) + 4) % 4];
-      float(*md)[BX + 2] = S.mu[(((z - 1) % 4) + 4) % 4];
-      float(*mu_)[BX + 2] = S.mu[(((z + 1) % 4) + 4) % 4];
-      float(*pc)[BX + 6] = S.psi[((z % 8) + 8) % 8];
-      float(*pd)[BX + 6] = S.psi[(((z - 1) % 8) + 8) % 8];
-      float(*pu)[BX + 6] = S.psi[(((z + 1) % 8) + 8) % 8];
-      const float lapmu = ((mc[r][c + 1] + mc[r][c - 1]) + (mc[r + 1][c] + mc[r - 1][c])) +
-                          (mu_[r][c] + md[r][c]) - 6.f * mc[r][c];
+      const float* mc = mr[h + 1];
+      const float* md = mr[h];
+      const float* mu_ = mr[h + 2];
+      const float lapmu = ((mc[oi + 1] + mc[oi - 1]) + (mc[oi + W1] + mc[oi - W1])) +
+                          (mu_[oi] + md[oi]) - 6.f * mc[oi];
       float adv = 0.f;
       if (HYDRO) {
-        float(*jc)[BY + 2][BX + 2] = S.u[((z % 4) + 4) % 4];
-        float(*jd)[BY + 2][BX + 2] = S.u[(((z - 1) % 4) + 4) % 4];
-        float(*ju)[BY + 2][BX + 2] = S.u[(((z + 1) % 4) + 4) % 4];
+        const float* jc = jr[h + 1];
+        const float* jd = jr[h];
+        const float* ju = jr[h + 2];
         // div(psi u), isotropic first differences of the staged fluxes
-        auto flux = [&](int k) {
-          return [&, k](int dz, int dr, int dc) {
-            return (dz == 0 ? jc : (dz > 0 ? ju : jd))[k][r + dr][c + dc];
+        auto flux = [&](int kk) {
+          return [&, kk](int dz, int dr, int dc) {
+            return (dz == 0 ? jc : (dz > 0 ? ju : jd))[kk * C1 + oi + dr * W1 + dc];
           };
         };
         adv = iso3_x(flux(0)) + iso3_y(flux(1)) + iso3_z(flux(2));
       }
-      psi_out[((size_t)z * ny + y) * nx + x] = pc[R][C] + P.h * (-adv + P.Gamma * lapmu);
+      const float pc = S.psi[j & 7][pi];
+      *plane_at(psi_out, (uint32_t)z * plane + (uint32_t)(y * nx + x)) =
+          pc + P.h * (-adv + P.Gamma * lapmu);
     }
   };
   for (int k = 0; k < K; k += 2) pair(k);
