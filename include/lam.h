@@ -50,6 +50,12 @@ extern "C" {
 #define LAM_ESIZE (-3)       /* workspace or buffer too small                                    */
 #define LAM_ENONFINITE (-4)  /* observables found a NaN or infinite value in the state          */
 #define LAM_ESTATE (-5)      /* checkpoint does not match this simulation                        */
+#define LAM_ECORRUPT (-6)    /* a guard band of the workspace was overwritten                     */
+
+/* Guard bands: LAM_GUARD_BYTES of a fixed pattern before the first region of the workspace and
+ * after each of its regions (populations, phi, phi scratch, u, T, reduction partials, observable
+ * scratch); they are counted in lam_workspace_bytes. */
+#define LAM_GUARD_BYTES 256
 
 typedef struct lam_params {
   int32_t dim;               /* 2 (D2Q9) or 3 (D3Q19)                                              */
@@ -178,6 +184,16 @@ int lam_advance_temperature(lam_sim* s, int64_t nsteps);
 int lam_state_bytes(const lam_sim* s, size_t* bytes);
 int lam_get_state(lam_sim* s, void* d_buf, size_t bytes);
 int lam_set_state(lam_sim* s, const void* d_buf, size_t bytes);
+
+/* Race and bounds check.  lam_init_fields and lam_set_state fill every guard band with a fixed
+ * 32-bit pattern; lam_check_guards copies the bands to the host (synchronises) and returns
+ * LAM_ECORRUPT, naming the region before the first damaged band in lam_last_error and setting
+ * *h_first_bad to its index (else -1; NULL allowed), if a kernel wrote past the end of a region.
+ * LAM_EINVAL before the fields are initialised.  lam_guard_layout writes the byte offsets of the
+ * bands within the workspace of parameter set p to h_offsets[max] and their number to *count
+ * (LAM_ESIZE if max is too small; host only, no device call). */
+int lam_check_guards(lam_sim* s, int32_t* h_first_bad);
+int lam_guard_layout(const lam_params* p, size_t* h_offsets, int32_t max, int32_t* count);
 
 /* Profiling aid.  With timing enabled, lam_step launches each kernel with a pair of HIP events
  * that take the kernel's own start and end timestamps (hipExtLaunchKernelGGL).  lam_kernel_times synchronises, writes the accumulated kernel time

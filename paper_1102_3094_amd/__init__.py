@@ -11,7 +11,9 @@ import os
 
 from .build import LIB_PATH
 
-LAM_OK, LAM_EINVAL, LAM_EHIP, LAM_ESIZE, LAM_ENONFINITE, LAM_ESTATE = 0, -1, -2, -3, -4, -5
+LAM_OK, LAM_EINVAL, LAM_EHIP, LAM_ESIZE, LAM_ENONFINITE, LAM_ESTATE, LAM_ECORRUPT = (
+    0, -1, -2, -3, -4, -5, -6)
+LAM_GUARD_BYTES = 256
 
 
 class LamError(RuntimeError):
@@ -42,6 +44,7 @@ EXPORTS = ("lam_workspace_bytes", "lam_create", "lam_substeps", "lam_init_fields
            "lam_state_bytes", "lam_get_state", "lam_set_state", "lam_set_timing",
            "lam_kernel_times", "lam_last_error", "lam_destroy", "lam_set_fields",
            "lam_advance_temperature", "lam_structure_factor_static", "lam_launch_mode",
+           "lam_check_guards", "lam_guard_layout",
            "lam_ensemble_workspace_bytes", "lam_ensemble_create", "lam_ensemble_member",
            "lam_ensemble_init_fields", "lam_ensemble_step", "lam_ensemble_tune",
            "lam_ensemble_sites", "lam_ensemble_last_error", "lam_ensemble_destroy")
@@ -74,6 +77,8 @@ def load():
     L.lam_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.lam_get_state.argtypes = [vp, vp, C.c_size_t]
     L.lam_set_state.argtypes = [vp, vp, C.c_size_t]
+    L.lam_check_guards.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.lam_guard_layout.argtypes = [pp, C.POINTER(C.c_size_t), C.c_int32, C.POINTER(C.c_int32)]
     L.lam_set_timing.argtypes = [vp, C.c_int32]
     L.lam_launch_mode.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float),
                                   C.POINTER(C.c_float)]
@@ -124,6 +129,16 @@ def _check(rc: int, handle=None):
     if rc != LAM_OK:
         msg = load().lam_last_error(handle).decode(errors="replace")
         raise LamError(rc, msg)
+
+
+def guard_layout(params: dict) -> list:
+    """Byte offsets of the guard bands within the workspace of a parameter set (host only)."""
+    q = make_params(params)
+    n = C.c_int32()
+    load().lam_guard_layout(C.byref(q), None, 0, C.byref(n))
+    offs = (C.c_size_t * max(n.value, 1))()
+    _check(load().lam_guard_layout(C.byref(q), offs, n.value, C.byref(n)))
+    return list(offs[:n.value])
 
 
 def workspace_bytes(params: dict) -> int:
@@ -302,6 +317,13 @@ class Sim:
 
     def set_state(self, buf):
         self._chk(load().lam_set_state(self._h, C.c_void_p(buf.data_ptr()), buf.numel()))
+        return self
+
+    def check_guards(self):
+        """Raise LamError (code LAM_ECORRUPT, naming the region) if a guard band of the workspace
+        was overwritten; synchronises."""
+        bad = C.c_int32()
+        self._chk(load().lam_check_guards(self._h, C.byref(bad)))
         return self
 
     def launch_mode(self) -> dict:

@@ -91,6 +91,8 @@ struct lam_sim {
   int nblk;
   int64_t step;
   bool initialised;
+  bool guards_set = false;   // the guard bands hold the pattern (set with the fields)
+  size_t guard[14];          // offsets of the guard bands in the workspace
   std::string err;
   // kernel timing (profiling aid)
   bool timing = false;
@@ -106,24 +108,44 @@ struct lam_sim {
 
 namespace {
 
+// Guard bands: LAM_GUARD_BYTES of a fixed 32-bit pattern before the first region of the workspace
+// and after every region, filled when the fields are initialised or restored and compared by
+// lam_check_guards.  A kernel that writes past the end of a field (a halo or tile-edge mistake)
+// changes the band behind it.
+constexpr int GUARD_BANDS = 14;
+constexpr uint32_t GUARD_WORD = 0x7FA5C3E1u;  // a NaN with a payload no kernel writes
+static_assert(sizeof(lam_sim::guard) / sizeof(size_t) == GUARD_BANDS, "one offset per band");
+const char* const GUARD_AFTER[GUARD_BANDS] = {
+    "the workspace start", "populations[0]", "populations[1]", "phi[0]", "phi[1]", "psi[0]",
+    "psi[1]", "u", "T[0]", "T[1]", "T[2]", "partials", "result", "observable scratch"};
+
 struct Layout {
   size_t g[2], phi[2], psi[2], u, T[3], partials, result, spec, total;
+  size_t guard[GUARD_BANDS];
   int nblk;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout layout(const lam_params& p) {
+  static_assert(LAM_GUARD_BYTES % 256 == 0, "guard bands keep every region 256-byte aligned");
   Layout L{};
   const size_t N = (size_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
   const int Q = p.dim == 2 ? 9 : 19;
   const int nrows = p.dim == 2 ? p.ny : p.nz;
   size_t off = 0;
+  int band = 0;
+  auto guard = [&]() {
+    L.guard[band++] = off;
+    off += LAM_GUARD_BYTES;
+  };
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align256(off + bytes);
+    guard();
     return o;
   };
+  guard();
   const size_t esz = p.pop_storage == 1 ? 2 : 4;
   for (int i = 0; i < 2; ++i) L.g[i] = take(esz * Q * N);
   for (int i = 0; i < 2; ++i) L.phi[i] = take(sizeof(float) * N);
@@ -216,6 +238,14 @@ int validate(const lam_params* p, std::string& why) {
   return LAM_OK;
 }
 
+int fill_guards(lam_sim* s) {
+  for (int i = 0; i < GUARD_BANDS; ++i)
+    HIPCHK(s, hipMemsetD32Async((hipDeviceptr_t)(s->ws + s->guard[i]), (int)GUARD_WORD,
+                                LAM_GUARD_BYTES / 4, s->st));
+  s->guards_set = true;
+  return LAM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -268,6 +298,7 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   s->result = (double*)(s->ws + L.result);
   s->spec = s->ws + L.spec;
   s->nblk = L.nblk;
+  for (int i = 0; i < GUARD_BANDS; ++i) s->guard[i] = L.guard[i];
   s->pop_bytes = (p->pop_storage == 1 ? 2 : 4) * (size_t)s->Q * s->N;
   KParams& k = s->k;
   k.nx = p->nx;
@@ -311,6 +342,7 @@ int lam_init_fields(lam_sim* s, const float* d_phi0, const float* d_u0, const fl
   HIPCHK(s, hipMemsetAsync(s->u, 0, sizeof(float) * s->p.dim * s->N, s->st));
   HIPCHK(s, launch_init_T(s->nrows, s->p.walls, (float)s->p.T0, (float)s->p.Tw, s->p.xi < 0,
                           s->T[0], s->T[1], s->st));
+  if (int rc = fill_guards(s)) return rc;
   s->step = 0;
   s->initialised = true;
   return LAM_OK;
@@ -715,8 +747,44 @@ int lam_set_state(lam_sim* s, const void* d_buf, size_t bytes) {
   b += sizeof(float) * s->N;
   for (int i = 0; i < 2; ++i)
     HIPCHK(s, hipMemcpyAsync(s->T[i], b, sizeof(float) * s->nrows, hipMemcpyDeviceToDevice, s->st));
+  if (int rc = fill_guards(s)) return rc;
   s->step = step;
   s->initialised = true;
+  return LAM_OK;
+}
+
+int lam_guard_layout(const lam_params* p, size_t* h_offsets, int32_t max, int32_t* count) {
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  if (!count) return fail(nullptr, LAM_EINVAL, "null count");
+  *count = GUARD_BANDS;
+  if (max < GUARD_BANDS || !h_offsets) return fail(nullptr, LAM_ESIZE, "offset array too small");
+  const Layout L = layout(*p);
+  for (int i = 0; i < GUARD_BANDS; ++i) h_offsets[i] = L.guard[i];
+  return LAM_OK;
+}
+
+int lam_check_guards(lam_sim* s, int32_t* h_first_bad) {
+  if (!s) return LAM_EINVAL;
+  if (h_first_bad) *h_first_bad = -1;
+  if (!s->guards_set) return fail(s, LAM_EINVAL, "fields not initialised (no guard bands yet)");
+  std::vector<uint32_t> h((size_t)GUARD_BANDS * LAM_GUARD_BYTES / 4);
+  for (int i = 0; i < GUARD_BANDS; ++i)
+    HIPCHK(s, hipMemcpyAsync(h.data() + (size_t)i * LAM_GUARD_BYTES / 4, s->ws + s->guard[i],
+                             LAM_GUARD_BYTES, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  for (int i = 0; i < GUARD_BANDS; ++i) {
+    int bad = 0;
+    for (int w = 0; w < LAM_GUARD_BYTES / 4; ++w)
+      bad += h[(size_t)i * LAM_GUARD_BYTES / 4 + w] != GUARD_WORD;
+    if (bad) {
+      if (h_first_bad) *h_first_bad = i;
+      return fail(s, LAM_ECORRUPT, std::string("guard band after ") + GUARD_AFTER[i] +
+                                       " overwritten (" + std::to_string(bad) + " of " +
+                                       std::to_string(LAM_GUARD_BYTES / 4) + " words)");
+    }
+  }
   return LAM_OK;
 }
 

@@ -118,3 +118,27 @@ def test_ensemble_validation(L):
     d = S.model_params("c3_256cube_xi0.1", nx=16, ny=16, nz=16)
     arr = (lam.lam_params * 2)(lam.make_params(a), lam.make_params(d))
     assert L.lam_ensemble_workspace_bytes(arr, 2, C.byref(n)) == lam.LAM_EINVAL
+
+
+@pytest.mark.parametrize("name,over", [("c1_64sq", dict()), ("c1_64sq", dict(pop_storage=1)),
+                                       ("c1_64sq", dict(nx=72, ny=40)),
+                                       ("c3_256cube_xi0.1", dict(nx=37, ny=12, nz=70)),
+                                       ("c3_256cube_xi0.1", dict(nx=64, ny=16, nz=9, pop_storage=1))])
+def test_guard_bands_separate_every_region(L, name, over):
+    """Guard bands: one at the workspace start and one behind every region, each 256-byte aligned,
+    none inside the room a region needs, the last one ending the workspace (host only)."""
+    p = S.model_params(name, **over)
+    offs = lam.guard_layout(p)
+    total = lam.workspace_bytes(p)
+    assert len(offs) == 14 and offs[0] == 0
+    assert all(o % 256 == 0 for o in offs)
+    assert offs[-1] + lam.LAM_GUARD_BYTES == total
+    N = p["nx"] * p["ny"] * (p["nz"] if p["dim"] == 3 else 1)
+    Q = 9 if p["dim"] == 2 else 19
+    esz = 2 if p.get("pop_storage", 0) else 4
+    nrows = p["ny"] if p["dim"] == 2 else p["nz"]
+    need = [Q * N * esz] * 2 + [4 * N] * 4 + [4 * p["dim"] * N] + [4 * nrows] * 3
+    for i, b in enumerate(need):  # region i lies between band i and band i + 1
+        assert offs[i + 1] - (offs[i] + lam.LAM_GUARD_BYTES) >= b
+    gaps = [offs[i + 1] - offs[i] - lam.LAM_GUARD_BYTES for i in range(13)]
+    assert min(gaps) > 0
