@@ -176,7 +176,8 @@ int lam_get_fields(lam_sim* s, float* d_phi, float* d_u, float* d_n, float* d_T)
 int lam_set_fields(lam_sim* s, const float* d_phi, const float* d_u, const float* d_n);
 
 /* Advance only the temperature by nsteps time steps (the FTCS sub-steps lam_step applies to T,
- * Section 2) and the step count; phi and the populations are unchanged.  Asynchronous. */
+ * Section 2) and the step count; phi and the populations are unchanged.  Asynchronous.  At most
+ * 8192 layers along the wall axis (the profile is held in LDS); LAM_EINVAL beyond. */
 int lam_advance_temperature(lam_sim* s, int64_t nsteps);
 
 /* Checkpoint: the complete state (populations, phi, T, step) in lam_state_bytes() bytes of

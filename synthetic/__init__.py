@@ -48,6 +48,41 @@ def phi0(shape, seed: int = 1, amplitude: float = 0.05) -> np.ndarray:
     return (amplitude * (2.0 * u - 1.0)).astype(np.float32).astype(np.float64).reshape(shape)
 
 
+def phi0_f32(shape, seed: int = 1, amplitude: float = 0.05, threads: int = 16,
+             chunk: int = 1 << 23) -> np.ndarray:
+    """The same field as ``phi0`` as a float32 array, generated in chunks on ``threads`` threads
+    (for lattices of up to about 2^30 sites)."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = int(np.prod(shape))
+    out = np.empty(n, dtype=np.float32)
+
+    def work(o):
+        m = min(chunk, n - o)
+        u = uniform01(seed, m, offset=o)
+        out[o:o + m] = (amplitude * (2.0 * u - 1.0)).astype(np.float32)
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, range(0, n, chunk)))
+    return out.reshape(shape)
+
+
+def phi0_patch(shape, origin, size, seed: int = 1, amplitude: float = 0.05) -> np.ndarray:
+    """The values of ``phi0(shape, seed, amplitude)`` on a periodically wrapped box of ``size``
+    cells per axis starting at ``origin`` (both in the axis order of ``shape``), without
+    generating the whole field."""
+    idx = np.zeros(size, dtype=np.int64)
+    stride = 1
+    for ax in range(len(shape) - 1, -1, -1):
+        c = (origin[ax] + np.arange(size[ax])) % shape[ax]
+        sh = [1] * len(shape)
+        sh[ax] = size[ax]
+        idx = idx + (c * stride).reshape(sh)
+        stride *= shape[ax]
+    z = splitmix64(seed, idx.reshape(-1).astype(np.uint64))
+    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return (amplitude * (2.0 * u - 1.0)).astype(np.float32).astype(np.float64).reshape(size)
+
+
 # Model parameters of the workloads.  tau: BGK relaxation time; Gamma: mobility; b, kappa, c:
 # Brazovskii free-energy coefficients; Tc, T0, Tw: critical, initial and wall temperatures;
 # xi: thermal conductivity (a negative value stands for an infinitely fast quench).  _DEEP_QUENCH:
