@@ -391,15 +391,21 @@ struct Phi2dDims {
   static constexpr int W = TX + 2 * R;
 };
 
+// Register strips of the phi sub-steps: KS cells of one column per thread.
+constexpr int PHI_KS = 4;
+
+// Every plane has PHI_KS rows beyond its last valid row: a strip that runs past the valid rows
+// reads them (unwritten values that feed only cells that are not computed), so no read is
+// clamped and each strip addresses its cells from one base with constant offsets.
 template <int S_, int TY, bool HYDRO>
 struct Phi2dSmem {
   using D = Phi2dDims<S_, TY>;
   static constexpr int H = D::H, W = D::W, HU = H - 4, WU = W - 4;
-  float A[H][W];
-  float B[H][W];
-  float Cm[HU][WU];
-  float Ux[HYDRO ? HU : 1][HYDRO ? WU : 1];
-  float Uy[HYDRO ? HU : 1][HYDRO ? WU : 1];
+  float A[H + PHI_KS][W];
+  float B[H + PHI_KS][W];
+  float Cm[HU + PHI_KS][WU];
+  float Ux[HYDRO ? HU + PHI_KS : 1][HYDRO ? WU : 1];
+  float Uy[HYDRO ? HU + PHI_KS : 1][HYDRO ? WU : 1];
   float sa[H];
   int rowoff[H], colx[W];
   float rowsgn[H];  // -1 on mirror-image rows (wall-normal velocity is odd)
@@ -486,7 +492,9 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
   // shares in registers (the 13-point biharmonic reads 7 instead of 13 LDS values per cell, the
   // update 15.5 instead of 30).  Consecutive lanes take consecutive columns.  Rows beyond a
   // plane's valid depth are clamped into the array and only feed cells that are not computed.
-  constexpr int KS = 4;
+  constexpr int KS = PHI_KS;
+  // strips read psi rows up to H - dd + KS (dd >= 2) and mu / velocity rows up to
+  // HU - dd + KS + 1 (dd >= 3): within the padded planes
   float(*ps)[W] = A;   // current psi
   float(*nx_)[W] = B;  // next psi
 #pragma unroll
@@ -500,19 +508,18 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
         const int c = dd + (t - rb * ww), r0 = dd + KS * rb;
         const int kk = min(KS, H - dd - r0);
         float cC[KS + 4], cL[KS + 2], cR[KS + 2], cLL[KS], cRR[KS];
+        const float* b = &ps[r0 - 2][c - 2];  // lowest row and column the strip reads
 #pragma unroll
-        for (int j = 0; j < KS + 4; ++j) cC[j] = ps[min(r0 - 2 + j, H - 1)][c];
+        for (int j = 0; j < KS + 4; ++j) cC[j] = b[j * W + 2];
 #pragma unroll
         for (int j = 0; j < KS + 2; ++j) {
-          const int rr = min(r0 - 1 + j, H - 1);
-          cL[j] = ps[rr][c - 1];
-          cR[j] = ps[rr][c + 1];
+          cL[j] = b[(j + 1) * W + 1];
+          cR[j] = b[(j + 1) * W + 3];
         }
 #pragma unroll
         for (int j = 0; j < KS; ++j) {
-          const int rr = min(r0 + j, H - 1);
-          cLL[j] = ps[rr][c - 2];
-          cRR[j] = ps[rr][c + 2];
+          cLL[j] = b[(j + 2) * W];
+          cRR[j] = b[(j + 2) * W + 4];
         }
 #pragma unroll
         for (int i = 0; i < KS; ++i) {
@@ -550,30 +557,31 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
         const int c2 = c - 2;  // column in the planes that start at depth 2 (mu, velocity)
         // mu: column c rows r0 - 1 .. r0 + KS, columns c +- 1 rows r0 .. r0 + KS - 1
         float mC[KS + 2], mL[KS], mR[KS];
+        const float* bm = &Cm[r0 - 3][c2 - 1];  // lowest row and column read, per plane
 #pragma unroll
-        for (int j = 0; j < KS + 2; ++j) mC[j] = Cm[min(r0 - 3 + j, HU - 1)][c2];
+        for (int j = 0; j < KS + 2; ++j) mC[j] = bm[j * WU + 1];
 #pragma unroll
         for (int j = 0; j < KS; ++j) {
-          const int rr = min(r0 - 2 + j, HU - 1);
-          mL[j] = Cm[rr][c2 - 1];
-          mR[j] = Cm[rr][c2 + 1];
+          mL[j] = bm[(j + 1) * WU];
+          mR[j] = bm[(j + 1) * WU + 2];
         }
         // psi in columns c - 1, c, c + 1, rows r0 - 1 .. r0 + KS, and the fluxes psi u there
         float pC[KS + 2], pL[KS + 2], pR[KS + 2];
         float jxL[KS + 2], jxR[KS + 2], jyL[KS + 2], jyC[KS + 2], jyR[KS + 2];
+        const float* bp = &ps[r0 - 1][c - 1];
+        const float* bx = &Ux[HYDRO ? r0 - 3 : 0][HYDRO ? c2 - 1 : 0];
+        const float* by = &Uy[HYDRO ? r0 - 3 : 0][HYDRO ? c2 - 1 : 0];
 #pragma unroll
         for (int j = 0; j < KS + 2; ++j) {
-          const int rr = min(r0 - 1 + j, H - 1);
-          pC[j] = ps[rr][c];
-          pL[j] = ps[rr][c - 1];
-          pR[j] = ps[rr][c + 1];
+          pC[j] = bp[j * W + 1];
+          pL[j] = bp[j * W];
+          pR[j] = bp[j * W + 2];
           if (HYDRO) {
-            const int ru = min(r0 - 3 + j, HU - 1);
-            jxL[j] = pL[j] * Ux[ru][c2 - 1];
-            jxR[j] = pR[j] * Ux[ru][c2 + 1];
-            jyL[j] = pL[j] * Uy[ru][c2 - 1];
-            jyC[j] = pC[j] * Uy[ru][c2];
-            jyR[j] = pR[j] * Uy[ru][c2 + 1];
+            jxL[j] = pL[j] * bx[j * WU];
+            jxR[j] = pR[j] * bx[j * WU + 2];
+            jyL[j] = pL[j] * by[j * WU];
+            jyC[j] = pC[j] * by[j * WU + 1];
+            jyR[j] = pR[j] * by[j * WU + 2];
           }
         }
 #pragma unroll

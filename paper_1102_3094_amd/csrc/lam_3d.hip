@@ -262,9 +262,11 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       const float* pd = S.phi[ring_back<5>(m5, 2)];
       const float* pu = S.phi[m5];
       float* dst = S.L[ring_back<3>(m3, 1)];
+      // reads as a per-thread base (the lowest cell read) plus constants, which the LDS
+      // instructions take as immediate offsets
       auto lap = [&](int o) {
-        return ((pc[o + 1] + pc[o - 1]) + (pc[o + W3] + pc[o - W3])) + (pu[o] + pd[o]) -
-               6.f * pc[o];
+        const float *c = pc + o - W3, *u = pu + o, *d = pd + o;
+        return ((c[W3 + 1] + c[W3 - 1]) + (c[2 * W3] + c[0])) + (u[0] + d[0]) - 6.f * c[W3];
       };
       dst[tid] = lap(lph[0]);
       if (tid < C2 - NT3) dst[tid + NT3] = lap(lph[1]);
@@ -280,17 +282,20 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       const float* lu = S.L[ring_back<3>(m3, 1)];
       float* dst = &S.P[ring_back<3>(m3, 2)][0][0];
       auto item = [&](int i, int op, int ol) {
-        const float ph = pc[op], L = lc[ol];
-        const float M = ((lc[ol + 1] + lc[ol - 1]) + (lc[ol + W2] + lc[ol - W2])) +
-                        (lu[ol] + ld[ol]) - 6.f * L;
+        // per-thread bases at the lowest cell read (row -1, column -1): constant offsets only
+        const float *pc0 = pc + op - W3 - 1, *pu0 = pu + op - W3 - 1, *pd0 = pd + op - W3 - 1;
+        const float *lc0 = lc + ol - W2 - 1, *lu0 = lu + ol - W2 - 1, *ld0 = ld + ol - W2 - 1;
+        const float ph = pc0[W3 + 1], L = lc0[W2 + 1];
+        const float M = ((lc0[W2 + 2] + lc0[W2]) + (lc0[2 * W2 + 1] + lc0[1])) +
+                        (lu0[W2 + 1] + ld0[W2 + 1]) - 6.f * L;
         if (P.force_form == 1) {
           dst[i] = a * ph + P.b * ph * ph * ph - P.kappa * L + P.c * M;
         } else {
           auto fp = [&](int dz, int dr, int dc) {
-            return (dz == 0 ? pc : (dz > 0 ? pu : pd))[op + dr * W3 + dc];
+            return (dz == 0 ? pc0 : (dz > 0 ? pu0 : pd0))[(dr + 1) * W3 + dc + 1];
           };
           auto fl = [&](int dz, int dr, int dc) {
-            return (dz == 0 ? lc : (dz > 0 ? lu : ld))[ol + dr * W2 + dc];
+            return (dz == 0 ? lc0 : (dz > 0 ? lu0 : ld0))[(dr + 1) * W2 + dc + 1];
           };
           const float px = iso3_x(fp), py = iso3_y(fp), pz = iso3_z(fp);
           const float Lx = iso3_x(fl), Ly = iso3_y(fl), Lz = iso3_z(fl);
@@ -309,9 +314,11 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       const float* pc = S.phi[ring_back<5>(m5, 3)];
       float Fx = 0.f, Fy = 0.f, Fz = 0.f;
       if (P.hydro) {  // isotropic first differences of P (or of mu)
+        // per-thread bases at the lowest cell read: constant offsets only
+        const float *Pc0 = Pc + o - W1 - 1, *Pu0 = Pu + o - W1 - 1, *Pd0 = Pd + o - W1 - 1;
         auto fP = [&](int kk) {
           return [&, kk](int dz, int dr, int dc) {
-            return (dz == 0 ? Pc : (dz > 0 ? Pu : Pd))[kk * C1 + o + dr * W1 + dc];
+            return (dz == 0 ? Pc0 : (dz > 0 ? Pu0 : Pd0))[kk * C1 + (dr + 1) * W1 + dc + 1];
           };
         };
         if (P.force_form == 1) {
@@ -461,12 +468,15 @@ struct Phi3dSmem {
 __device__ __forceinline__ float mu_at(const KParams& P, float a, const float* m2,
                                        const float* m1, const float* c0, const float* p1,
                                        const float* p2, int o) {
-  const float v = c0[o];
-  const float face = ((c0[o + 1] + c0[o - 1]) + (c0[o + W3] + c0[o - W3])) + (p1[o] + m1[o]);
-  const float edge = ((c0[o + W3 + 1] + c0[o + W3 - 1]) + (c0[o - W3 + 1] + c0[o - W3 - 1])) +
-                     ((p1[o + 1] + p1[o - 1]) + (m1[o + 1] + m1[o - 1])) +
-                     ((p1[o + W3] + p1[o - W3]) + (m1[o + W3] + m1[o - W3]));
-  const float far = ((c0[o + 2] + c0[o - 2]) + (c0[o + 2 * W3] + c0[o - 2 * W3])) + (p2[o] + m2[o]);
+  // bases at the lowest cell read (two rows and two columns below o): constant offsets only
+  const int B = 2 * W3 + 2;
+  const float *c = c0 + o - B, *u = p1 + o - B, *d = m1 + o - B;
+  const float v = c[B];
+  const float face = ((c[B + 1] + c[B - 1]) + (c[B + W3] + c[B - W3])) + (p1[o] + m1[o]);
+  const float edge = ((c[B + W3 + 1] + c[B + W3 - 1]) + (c[B - W3 + 1] + c[B - W3 - 1])) +
+                     ((u[B + 1] + u[B - 1]) + (d[B + 1] + d[B - 1])) +
+                     ((u[B + W3] + u[B - W3]) + (d[B + W3] + d[B - W3]));
+  const float far = ((c[B + 2] + c[B - 2]) + (c[B + 2 * W3] + c[2])) + (p2[o] + m2[o]);
   const float L = face - 6.f * v;
   const float M = 42.f * v - 12.f * face + 2.f * edge + far;
   return a * v + P.b * v * v * v - P.kappa * L + P.c * M;
@@ -621,17 +631,19 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
       const float* mc = mr[h + 1];
       const float* md = mr[h];
       const float* mu_ = mr[h + 2];
-      const float lapmu = ((mc[oi + 1] + mc[oi - 1]) + (mc[oi + W1] + mc[oi - W1])) +
-                          (mu_[oi] + md[oi]) - 6.f * mc[oi];
+      // per-thread bases at the lowest cell read (row -1, column -1): constant offsets only
+      const float* mc0 = mc + oi - W1 - 1;
+      const float lapmu = ((mc0[W1 + 2] + mc0[W1]) + (mc0[2 * W1 + 1] + mc0[1])) +
+                          (mu_[oi] + md[oi]) - 6.f * mc0[W1 + 1];
       float adv = 0.f;
       if (HYDRO) {
-        const float* jc = jr[h + 1];
-        const float* jd = jr[h];
-        const float* ju = jr[h + 2];
+        const float* jc = jr[h + 1] + oi - W1 - 1;
+        const float* jd = jr[h] + oi - W1 - 1;
+        const float* ju = jr[h + 2] + oi - W1 - 1;
         // div(psi u), isotropic first differences of the staged fluxes
         auto flux = [&](int kk) {
           return [&, kk](int dz, int dr, int dc) {
-            return (dz == 0 ? jc : (dz > 0 ? ju : jd))[kk * C1 + oi + dr * W1 + dc];
+            return (dz == 0 ? jc : (dz > 0 ? ju : jd))[kk * C1 + (dr + 1) * W1 + dc + 1];
           };
         };
         adv = iso3_x(flux(0)) + iso3_y(flux(1)) + iso3_z(flux(2));
