@@ -208,11 +208,10 @@ def unet_shapes(in_ch, levels=4, base=32):
 
 
 def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noise=0.0,
-                    held_out=(99, 98, 97), density=False, unroll_steps=1000, curves=None):
+                    held_out=(99, 98, 97), unroll_steps=1000, curves=None):
     """Train the surrogate on plain runs and compare the accelerated run with the plain solver.
-    With `density` the network also reads and predicts the lattice density n; `unroll_steps`
-    Adam steps of two-step training follow the one-step rounds; `curves` (a path) receives the
-    S(k) curves of the held-out runs as JSON."""
+    `unroll_steps` Adam steps of two-step training follow the one-step rounds; `curves` (a path)
+    receives the S(k) curves of the held-out runs as JSON."""
     import numpy as np
     import torch
     import synthetic as S
@@ -221,16 +220,15 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
     t_start, nsnap, every = 8000, 200, 100
     mem, phis = S.surrogate_members(seed=7, count=members + 1, side=side, instant=members + 1)
     t = time.perf_counter()
-    snaps = ST.snapshots(mem, phis, t_start, nsnap, every, density=density)
+    snaps = ST.snapshots(mem, phis, t_start, nsnap, every)
     val, train = snaps[members:], snaps[:members]
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t
     print(f"surrogate: {members + 1} runs of {side}^2 snapshotted in {gen_s:.1f} s", file=sys.stderr,
           flush=True)
     norm = ST.normalisation(train, mem[0]["Tc"])
-    d = int(bool(density))
-    shapes = unet_shapes(5 + d)
-    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3 + d)), dtype=torch.float32, device="cuda:0")
+    shapes = unet_shapes(5)
+    th = torch.tensor(S.he_uniform(5, shapes, head=(32, 3)), dtype=torch.float32, device="cuda:0")
     net = Surrogate(side, side, training=True, **norm).set_params(th)
     val0 = ST.validation_loss(net, val)
     stream = torch.cuda.Stream()  # a capturable stream: the rollout replays its step graph
@@ -330,7 +328,7 @@ def bench_surrogate(members=16, train_steps=6000, anchor_steps=50, side=512, noi
         "no_network_phi_rel_l2": None if r["no_network_phi_rel_l2"] is None else round(r["no_network_phi_rel_l2"], 4),
         "finite": bool(r["surrogate_finite"]),
         "finite_runs": sum(bool(q["surrogate_finite"]) for q in runs), "held_out_runs": len(runs),
-        "per_run": per_run, "input_noise": noise, "density_channel": bool(density),
+        "per_run": per_run, "input_noise": noise,
         "reanchor_every_5_calls": every5,
         "limiter_factor": 1.05, "without_limiter": no_lim,
         "validation_loss_untrained": round(val0, 4), "validation_loss_trained": round(val1, 4),
@@ -388,8 +386,6 @@ def main():
                     help="plain steps after every 10 surrogate calls (re-anchoring)")
     ap.add_argument("--surrogate-curves", default=None,
                     help="file for the S(k) curves of the held-out surrogate runs (JSON)")
-    ap.add_argument("--surrogate-density", type=int, default=0, choices=(0, 1),
-                    help="1: the surrogate also reads and predicts the lattice density")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the learned-surrogate leg, printed as its own JSON line")
     ap.add_argument("--surrogate-profile-pass", action="store_true",
@@ -415,7 +411,6 @@ def main():
         return bench_ensemble(args)
     if args.surrogate_only:
         print(json.dumps({"surrogate": bench_surrogate(train_steps=args.surrogate_train_steps,
-                                                       density=bool(args.surrogate_density),
                                                        unroll_steps=args.surrogate_two_step,
                                                        curves=args.surrogate_curves,
                                                        anchor_steps=args.surrogate_anchor_steps)}),
@@ -466,7 +461,6 @@ def main():
         out["hbm_legs"] = legs
     if not args.no_surrogate and wl == WORKLOAD:
         out["surrogate"] = bench_surrogate(train_steps=args.surrogate_train_steps,
-                                           density=bool(args.surrogate_density),
                                            unroll_steps=args.surrogate_two_step,
                                            curves=args.surrogate_curves,
                                            anchor_steps=args.surrogate_anchor_steps)

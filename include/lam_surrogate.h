@@ -16,13 +16,12 @@
  * Parameter vector (FP32, lsn_param_count entries): for each 3x3 layer in the order e1a, e1, e2a,
  * e2, ..., eLa, eL, d(L-1)a, d(L-1), ..., d1a, d1 the weights [9][C_out][C_in] (tap = 3 (dy+1) +
  * (dx+1)) then the biases [C_out]; then the head weights [NOUT][base] and biases [NOUT].  C_in of
- * e1a is 5 + with_density; C_in of d(l)a is width(l+1) + width(l).
+ * e1a is 5; C_in of d(l)a is width(l+1) + width(l).
  *
  * Fields are planar FP32 in device memory: [4][H][W] = phi, u_x, u_y, T (x fastest), the layout
- * lam_get_fields writes, and with_density a fifth plane n (the lattice density).  Network inputs
- * are (field - shift) * scale per channel: phi, u_x, u_y, T, a (from T) and, with_density, n;
- * outputs are normalised increments of phi, u_x, u_y and, with_density, n:
- * field += out * out_scale.  NF = 4 + with_density field planes, NOUT = 3 + with_density outputs.
+ * lam_get_fields writes.  Network inputs are (field - shift) * scale per channel: phi, u_x, u_y,
+ * T and a (from T); outputs are normalised increments of phi, u_x, u_y: field += out * out_scale.
+ * NF = 4 field planes, NOUT = 3 outputs.
  *
  * Ownership: the caller owns every device buffer (one workspace of lsn_workspace_bytes); the
  * library allocates no device memory.  All work is queued on the caller's HIP stream; functions
@@ -47,10 +46,9 @@ typedef struct {
   int32_t levels;         /* 1 .. 5 */
   int32_t base_width;     /* channels of level 1: 32 or 64 */
   int32_t training;       /* 1: keep activations, gradients and Adam moments */
-  int32_t with_density;   /* 1: the density n is a sixth input and a fourth output channel */
   float Tc;               /* critical temperature, for a = (T - Tc)/Tc */
-  float in_shift[6], in_scale[6];  /* input normalisation of phi, u_x, u_y, T, a, n */
-  float out_scale[4];              /* increments of phi, u_x, u_y, n per unit output */
+  float in_shift[5], in_scale[5];  /* input normalisation of phi, u_x, u_y, T, a */
+  float out_scale[3];              /* increments of phi, u_x, u_y per unit output */
 } lsn_config;
 
 int lsn_param_count(const lsn_config* cfg, int64_t* count);
@@ -67,13 +65,13 @@ int lsn_get_params(lsn_net* net, float* d_params);
  * increments). */
 int lsn_forward(lsn_net* net, const float* d_fields, float* d_out);
 
-/* One surrogate step in place on d_fields [NF][H][W]: phi, u_x, u_y (and n) += out * out_scale,
- * then phi (and n) are shifted by a constant so that their sums over the lattice are unchanged
+/* One surrogate step in place on d_fields [NF][H][W]: phi, u_x, u_y += out * out_scale,
+ * then phi is shifted by a constant so that its sum over the lattice is unchanged
  * (the exact conservation of sum phi, eq. massdiff, and of the mass).  T is left alone. */
 int lsn_advance(lsn_net* net, float* d_fields);
 
 /* Training target from two snapshots [NF][H][W] taken the surrogate's step count apart:
- * d_target [NOUT][H][W] = (later - earlier) / out_scale for phi, u_x, u_y (and n). */
+ * d_target [NOUT][H][W] = (later - earlier) / out_scale for phi, u_x, u_y. */
 int lsn_make_target(lsn_net* net, const float* d_earlier, const float* d_later, float* d_target);
 
 /* Loss and gradient (training networks only): loss = mean over the NOUT H W outputs of
@@ -98,10 +96,10 @@ int lsn_get_grads(lsn_net* net, float* d_grads);
 int lsn_adam(lsn_net* net, float lr, float beta1, float beta2, float eps, float grad_scale);
 
 /* Surrogate-accelerated run of the solver s (2D, walls normal to y, the network's lattice),
- * `cycles` times: read phi, u, T (and n) of s into d_fields [NF][H][W] (caller scratch), apply
+ * `cycles` times: read phi, u, T of s into d_fields [NF][H][W] (caller scratch), apply
  * `calls` surrogate steps (lsn_advance), each standing for `steps_per_call` lattice steps during
  * which T advances exactly (lam_advance_temperature), then re-anchor s on the result
- * (lam_set_fields with the predicted n, or n = 1 without the density channel) and run
+ * (lam_set_fields: populations restarted from the equilibrium at n = 1 and the predicted u) and run
  * `anchor_steps` plain steps (lam_step).  The simulated time advances by
  * cycles * (calls * steps_per_call + anchor_steps) steps.  Asynchronous on the network's stream,
  * which must be the stream of s.

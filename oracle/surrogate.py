@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE (part of the oracle).  Only tests and the benchmark's CPU ba
 The paper itself has no network; this is the learned part that advances the order parameter and
 the velocity of the hybrid lattice Boltzmann / finite-difference method by a fixed number of
 lattice steps.  The network maps the normalised fields (phi, u_x, u_y, T, a) on an H x W lattice
-to the increments of (phi, u_x, u_y) over those steps; with the density variant the input has a
-sixth channel (n) and the output a fourth (the increment of n).
+to the increments of (phi, u_x, u_y) over those steps (the channel counts are parameters of the
+functions below; the tests also use other counts).
 
 Architecture (L levels, widths w_1 .. w_L, default 4 levels of 32, 64, 128, 256 channels):
   encoder level l:   two 3x3 convolutions w_{l-1} -> w_l -> w_l, each followed by SiLU;

@@ -55,7 +55,7 @@ static thread_local std::string g_nn_error;
 struct lsn_net {
   lsn_config c;
   int L, H, W, wid[MAXL];
-  int nf, nout;    // field planes (4 + with_density) and output channels (3 + with_density)
+  int nf, nout;    // field planes (4) and output channels (3)
   size_t P[MAXL];  // pixels per level
   hipStream_t st;
   size_t nparam, head_off;
@@ -106,12 +106,10 @@ int check_config(const lsn_config* c) {
     return fail(nullptr, LAM_EINVAL,
                 "height must be a multiple of 4 * 2^(levels-1) and width of 32 * 2^(levels-1)");
   if (!(c->Tc != 0.f) || !isfinite(c->Tc)) return fail(nullptr, LAM_EINVAL, "Tc must be finite and non-zero");
-  if (c->with_density != 0 && c->with_density != 1)
-    return fail(nullptr, LAM_EINVAL, "with_density must be 0 or 1");
-  for (int i = 0; i < 5 + c->with_density; ++i)
+  for (int i = 0; i < 5; ++i)
     if (!isfinite(c->in_shift[i]) || !isfinite(c->in_scale[i]))
       return fail(nullptr, LAM_EINVAL, "input normalisation must be finite");
-  for (int i = 0; i < 3 + c->with_density; ++i)
+  for (int i = 0; i < 3; ++i)
     if (!isfinite(c->out_scale[i]) || c->out_scale[i] == 0.f)
       return fail(nullptr, LAM_EINVAL, "out_scale must be finite and non-zero");
   return LAM_OK;
@@ -125,7 +123,7 @@ void build_layers(const lsn_config& c, std::vector<Layer>& ly, size_t* nparam, s
   ly.clear();
   auto add = [&](int cin, int cout, int cin_pad) { ly.push_back(Layer{cin, cout, cin_pad, 0, 0, nullptr, nullptr, 0, false}); };
   for (int l = 0; l < L; ++l) {
-    if (l == 0) add(5 + c.with_density, w[0], IN_PAD);
+    if (l == 0) add(5, w[0], IN_PAD);
     else add(w[l - 1], w[l], w[l - 1]);
     add(w[l], w[l], w[l]);
   }
@@ -141,8 +139,7 @@ void build_layers(const lsn_config& c, std::vector<Layer>& ly, size_t* nparam, s
     o += q.cout;
   }
   *head_off = o;
-  const size_t nout = 3 + c.with_density;
-  *nparam = o + nout * w[0] + nout;
+  *nparam = o + 3 * (size_t)w[0] + 3;
 }
 
 int enc_a(int l) { return 2 * l; }
@@ -285,12 +282,11 @@ LayerIO layer_io(const lsn_net* n, int i, bool keep) {
 
 PackArgs pack_args(const lsn_net* n) {
   PackArgs pa;
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 5; ++i) {
     pa.shift[i] = n->c.in_shift[i];
     pa.scale[i] = n->c.in_scale[i];
   }
   pa.Tc = n->c.Tc;
-  pa.density = n->c.with_density;
   return pa;
 }
 
@@ -331,7 +327,6 @@ hipError_t fwd_layer(lsn_net* n, int i, bool keep, int shape = 0) {
       a.fuse = FUSE_HEAD;
       a.head_w = n->master + n->head_off;
       a.head_out = n->out;
-      a.nout = n->nout;
       a.head_part = n->dpart;
       n->head_parts = conv_blocks(a);
     }
@@ -456,8 +451,8 @@ static void init_dims(lsn_net* n, const lsn_config* cfg) {
   n->L = cfg->levels;
   n->H = cfg->height;
   n->W = cfg->width;
-  n->nf = 4 + cfg->with_density;
-  n->nout = 3 + cfg->with_density;
+  n->nf = 4;
+  n->nout = 3;
   for (int l = 0; l < n->L; ++l) {
     n->wid[l] = cfg->base_width << l;
     n->P[l] = (size_t)(n->H >> l) * (n->W >> l);
@@ -541,7 +536,7 @@ int lsn_advance(lsn_net* n, float* d_fields) {
   hipError_t e;
   if (n->timing && (e = hipEventRecord(n->ev0, n->st))) return hip_fail(n, e, "event");
   if ((e = forward(n, d_fields, n->c.training != 0))) return hip_fail(n, e, "forward");
-  if ((e = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->head_parts, n->st)))
+  if ((e = launch_apply(d_fields, n->out, n->P[0], n->c.out_scale, n->dpart, n->head_parts, n->st)))
     return hip_fail(n, e, "apply");
   if (n->timing) {
     if ((e = hipEventRecord(n->ev1, n->st))) return hip_fail(n, e, "event");
@@ -552,7 +547,7 @@ int lsn_advance(lsn_net* n, float* d_fields) {
 
 int lsn_make_target(lsn_net* n, const float* d_earlier, const float* d_later, float* d_target) {
   if (!n || !d_earlier || !d_later || !d_target) return fail(n, LAM_EINVAL, "null argument");
-  hipError_t e = launch_make_target(d_earlier, d_later, n->nout, n->P[0], n->c.out_scale, d_target,
+  hipError_t e = launch_make_target(d_earlier, d_later, n->P[0], n->c.out_scale, d_target,
                                     n->st);
   return e ? hip_fail(n, e, "target") : LAM_OK;
 }
@@ -629,7 +624,7 @@ int advance_step(lsn_net* n, float* d_fields) {
       hipError_t r = hipStreamBeginCapture(n->st, hipStreamCaptureModeThreadLocal);
       if (r == hipSuccess) {
         hipError_t r1 = forward(n, d_fields, false);
-        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->nout, n->P[0], n->c.out_scale, n->dpart, n->head_parts, n->st);
+        if (r1 == hipSuccess) r1 = launch_apply(d_fields, n->out, n->P[0], n->c.out_scale, n->dpart, n->head_parts, n->st);
         hipError_t r2 = hipStreamEndCapture(n->st, &g);
         if (r1 == hipSuccess && r2 == hipSuccess) {
           hipGraphExec_t ex;
@@ -663,12 +658,11 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
     return fail(n, LAM_EINVAL, "the simulation is not an initialised 2D run on the network's lattice");
   const size_t N = n->P[0];
   const bool frozen = lam::sim_temperature_frozen(s);
-  float* d_n = n->c.with_density ? d_fields + 4 * N : nullptr;
   const bool limit = n->lim_factor > 0.f;
   int r;
   hipError_t e;
   for (int c = 0; c < cycles; ++c) {
-    if ((r = lam_get_fields(s, d_fields, d_fields + N, d_n, d_fields + 3 * N)))
+    if ((r = lam_get_fields(s, d_fields, d_fields + N, nullptr, d_fields + 3 * N)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
     if (c == 0 && limit && (e = launch_absmax(d_fields, N, n->dpart, n->lim, n->st)))
       return hip_fail(n, e, "limiter");
@@ -681,7 +675,7 @@ int lsn_rollout(lsn_net* n, lam_sim* s, float* d_fields, int32_t cycles, int32_t
     }
     if (limit && (e = launch_clamp_conserve(d_fields, N, n->lim, n->lim_factor, n->dpart, n->st)))
       return hip_fail(n, e, "limiter");
-    if ((r = lam_set_fields(s, d_fields, d_fields + N, d_n)) || (r = lam_step(s, anchor_steps)))
+    if ((r = lam_set_fields(s, d_fields, d_fields + N, nullptr)) || (r = lam_step(s, anchor_steps)))
       return fail(n, r, std::string("solver: ") + lam_last_error(s));
   }
   return LAM_OK;

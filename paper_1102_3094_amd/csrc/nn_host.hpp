@@ -16,9 +16,8 @@ enum { CONV_FWD = 0, CONV_BWD_SILU = 1, CONV_BWD_PLAIN = 2 };
 enum { FUSE_NONE = 0, FUSE_FIELDS = 1, FUSE_POOL = 2, FUSE_HEAD = 3 };
 
 struct PackArgs {
-  float shift[6], scale[6];
+  float shift[5], scale[5];
   float Tc;
-  int density;  // the fields carry n as a fifth plane, packed as input channel 5
 };
 
 struct ConvArgs {
@@ -39,11 +38,10 @@ struct ConvArgs {
   int fuse;             // FUSE_*; forward passes only
   const float* fields;  // FUSE_FIELDS: planar FP32 [4][H][W] and its normalisation
   PackArgs pk;
-  const float* head_w;  // FUSE_HEAD: head weights [nout][32] then biases [nout]; output [nout][H][W]
+  const float* head_w;  // FUSE_HEAD: head weights [3][32] then biases [3]; output [3][H][W]
   float* head_out;
-  int nout;
-  double* head_part;    // FUSE_HEAD, optional: per-workgroup FP64 sums of output 0 at [block] and
-                        // of output 3 at [blocks + 1 + block] (the conservation shifts of a step)
+  double* head_part;    // FUSE_HEAD, optional: per-workgroup FP64 sums of output 0 at [block]
+                        // (the conservation shift of a step)
   int tiles_x, nco;     // set by the launcher
 };
 
@@ -73,7 +71,7 @@ int loss_blocks(size_t npix);
 // gout = d loss / d out (+ extra, nullable: a gradient of later uses of the output)
 hipError_t launch_loss_grad(const float* out, const float* t, const float* extra, int nout,
                             size_t npix, float* gout, double* part, hipStream_t st);
-// Gradient with respect to the planar fields [4 + density][npix] from that of the packed input.
+// Gradient with respect to the planar fields [4][npix] from that of the packed input.
 hipError_t launch_field_grad(const bf16_t* gx, size_t npix, const PackArgs& pa, float* g,
                              hipStream_t st);
 hipError_t launch_head_bwd(const bf16_t* d, int C, int nout, size_t npix, const float* gout,
@@ -83,16 +81,16 @@ hipError_t launch_refresh(const float* W, int Cout, int Cin, int Cin_pad, bf16_t
                           hipStream_t st);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, float lr, float b1,
                        float b2, float eps, float c1, float c2, float gscale, hipStream_t st);
-hipError_t launch_make_target(const float* e, const float* l, int nout, size_t npix, const float* s,
+hipError_t launch_make_target(const float* e, const float* l, size_t npix, const float* s,
                               float* t, hipStream_t st);
 // Rollout limiter: *out = max |x| (part: ceil(n / 256) doubles); phi clamped to +-factor * *bound
 // with the removed excess spread evenly so that sum phi is unchanged (part: ceil(n/256) + 1).
 hipError_t launch_absmax(const float* x, size_t n, double* part, double* out, hipStream_t st);
 hipError_t launch_clamp_conserve(float* phi, size_t n, const double* bound, float factor,
                                  double* part, hipStream_t st);
-// part: at least 2 (max(parts, ceil(npix / 256)) + 1) doubles.  parts > 0: the per-block sums
-// of the increments are already in part (written by the fused head of the forward pass).
-hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
+// part: at least max(parts, ceil(npix / 256)) + 1 doubles.  parts > 0: the per-block sums of the
+// phi increment are already in part (written by the fused head of the forward pass).
+hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s,
                         double* part, int parts, hipStream_t st);
 // Workgroups of a forward convolution launch (the grid launch_conv uses for these arguments).
 int conv_blocks(const ConvArgs& a);

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64 * WV) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) v[c] = (a.fields[c * np + q] - a.pk.shift[c]) * a.pk.scale[c];
           v[4] = ((a.fields[3 * np + q] - a.pk.Tc) / a.pk.Tc - a.pk.shift[4]) * a.pk.scale[4];
-          v[5] = a.pk.density ? (a.fields[4 * np + q] - a.pk.shift[5]) * a.pk.scale[5] : 0.f;
+          v[5] = 0.f;
           rp[i][0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
           rp[i][1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
           rp[i][2] = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
@@ -222,13 +222,10 @@ __global__ __launch_bounds__(64 * WV) void conv3x3_kernel(ConvArgs a) {
     const int passes = (MODE == CONV_FWD && a.zout) ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
       __syncthreads();
-      if (FUSE == FUSE_HEAD && tid < 132) {
-        // head weights into the free weight buffer: [4][32] (zero rows beyond nout), biases [4]
+      if (FUSE == FUSE_HEAD && tid < 99) {
+        // head weights into the free weight buffer: [3][32], then the 3 biases
         float* hw = (float*)sw;
-        const int o = tid < 128 ? tid >> 5 : tid - 128;
-        float v = 0.f;
-        if (o < a.nout) v = tid < 128 ? a.head_w[tid] : a.head_w[32 * a.nout + o];
-        hw[tid] = v;
+        hw[tid] = a.head_w[tid];
       }
 #pragma unroll
       for (int r = 0; r < RW; ++r) {
@@ -251,16 +248,15 @@ __global__ __launch_bounds__(64 * WV) void conv3x3_kernel(ConvArgs a) {
       }
       __syncthreads();
       if (FUSE == FUSE_HEAD) {
-        // 1x1 head over the Cout = 32 channels of each pixel (launched with NJ = 1 only)
-        // (weights from LDS, read at the same address by every lane; rows o >= nout are zero)
+        // 1x1 head (3 outputs) over the Cout = 32 channels of each pixel (launched with NJ = 1
+        // only; weights from LDS, read at the same address by every lane)
         const size_t np = (size_t)H * W;
-        const int no = a.nout;
         const float* hw = (const float*)sw;
-        double hs0 = 0.0, hs3 = 0.0;
+        double hs0 = 0.0;
         for (int pl = tid; pl < TP; pl += NT) {
-          float sacc[4];
+          float sacc[3];
 #pragma unroll
-          for (int o = 0; o < 4; ++o) sacc[o] = hw[128 + o];
+          for (int o = 0; o < 3; ++o) sacc[o] = hw[96 + o];
 #pragma unroll
           for (int k8 = 0; k8 < 4; ++k8) {
             const u32x4 v = *(const u32x4*)(so + pl * PSTR + 8 * k8);
@@ -269,33 +265,23 @@ __global__ __launch_bounds__(64 * WV) void conv3x3_kernel(ConvArgs a) {
               const float x = __uint_as_float(t & 1 ? (v[t / 2] & 0xFFFF0000u) : (v[t / 2] << 16));
               const int k = 8 * k8 + t;
 #pragma unroll
-              for (int o = 0; o < 4; ++o) sacc[o] += hw[32 * o + k] * x;
+              for (int o = 0; o < 3; ++o) sacc[o] += hw[32 * o + k] * x;
             }
           }
           const size_t p = (size_t)(y0 + pl / 32) * W + x0 + (pl & 31);
 #pragma unroll
-          for (int o = 0; o < 4; ++o)
-            if (o < no) a.head_out[o * np + p] = sacc[o];
+          for (int o = 0; o < 3; ++o) a.head_out[o * np + p] = sacc[o];
           hs0 += (double)sacc[0];
-          hs3 += (double)sacc[3];
         }
-        if (a.head_part) {  // per-workgroup sums for the conservation shifts of a surrogate step
-          __shared__ double hred[2][WV];
+        if (a.head_part) {  // per-workgroup sums for the conservation shift of a surrogate step
+          __shared__ double hred[WV];
           hs0 = wave_sum(hs0);
-          hs3 = wave_sum(hs3);
-          if (lane == 0) {
-            hred[0][wave] = hs0;
-            hred[1][wave] = hs3;
-          }
+          if (lane == 0) hred[wave] = hs0;
           __syncthreads();
           if (tid == 0) {
-            double s0 = 0.0, s3 = 0.0;
-            for (int w = 0; w < WV; ++w) {
-              s0 += hred[0][w];
-              s3 += hred[1][w];
-            }
+            double s0 = 0.0;
+            for (int w = 0; w < WV; ++w) s0 += hred[w];
             a.head_part[blockIdx.x] = s0;
-            a.head_part[gridDim.x + 1 + blockIdx.x] = s3;
           }
         }
         continue;
@@ -469,9 +455,8 @@ __global__ void reduce_blocks_f64_kernel(const double* __restrict__ part, int nb
   out[i] += (float)s;
 }
 
-// Input packing: fields [4 or 5][H][W] FP32 (phi, ux, uy, T, n) -> [H W][32] bfloat16, channels
-// (f - shift) * scale, channel 4 from a = (T - Tc) / Tc, channel 5 from n (zero without the
-// density), channels 6..31 zero.
+// Input packing: fields [4][H][W] FP32 (phi, ux, uy, T) -> [H W][32] bfloat16, channels
+// (f - shift) * scale, channel 4 from a = (T - Tc) / Tc, channels 5..31 zero.
 __global__ void pack_input_kernel(const float* __restrict__ f, size_t npix, PackArgs pa,
                                   bf16_t* __restrict__ x) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,7 +465,7 @@ __global__ void pack_input_kernel(const float* __restrict__ f, size_t npix, Pack
 #pragma unroll
   for (int c = 0; c < 4; ++c) v[c] = (f[c * npix + p] - pa.shift[c]) * pa.scale[c];
   v[4] = ((f[3 * npix + p] - pa.Tc) / pa.Tc - pa.shift[4]) * pa.scale[4];
-  v[5] = pa.density ? (f[4 * npix + p] - pa.shift[5]) * pa.scale[5] : 0.f;
+  v[5] = 0.f;
   u32x4 w0;
   w0[0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
   w0[1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
@@ -509,7 +494,6 @@ __global__ void field_grad_kernel(const bf16_t* __restrict__ gx, size_t npix, Pa
   g[npix + p] = v[1] * pa.scale[1];
   g[2 * npix + p] = v[2] * pa.scale[2];
   g[3 * npix + p] = v[3] * pa.scale[3] + v[4] * (pa.scale[4] / pa.Tc);
-  if (pa.density) g[4 * npix + p] = v[5] * pa.scale[5];
 }
 
 // 2x2 average pool: in [H][W] (pixel stride in_ld) -> out [H/2][W/2][C]; one thread per output
@@ -752,17 +736,16 @@ __global__ void adam_kernel(float* __restrict__ th, float* __restrict__ m, float
   th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Training target: t[c][p] = (later - earlier) / out_scale[c] for the output channels c < nout,
-// taken from the field planes phi, u_x, u_y and (c = 3) n.
+// Training target: t[c][p] = (later - earlier) / out_scale[c] for the output channels phi, u_x,
+// u_y (the first three field planes).
 __global__ void make_target_kernel(const float* __restrict__ e, const float* __restrict__ l,
-                                   int nout, size_t npix, float s0, float s1, float s2, float s3,
+                                   size_t npix, float s0, float s1, float s2,
                                    float* __restrict__ t) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)nout * npix) return;
+  if (i >= 3 * npix) return;
   const int c = (int)(i / npix);
-  const size_t src = c == 3 ? i + npix : i;
-  const float s = c == 0 ? s0 : (c == 1 ? s1 : (c == 2 ? s2 : s3));
-  t[i] = (l[src] - e[src]) / s;
+  const float s = c == 0 ? s0 : (c == 1 ? s1 : s2);
+  t[i] = (l[i] - e[i]) / s;
 }
 
 // Per-block FP64 sums of one FP32 plane (an increment in units of its output scale).
@@ -777,7 +760,7 @@ __global__ __launch_bounds__(256) void sum_f32_kernel(const float* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
 }
 
-// Mean of the per-block sums (phi increment, density increment or clamp excess): fixed-order tree
+// Mean of the per-block sums (phi increment or clamp excess): fixed-order tree
 // over the blocks (one workgroup), written to part[nblk].
 __global__ __launch_bounds__(256) void mean_kernel(double* __restrict__ part, int nblk, size_t npix) {
   __shared__ double sm[256];
@@ -792,19 +775,16 @@ __global__ __launch_bounds__(256) void mean_kernel(double* __restrict__ part, in
   if (threadIdx.x == 0) part[nblk] = sm[0] / (double)npix;
 }
 
-// One surrogate step applied in place: f[c] += out[c] s_c for phi, u_x, u_y and (nout = 4) n, with
-// phi and n shifted by the mean of their increments so that their sums are unchanged.
-__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, int nout,
-                             size_t npix, float s0, float s1, float s2, float s3,
-                             const double* __restrict__ mean_phi,
-                             const double* __restrict__ mean_n) {
+// One surrogate step applied in place: f[c] += out[c] s_c for phi, u_x, u_y, with phi shifted by
+// the mean of its increment so that its sum is unchanged.
+__global__ void apply_kernel(float* __restrict__ f, const float* __restrict__ out, size_t npix,
+                             float s0, float s1, float s2, const double* __restrict__ mean_phi) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   const float mu = (float)*mean_phi;
   f[p] += (out[p] - mu) * s0;
   f[npix + p] += out[npix + p] * s1;
   f[2 * npix + p] += out[2 * npix + p] * s2;
-  if (nout > 3) f[4 * npix + p] += (out[3 * npix + p] - (float)*mean_n) * s3;
 }
 
 // Order-parameter limiter of a rollout.  absmax: per-block max |phi| into part, then the block
@@ -1068,26 +1048,20 @@ hipError_t launch_adam(float* th, float* m, float* v, const float* g, size_t n, 
                      c2, gscale);
   return hipGetLastError();
 }
-hipError_t launch_make_target(const float* e, const float* l, int nout, size_t npix, const float* s,
+hipError_t launch_make_target(const float* e, const float* l, size_t npix, const float* s,
                               float* t, hipStream_t st) {
-  hipLaunchKernelGGL(make_target_kernel, nblocks(nout * npix, 256), 256, 0, st, e, l, nout, npix,
-                     s[0], s[1], s[2], nout > 3 ? s[3] : 1.f, t);
+  hipLaunchKernelGGL(make_target_kernel, nblocks(3 * npix, 256), 256, 0, st, e, l, npix, s[0], s[1],
+                     s[2], t);
   return hipGetLastError();
 }
-hipError_t launch_apply(float* f, const float* out, int nout, size_t npix, const float* s,
-                        double* part, int parts, hipStream_t st) {
+hipError_t launch_apply(float* f, const float* out, size_t npix, const float* s, double* part,
+                        int parts, hipStream_t st) {
   const int nb = (int)((npix + 255) / 256);
-  const int np = parts > 0 ? parts : nb;  // partial sums per plane
+  const int np = parts > 0 ? parts : nb;  // partial sums of the phi increment
   if (parts <= 0) hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out, npix, part);
   hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part, np, npix);
-  double* part_n = part + np + 1;
-  if (nout > 3) {
-    if (parts <= 0) hipLaunchKernelGGL(sum_f32_kernel, nb, 256, 0, st, out + 3 * npix, npix, part_n);
-    hipLaunchKernelGGL(mean_kernel, 1, 256, 0, st, part_n, np, npix);
-  }
-  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, nout, npix, s[0], s[1], s[2],
-                     nout > 3 ? s[3] : 0.f, (const double*)(part + np),
-                     (const double*)(part_n + np));
+  hipLaunchKernelGGL(apply_kernel, nb, 256, 0, st, f, out, npix, s[0], s[1], s[2],
+                     (const double*)(part + np));
   return hipGetLastError();
 }
 

@@ -16,9 +16,9 @@ SURROGATE_EXPORTS = ("lsn_param_count", "lsn_workspace_bytes", "lsn_create", "ls
 
 class lsn_config(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("levels", C.c_int32),
-                ("base_width", C.c_int32), ("training", C.c_int32), ("with_density", C.c_int32),
-                ("Tc", C.c_float), ("in_shift", C.c_float * 6), ("in_scale", C.c_float * 6),
-                ("out_scale", C.c_float * 4)]
+                ("base_width", C.c_int32), ("training", C.c_int32),
+                ("Tc", C.c_float), ("in_shift", C.c_float * 5), ("in_scale", C.c_float * 5),
+                ("out_scale", C.c_float * 3)]
 
 
 _bound = None
@@ -57,24 +57,21 @@ def lib():
 
 
 def make_config(height, width, levels=4, base_width=32, training=False, Tc=1.0,
-                in_shift=None, in_scale=None, out_scale=None, with_density=False) -> lsn_config:
-    """Normalisation tuples have 5 (6 with the density) inputs and 3 (4) outputs; omitted ones
-    are the identity."""
-    d = int(bool(with_density))
-    in_shift = tuple(in_shift) if in_shift is not None else (0.0,) * (5 + d)
-    in_scale = tuple(in_scale) if in_scale is not None else (1.0,) * (5 + d)
-    out_scale = tuple(out_scale) if out_scale is not None else (1.0,) * (3 + d)
-    if len(in_shift) != 5 + d or len(in_scale) != 5 + d or len(out_scale) != 3 + d:
-        raise ValueError("normalisation of 5 + with_density inputs and 3 + with_density outputs")
+                in_shift=None, in_scale=None, out_scale=None) -> lsn_config:
+    """Normalisation tuples have 5 inputs and 3 outputs; omitted ones are the identity."""
+    in_shift = tuple(in_shift) if in_shift is not None else (0.0,) * 5
+    in_scale = tuple(in_scale) if in_scale is not None else (1.0,) * 5
+    out_scale = tuple(out_scale) if out_scale is not None else (1.0,) * 3
+    if len(in_shift) != 5 or len(in_scale) != 5 or len(out_scale) != 3:
+        raise ValueError("normalisation of 5 inputs and 3 outputs")
     c = lsn_config()
     c.height, c.width, c.levels, c.base_width = int(height), int(width), int(levels), int(base_width)
     c.training = int(bool(training))
-    c.with_density = d
     c.Tc = float(Tc)
-    for i in range(5 + d):
+    for i in range(5):
         c.in_shift[i] = float(in_shift[i])
         c.in_scale[i] = float(in_scale[i])
-    for i in range(3 + d):
+    for i in range(3):
         c.out_scale[i] = float(out_scale[i])
     return c
 
@@ -93,8 +90,8 @@ def param_count(**cfg) -> int:
 
 class Surrogate:
     """U-Net surrogate on one GPU.  Fields are planar FP32 device tensors [NF, H, W] (phi, u_x,
-    u_y, T and, with the density, n); outputs and targets are [NOUT, H, W] (increments of phi,
-    u_x, u_y and n).  NF = 4 + with_density, NOUT = 3 + with_density."""
+    u_y, T); outputs and targets are [NOUT, H, W] (increments of phi, u_x, u_y).  NF = 4,
+    NOUT = 3."""
 
     def __init__(self, height, width, device="cuda:0", stream=None, **cfg):
         import torch
@@ -102,7 +99,7 @@ class Surrogate:
         self.device = torch.device(device)
         self.H, self.W = int(height), int(width)
         self.cfg = make_config(height, width, **cfg)
-        self.NF, self.NOUT = 4 + self.cfg.with_density, 3 + self.cfg.with_density
+        self.NF, self.NOUT = 4, 3
         n = C.c_size_t()
         _check(L.lsn_workspace_bytes(C.byref(self.cfg), C.byref(n)))
         with torch.cuda.device(self.device):

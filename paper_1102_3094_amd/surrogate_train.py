@@ -4,7 +4,7 @@ lam_surrogate.h); torch holds the snapshot tensors on the device and does the el
 the two-step gradient.
 
 Workflow:
-  1. snapshots(): plain solver runs; fields (phi, u_x, u_y, T and optionally the density n)
+  1. snapshots(): plain solver runs; fields (phi, u_x, u_y, T)
      every `every` steps from t_start.
   2. normalisation(): input shifts/scales and output scales from the snapshot statistics.
   3. train(): Adam on random consecutive snapshot pairs (target = normalised increment), or on
@@ -26,13 +26,12 @@ from . import Ensemble, Sim
 from .surrogate import Surrogate
 
 
-def snapshots(members, phis, t_start, count, every=100, device="cuda:0", density=False):
-    """[M, count + 1, NF, H, W] FP32 device tensor of fields at t_start + k * every (NF = 4, or 5
-    with the density plane)."""
+def snapshots(members, phis, t_start, count, every=100, device="cuda:0"):
+    """[M, count + 1, 4, H, W] FP32 device tensor of the fields (phi, u_x, u_y, T) at
+    t_start + k * every."""
     import torch
     H, W = members[0]["ny"], members[0]["nx"]
-    nf = 5 if density else 4
-    out = torch.empty((len(members), count + 1, nf, H, W), dtype=torch.float32, device=device)
+    out = torch.empty((len(members), count + 1, 4, H, W), dtype=torch.float32, device=device)
     for m, (p, phi) in enumerate(zip(members, phis)):
         sim = Sim(p, device=device).init_fields(torch.tensor(phi, dtype=torch.float32))
         sim.step(t_start)
@@ -49,20 +48,14 @@ def snapshots(members, phis, t_start, count, every=100, device="cuda:0", density
 def normalisation(snaps, Tc, u_ref=0.01, a_ref=0.25):
     """phi scaled to unit spread, velocities by a reference speed u_ref (a Mach-number scale:
     the spread of u is dominated by the few active runs), T - Tc and a by a reference reduced
-    temperature a_ref (T may be uniform in every run); with a density plane, n - 1 scaled to unit
-    spread; outputs scaled by the standard deviation of each increment over the pairs."""
-    density = snaps.shape[2] == 5
+    temperature a_ref (T may be uniform in every run); outputs scaled by the standard deviation
+    of each increment over the pairs."""
     x = snaps[:, :-1]
-    planes = (0, 1, 2, 4) if density else (0, 1, 2)
     sd = lambda t: max(float(t.double().std()), 1e-12)  # noqa: E731
     in_scale = (1.0 / sd(x[:, :, 0]), 1.0 / u_ref, 1.0 / u_ref, 1.0 / (a_ref * Tc), 1.0 / a_ref)
     in_shift = (0.0, 0.0, 0.0, Tc, 0.0)
-    if density:
-        in_scale += (1.0 / sd(x[:, :, 4]),)
-        in_shift += (1.0,)
-    out_scale = tuple(sd(snaps[:, 1:, c] - snaps[:, :-1, c]) for c in planes)
-    return dict(Tc=Tc, in_shift=in_shift, in_scale=in_scale, out_scale=out_scale,
-                with_density=density)
+    out_scale = tuple(sd(snaps[:, 1:, c] - snaps[:, :-1, c]) for c in (0, 1, 2))
+    return dict(Tc=Tc, in_shift=in_shift, in_scale=in_scale, out_scale=out_scale)
 
 
 def mirror(f):

@@ -40,7 +40,7 @@ def test_config_layout():
 #include <stdio.h>
 #include <stddef.h>
 #include "lam_surrogate.h"
-int main(){printf("%zu %zu %zu %zu %zu\n", sizeof(lsn_config), offsetof(lsn_config, with_density),
+int main(){printf("%zu %zu %zu %zu %zu\n", sizeof(lsn_config), offsetof(lsn_config, training),
 offsetof(lsn_config, Tc), offsetof(lsn_config, in_scale), offsetof(lsn_config, out_scale));
 return 0;}
 '''
@@ -49,7 +49,7 @@ return 0;}
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", os.path.join(d, "t"),
                         os.path.join(d, "t.c")], check=True)
         out = subprocess.run([os.path.join(d, "t")], capture_output=True, text=True).stdout.split()
-    got = [C.sizeof(sg.lsn_config), sg.lsn_config.with_density.offset, sg.lsn_config.Tc.offset,
+    got = [C.sizeof(sg.lsn_config), sg.lsn_config.training.offset, sg.lsn_config.Tc.offset,
            sg.lsn_config.in_scale.offset, sg.lsn_config.out_scale.offset]
     assert [int(v) for v in out] == got
 
@@ -58,24 +58,17 @@ return 0;}
 def test_param_count_matches_oracle_layers(L, levels, base):
     widths = tuple(base << l for l in range(levels))
     assert sg.param_count(height=64, width=512, levels=levels, base_width=base) == U.param_count(widths)
-    assert (sg.param_count(height=64, width=512, levels=levels, base_width=base, with_density=True)
-            == U.param_count(widths, 6, 4))
 
 
 @pytest.mark.parametrize("bad", [dict(levels=0), dict(levels=6), dict(base_width=48),
                                  dict(height=60), dict(width=200), dict(Tc=0.0),
                                  dict(out_scale=(1.0, 0.0, 1.0)),
-                                 dict(with_density=True, out_scale=(1.0, 1.0, 1.0, 0.0)),
-                                 dict(with_density=True, in_scale=(1.0,) * 5 + (float("inf"),)),
-                                 dict(with_density=2)])
+                                 dict(in_scale=(1.0,) * 4 + (float("inf"),)),
+                                 dict(in_shift=(float("nan"),) + (0.0,) * 4)])
 def test_bad_config_rejected(L, bad):
     cfg = dict(height=64, width=256, levels=4, base_width=32)
-    bad = dict(bad)
-    wd = bad.pop("with_density") if bad.get("with_density") == 2 else None
     cfg.update(bad)
     c = sg.make_config(**cfg)
-    if wd is not None:
-        c.with_density = wd
     n = C.c_size_t()
     assert L.lsn_workspace_bytes(C.byref(c), C.byref(n)) == lam.LAM_EINVAL
     assert L.lsn_last_error(None)

@@ -276,146 +276,6 @@ def test_rollout_graph_and_direct_paths_agree(gpu):
     assert torch.equal(results[0], sim.fields()["phi"])
 
 
-# --- the variant with the density: a sixth input and a fourth output channel ----------------
-
-CFG_N = dict(Tc=1.0, with_density=True, in_shift=(0.0, 0.0, 0.0, 1.0, 0.0, 1.0),
-             in_scale=(1.0, 20.0, 20.0, 2.0, 2.0, 200.0), out_scale=(0.05, 0.005, 0.005, 0.001))
-
-
-def fields_n(H, W, seed=11):
-    f = np.empty((5, H, W))
-    f[:4] = fields(H, W, seed)
-    u = S.uniform01(seed + 1, H * W).reshape(H, W)
-    f[4] = 1.0 + 0.005 * (2 * u - 1) + 0.002 * np.cos(2 * np.pi * np.arange(W) / W)[None, :]
-    return f.astype(np.float32).astype(np.float64)
-
-
-def packed_n(f, cfg=CFG_N):
-    x = np.empty(f.shape[1:] + (6,))
-    x[..., :5] = packed(f[:4], cfg)
-    x[..., 5] = (f[4] - cfg["in_shift"][5]) * cfg["in_scale"][5]
-    return x
-
-
-def params_n(widths, seed=4):
-    shapes = [(ci, co) for _, ci, co in U.layers(widths, in_ch=6)]
-    th = S.he_uniform(seed, shapes, head=(widths[0], 4))
-    r = S.uniform01(seed + 100, 4 * widths[0] + 4)
-    th[-(4 * widths[0] + 4):] = 0.3 * (2 * r - 1)
-    return th.astype(np.float32).astype(np.float64)
-
-
-def make_n(H, W, levels=4, base=32, training=False, stream=None):
-    from paper_1102_3094_amd.surrogate import Surrogate
-    return Surrogate(H, W, levels=levels, base_width=base, training=training, stream=stream, **CFG_N)
-
-
-@pytest.mark.parametrize("H,W,levels,base,training", [(64, 256, 4, 32, False), (32, 128, 3, 64, False),
-                                                      (64, 256, 4, 32, True)])
-def test_density_forward_parity(gpu, H, W, levels, base, training):
-    widths = tuple(base << l for l in range(levels))
-    th = params_n(widths)
-    f = fields_n(H, W)
-    net = make_n(H, W, levels, base, training).set_params(dev(th))
-    out = net.forward(dev(f)).cpu().double().numpy()
-    ref, _ = U.forward(th, packed_n(f), widths, q=True, out_ch=4)
-    ref = np.moveaxis(ref, 2, 0)
-    err = rel_l2(out, ref)
-    print(f"density variant: forward rel-L2 {err:.2e}; channel n {rel_l2(out[3], ref[3]):.2e}")
-    assert out.shape == (4, H, W) and np.abs(ref[3]).max() > 0.1
-    assert err <= 1e-2 and rel_l2(out[3], ref[3]) <= 1e-2
-    # the density input matters: a changed n plane changes the output
-    g = f.copy()
-    g[4] = 1.0
-    assert rel_l2(net.forward(dev(g)).cpu().double().numpy(), out) > 1e-3
-
-
-def test_density_gradient_parity(gpu):
-    H, W, widths = 64, 256, (32, 64, 128, 256)
-    th = params_n(widths)
-    f = fields_n(H, W)
-    tgt = 0.5 * (2 * S.uniform01(22, 4 * H * W).reshape(4, H, W) - 1)
-    net = make_n(H, W, training=True).set_params(dev(th))
-    net.zero_grad()
-    loss = net.loss_backward(dev(f), dev(tgt))
-    g = net.grads().cpu().double().numpy()
-    out, cache = U.forward(th, packed_n(f), widths, q=True, out_ch=4)
-    ref_loss = U.loss(out, np.moveaxis(tgt, 0, 2))
-    ref, _ = U.backward(th, cache, out, np.moveaxis(tgt, 0, 2), widths, q=True)
-    print(f"density variant: loss {loss:.6e} vs {ref_loss:.6e}; gradient rel-L2 {rel_l2(g, ref):.2e}")
-    assert g.size == U.param_count(widths, 6, 4)
-    assert loss == pytest.approx(ref_loss, rel=2e-3)
-    assert rel_l2(g, ref) <= 3e-2
-    Pg, Pr = U.split(g, widths, in_ch=6, out_ch=4), U.split(ref, widths, in_ch=6, out_ch=4)
-    for name in Pr:
-        for a, b in zip(Pg[name], Pr[name]):
-            assert rel_l2(a, b) <= 6e-2, name
-
-
-def test_density_advance_and_target(gpu):
-    H, W, widths = 64, 256, (32, 64, 128, 256)
-    net = make_n(H, W).set_params(dev(params_n(widths)))
-    f = dev(fields_n(H, W))
-    out = net.forward(f).double()
-    g = f.clone()
-    net.advance(g)
-    torch.cuda.synchronize()
-    s = torch.tensor(CFG_N["out_scale"], dtype=torch.float64, device="cuda")[:, None, None]
-    inc = out * s
-    inc[0] -= inc[0].mean()
-    inc[3] -= inc[3].mean()
-    assert torch.equal(g[3], f[3])
-    assert torch.allclose(g[:3].double() - f[:3].double(), inc[:3], atol=2e-6)
-    assert torch.allclose(g[4].double() - f[4].double(), inc[3], atol=2e-6)
-    assert abs(g[0].double().sum() - f[0].double().sum()) < 1e-6 * H * W
-    assert abs(g[4].double().sum() - f[4].double().sum()) < 1e-6 * H * W
-    t = net.make_target(f, g).double()
-    assert t.shape == (4, H, W)
-    assert torch.allclose(t[:3] * s[:3], g[:3].double() - f[:3].double(), atol=1e-6)
-    assert torch.allclose(t[3] * s[3], g[4].double() - f[4].double(), atol=1e-6)
-
-
-def test_density_fused_equals_unfused(gpu):
-    H, W, widths = 64, 256, (32, 64, 128, 256)
-    th = dev(params_n(widths))
-    f = dev(fields_n(H, W))
-    a = make_n(H, W).set_params(th).forward(f)
-    b = make_n(H, W, training=True).set_params(th).forward(f)
-    assert torch.equal(a, b)
-
-
-def test_density_rollout_reanchors_with_predicted_density(gpu):
-    """The rollout of the density variant re-anchors the solver on the predicted n: it equals the
-    same sequence of single calls with the n plane passed to set_fields."""
-    H, W, widths = 64, 256, (32, 64, 128, 256)
-    th = params_n(widths)
-    th[-(4 * 32 + 4):] *= 0.05
-    p = S.model_params("c1_64sq", nx=W, ny=H, Tw=0.95, tau=1.5, xi=-1.0)
-    phi0 = torch.tensor(S.phi0((H, W), seed=5), dtype=torch.float32)
-    state = gpu.Sim(p).init_fields(phi0).step(200).get_state()
-    st = torch.cuda.Stream()
-    net = make_n(H, W, stream=st).set_params(dev(th)).set_limiter(0)
-    sim = gpu.Sim(p, stream=st).set_state(state)
-    scratch = torch.empty((5, H, W), dtype=torch.float32, device="cuda")
-    net.rollout(sim, scratch, cycles=2, calls=3, steps_per_call=100, anchor_steps=20)
-    st.synchronize()
-    got = sim.fields()
-    net2 = make_n(H, W).set_params(dev(th))
-    ref = gpu.Sim(p).set_state(state)
-    buf = torch.empty((5, H, W), dtype=torch.float32, device="cuda")
-    for _ in range(2):
-        ref.fields_into(buf)
-        for _ in range(3):
-            net2.advance(buf)
-            ref.advance_temperature(100)
-        ref.set_fields(buf[0], buf[1:3], buf[4])
-        ref.step(20)
-    torch.cuda.synchronize()
-    want = ref.fields()
-    assert torch.equal(got["phi"], want["phi"]) and torch.equal(got["n"], want["n"])
-    assert not sim.observables()["nonfinite"]
-
-
 def test_rollout_limiter_clamps_and_conserves(gpu):
     """With the limiter on, phi handed to the solver at re-anchoring is clamped to 1.05 x the
     max |phi| at the start of the call, with the excess spread evenly (sum phi unchanged): the
@@ -503,31 +363,27 @@ def test_full_size_gradient_parity(gpu):
 
 def field_grad_ref(gx, cfg):
     """Gradient with respect to the planar fields from the oracle's gradient with respect to the
-    packed input: the adjoint of packed() / packed_n() (T enters channels 3 and 4)."""
+    packed input: the adjoint of packed() (T enters channels 3 and 4)."""
     sc = cfg["in_scale"]
-    nf = 5 if gx.shape[2] == 6 else 4
-    g = np.empty((nf,) + gx.shape[:2])
+    g = np.empty((4,) + gx.shape[:2])
     for c in range(3):
         g[c] = gx[..., c] * sc[c]
     g[3] = gx[..., 3] * sc[3] + gx[..., 4] * sc[4] / cfg["Tc"]
-    if nf == 5:
-        g[4] = gx[..., 5] * sc[5]
     return g
 
 
-@pytest.mark.parametrize("density", [False, True])
-def test_chained_backward_parity(gpu, density):
+def test_chained_backward_parity(gpu):
     """lsn_loss_backward_ex: an extra output gradient E (the chain rule through a later surrogate
     step) and the gradient with respect to the input fields, against the oracle's gradient of
     loss + sum(E * out)."""
     H, W, widths = 64, 256, (32, 64, 128, 256)
-    cfg, pk = (CFG_N, packed_n) if density else (CFG, packed)
-    nout = 4 if density else 3
-    th = params_n(widths) if density else params(widths)
-    f = fields_n(H, W) if density else fields(H, W)
+    cfg, pk = CFG, packed
+    nout = 3
+    th = params(widths)
+    f = fields(H, W)
     tgt = 0.5 * (2 * S.uniform01(23, nout * H * W).reshape(nout, H, W) - 1)
     E = 4e-5 * (2 * S.uniform01(24, nout * H * W).reshape(nout, H, W) - 1)
-    net = (make_n(H, W, training=True) if density else make(gpu, H, W, training=True)).set_params(dev(th))
+    net = make(gpu, H, W, training=True).set_params(dev(th))
     fg = torch.full((f.shape[0], H, W), float("nan"), dtype=torch.float32, device="cuda")
     net.zero_grad()
     loss = net.loss_backward(dev(f), dev(tgt), out_grad=dev(E), field_grad=fg)
@@ -539,7 +395,7 @@ def test_chained_backward_parity(gpu, density):
                          g_extra=np.moveaxis(E, 0, 2))
     ref_f = field_grad_ref(gx, cfg)
     e_p, e_f = rel_l2(g, ref), rel_l2(fgd, ref_f)
-    print(f"density={density}: parameter gradient rel-L2 {e_p:.2e}, field gradient rel-L2 {e_f:.2e}")
+    print(f"parameter gradient rel-L2 {e_p:.2e}, field gradient rel-L2 {e_f:.2e}")
     assert loss == pytest.approx(U.loss(out, np.moveaxis(tgt, 0, 2)), rel=2e-3)
     assert np.isfinite(fgd).all() and np.abs(ref_f).max() > 0
     assert e_p <= 3e-2 and e_f <= 3e-2
@@ -555,31 +411,30 @@ def test_chained_backward_parity(gpu, density):
     _, gx64 = U.backward(th, c64, o64, np.moveaxis(tgt, 0, 2), widths, g_extra=np.moveaxis(E, 0, 2))
     r64 = field_grad_ref(gx64, cfg)
     h = 1e-5
-    for (c, yy, xx) in [(0, 0, 5), (3, 30, 100)] + ([(4, 10, 7)] if density else []):
+    for (c, yy, xx) in [(0, 0, 5), (3, 30, 100)]:
         fp, fm = f.copy(), f.copy()
         fp[c, yy, xx] += h
         fm[c, yy, xx] -= h
         assert (J(fp) - J(fm)) / (2 * h) == pytest.approx(r64[c, yy, xx], rel=1e-4, abs=1e-12), (c, yy, xx)
 
 
-@pytest.mark.parametrize("density", [False, True])
-def test_two_step_training_gradient(gpu, density):
+def test_two_step_training_gradient(gpu):
     """The training driver's two-step objective (two_step_backward: advance, second pass, chained
     backward through lsn_loss_backward_ex) against the oracle's composition of the same steps."""
     from paper_1102_3094_amd.surrogate_train import two_step_backward
     from tests._two_step import two_step
     H, W, widths = 64, 256, (32, 64, 128, 256)
-    cfg, pk = (CFG_N, packed_n) if density else (CFG, packed)
-    th = params_n(widths) if density else params(widths)
-    a = fields_n(H, W) if density else fields(H, W)
+    cfg, pk = CFG, packed
+    th = params(widths)
+    a = fields(H, W)
     nf = a.shape[0]
-    amp = np.array([0.03, 0.003, 0.003, 0.0, 0.001][:nf])[:, None, None]
+    amp = np.array([0.03, 0.003, 0.003, 0.0])[:, None, None]
     b = a + amp * (2 * S.uniform01(31, nf * H * W).reshape(a.shape) - 1)
     b[3] = a[3] + 0.01
     c = b + amp * (2 * S.uniform01(32, nf * H * W).reshape(a.shape) - 1)
     c[3] = b[3] + 0.01
     b, c = (v.astype(np.float32).astype(np.float64) for v in (b, c))
-    net = (make_n(H, W, training=True) if density else make(gpu, H, W, training=True)).set_params(dev(th))
+    net = make(gpu, H, W, training=True).set_params(dev(th))
     fg = torch.empty((nf, H, W), dtype=torch.float32, device="cuda")
     net.zero_grad()
     l1, l2 = two_step_backward(net, dev(a), dev(b), dev(c), fg, want_loss=True)
@@ -587,6 +442,6 @@ def test_two_step_training_gradient(gpu, density):
     r1, r2, ref = two_step(th, a, b, c, widths, pk, lambda gx: field_grad_ref(gx, cfg), cfg["out_scale"],
                            q=True)
     err = rel_l2(g, ref)
-    print(f"density={density}: L1 {l1:.5e} vs {r1:.5e}, L2 {l2:.5e} vs {r2:.5e}, gradient rel-L2 {err:.2e}")
+    print(f"L1 {l1:.5e} vs {r1:.5e}, L2 {l2:.5e} vs {r2:.5e}, gradient rel-L2 {err:.2e}")
     assert l1 == pytest.approx(r1, rel=2e-3) and l2 == pytest.approx(r2, rel=1e-2)
     assert err <= 3e-2

@@ -194,8 +194,9 @@ def test_he_uniform_bounds():
     assert np.all(th[-(32 * 3 + 3):] == 0)
 
 
-def test_gradient_finite_differences_density_variant():
-    """Six input and four output channels (the variant with the density)."""
+def test_gradient_finite_differences_other_channel_counts():
+    """Six input and four output channels: the oracle's network takes its channel counts as
+    parameters, and its gradient holds for counts other than the product's five and three."""
     widths = (4, 6)
     shapes = [(ci, co) for _, ci, co in U.layers(widths, in_ch=6)]
     r = rng(9)
