@@ -17,6 +17,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lam_dev.hpp"
@@ -24,8 +25,8 @@
 namespace lam {
 
 constexpr int BX = 64, BY = 8, NT3 = BX * BY;
-// z slices per workgroup (measured at 256^3: 16 for lb3d, whose pipeline prologue is short
-// against its per-slice work, 64 for phi3d)
+// z slices per workgroup: 16 for lb3d (measured at 256^3; its pipeline prologue is short against
+// its per-slice work); for phi3d the host picks up to ZPH (KParams::zch_phi)
 constexpr int ZLB = 16, ZPH = 64;
 enum { MODE3_STEP = 0, MODE3_OBS = 1, MODE3_FIELDS = 2 };
 
@@ -43,9 +44,8 @@ struct Tile3 {
   int x0, y0, z0, z1;
 };
 
-template <int ZCH>
-__device__ __forceinline__ Tile3 tile3(const KParams& P) {
-  const int nbx = (P.nx + BX - 1) / BX, nby = (P.ny + BY - 1) / BY, nbz = (P.nz + ZCH - 1) / ZCH;
+__device__ __forceinline__ Tile3 tile3(const KParams& P, int zch) {
+  const int nbx = (P.nx + BX - 1) / BX, nby = (P.ny + BY - 1) / BY, nbz = (P.nz + zch - 1) / zch;
   // x fastest, then y, then z: the tiles an XCD runs together are xy neighbours, so the halo
   // lines they share (x +- 1 pulls cross a cache line) are fetched from HBM once into that L2
   const int t = xcd_tile(blockIdx.x, nbx * nby * nbz);
@@ -53,8 +53,8 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P) {
   Tile3 T;
   T.x0 = bx * BX;
   T.y0 = by * BY;
-  T.z0 = bz * ZCH;
-  T.z1 = min(T.z0 + ZCH, P.nz);
+  T.z0 = bz * zch;
+  T.z1 = min(T.z0 + zch, P.nz);
   return T;
 }
 
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   const uint32_t plane = (uint32_t)nx * ny;
   const size_t N = (size_t)plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
-  const Tile3 T = tile3<ZLB>(P);
+  const Tile3 T = tile3(P, ZLB);
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
 
@@ -446,17 +446,19 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 // ------------------------------------------------------------------------------------------------
 // Two slices per iteration.  psi ring of 8: the stores of slices s + 2, s + 3 must not overwrite
 // slices s - 4 .. s - 1, which slower threads may still read for the output slices of the previous
-// iteration (no barrier between them).  mu and the fluxes are written after the iteration's first
-// barrier and read for outputs s - 3, s - 2 (slices s - 4 .. s - 1): rings of 4.  psi is the same
-// for the whole launch (one Euler sub-step), so the ring holds the fluxes psi u (formed once per
-// cell when the velocity is staged) rather than u: the advection reads 30 instead of 60 values.
-// Ring slots are the slice index relative to z0 - 3 masked to the ring length.
-// The rings read most per output (fluxes, mu) come first, so that their reads fit the 16-bit
-// immediate offset of the LDS instructions.
+// iteration (no barrier between them).  mu and the fluxes of slices s - 2, s - 1 are written after
+// the iteration's first barrier and read only after its second, by the same iteration: every
+// thread adds what one slice contributes to the outputs of slices s - 1, s and s + 1 into
+// registers (the 7-point Laplacian and the isotropic divergence split by z offset), so their
+// rings hold just the two slices of the iteration.  psi is the same for the whole launch (one
+// Euler sub-step), so the ring holds the fluxes psi u (formed once per cell when the velocity is
+// staged) rather than u.  Ring slots are the slice index relative to z0 - 3 masked to the ring
+// length.  The rings read most per output (fluxes, mu) come first, so that their reads fit the
+// 16-bit immediate offset of the LDS instructions.
 template <bool HYDRO>
 struct Phi3dSmem {
-  float u[HYDRO ? 4 : 1][3][C1];  // fluxes psi u_x, psi u_y, psi u_z
-  float mu[4][C1];
+  float u[HYDRO ? 2 : 1][3][C1];  // fluxes psi u_x, psi u_y, psi u_z
+  float mu[2][C1];
   float psi[8][C3];
   float a[ZPH + 6];  // (T - Tc)/Tc of the chunk's slices, from slice z0 - 3
   int rowoff[BY + 6], colx[BX + 6];
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
   const uint32_t plane = (uint32_t)nx * ny;
   const size_t N = (size_t)plane * nz;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
-  const Tile3 T = tile3<ZPH>(P);
+  const Tile3 T = tile3(P, P.zch_phi);
   const int x = T.x0 + tx, y = T.y0 + ty;
   const bool in_xy = x < nx && y < ny;
 
@@ -571,6 +573,8 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
 
   // Iteration k (even): store psi slices k, k + 1 (relative to z0 - 3) and the fluxes of slices
   // k - 2, k - 1, compute mu of slices k - 2, k - 1, write the output slices k - 3, k - 2.
+  // rb, rc: partial R of slices k - 3 and k - 2 (from the slices before k - 2).
+  float rb = 0.f, rc = 0.f;
   auto pair = [&](const int k) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -579,10 +583,10 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
       if (tid < C3 - NT3) dst[tid + NT3] = pv[h][1];
     }
     __syncthreads();
-    if (HYDRO) {  // fluxes psi u of slices k - 2, k - 1 (xy halo 1; normal component odd)
+    if (HYDRO && k >= 4) {  // fluxes psi u of slices k - 2, k - 1 (xy halo 1; normal one odd)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        float* jd = S.u[(k - 2 + h) & 3][0];
+        float* jd = S.u[(k - 2 + h) & 1][0];
         const float* pp = S.psi[(k - 2 + h) & 7];
         const float ps = pp[pi];
         jd[oi] = ps * uv[h][0][0];
@@ -606,8 +610,8 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
       const float* q3 = S.psi[(k - 1) & 7];
       const float* q4 = S.psi[k & 7];
       const float* q5 = S.psi[(k + 1) & 7];
-      float* m0 = S.mu[(k - 2) & 3];
-      float* m1 = S.mu[(k - 1) & 3];
+      float* m0 = S.mu[(k - 2) & 1];
+      float* m1 = S.mu[(k - 1) & 1];
       m0[oi] = mu_at(P, a0, q0, q1, q2, q3, q4, pi);
       m1[oi] = mu_at(P, a1, q1, q2, q3, q4, q5, pi);
       if (has_h) {
@@ -616,41 +620,42 @@ __global__ __launch_bounds__(NT3) void phi3d_kernel(KParams P, const float* __re
       }
     }
     __syncthreads();
-    // output slices k - 3 + h read mu and the fluxes of slices k - 4 + h .. k - 2 + h
-    const float* mr[4];
-    const float* jr[4];
+    // Slices k - 2 + h in order: with R = Gamma lap mu - div(psi u), slice s adds `below` to
+    // R(s - 1) (completing it), `cen` to R(s) and `above` to R(s + 1).  The z +- 1 terms of the
+    // isotropic divergence are A +- B: A from the x and y fluxes of the xz and yz edges, B from
+    // the z fluxes of the z face and the edges.
+    if (k >= 4 && in_xy) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      mr[i] = S.mu[(k - 4 + i) & 3];
-      jr[i] = S.u[(k - 4 + i) & 3][0];
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = k - 3 + h, z = T.z0 - 3 + j;
-      if (z < T.z0 || z >= T.z1 || !in_xy) continue;
-      const float* mc = mr[h + 1];
-      const float* md = mr[h];
-      const float* mu_ = mr[h + 2];
-      // per-thread bases at the lowest cell read (row -1, column -1): constant offsets only
-      const float* mc0 = mc + oi - W1 - 1;
-      const float lapmu = ((mc0[W1 + 2] + mc0[W1]) + (mc0[2 * W1 + 1] + mc0[1])) +
-                          (mu_[oi] + md[oi]) - 6.f * mc0[W1 + 1];
-      float adv = 0.f;
-      if (HYDRO) {
-        const float* jc = jr[h + 1] + oi - W1 - 1;
-        const float* jd = jr[h] + oi - W1 - 1;
-        const float* ju = jr[h + 2] + oi - W1 - 1;
-        // div(psi u), isotropic first differences of the staged fluxes
-        auto flux = [&](int kk) {
-          return [&, kk](int dz, int dr, int dc) {
-            return (dz == 0 ? jc : (dz > 0 ? ju : jd))[kk * C1 + (dr + 1) * W1 + dc + 1];
-          };
-        };
-        adv = iso3_x(flux(0)) + iso3_y(flux(1)) + iso3_z(flux(2));
+      for (int h = 0; h < 2; ++h) {
+        // per-thread bases at the lowest cell read (row -1, column -1): constant offsets only
+        const float* m = S.mu[(k - 2 + h) & 1] + oi - W1 - 1;
+        const float mc = m[W1 + 1];
+        float cen = P.Gamma * (((m[W1 + 2] + m[W1]) + (m[2 * W1 + 1] + m[1])) - 6.f * mc);
+        float below = P.Gamma * mc, above = below;
+        if (HYDRO) {
+          const float* jb = S.u[(k - 2 + h) & 1][0] + oi - W1 - 1;
+          auto jx = [&](int dr, int dc) { return jb[(dr + 1) * W1 + dc + 1]; };
+          auto jy = [&](int dr, int dc) { return jb[C1 + (dr + 1) * W1 + dc + 1]; };
+          auto jz = [&](int dr, int dc) { return jb[2 * C1 + (dr + 1) * W1 + dc + 1]; };
+          const float d0 = (jx(0, 1) - jx(0, -1)) + (jy(1, 0) - jy(-1, 0));
+          const float de = ((jx(1, 1) - jx(1, -1)) + (jx(-1, 1) - jx(-1, -1))) +
+                           ((jy(1, 1) - jy(-1, 1)) + (jy(1, -1) - jy(-1, -1)));
+          const float A = (1.f / 12.f) * d0;
+          const float B = (1.f / 6.f) * jz(0, 0) +
+                          (1.f / 12.f) * ((jz(0, 1) + jz(0, -1)) + (jz(1, 0) + jz(-1, 0)));
+          cen -= (1.f / 6.f) * d0 + (1.f / 12.f) * de;
+          below -= A + B;
+          above -= A - B;
+        }
+        const int j = k - 3 + h, z = T.z0 - 3 + j;  // output slice s - 1
+        if (z >= T.z0 && z < T.z1) {
+          const float pc = S.psi[j & 7][pi];
+          *plane_at(psi_out, (uint32_t)z * plane + (uint32_t)(y * nx + x)) =
+              pc + P.h * (rb + below);
+        }
+        rb = rc + cen;
+        rc = above;
       }
-      const float pc = S.psi[j & 7][pi];
-      *plane_at(psi_out, (uint32_t)z * plane + (uint32_t)(y * nx + x)) =
-          pc + P.h * (-adv + P.Gamma * lapmu);
     }
   };
   for (int k = 0; k < K; k += 2) pair(k);
@@ -682,7 +687,17 @@ int blocks3d(const KParams& P) {
   return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + ZLB - 1) / ZLB);
 }
 static int blocks3d_phi(const KParams& P) {
-  return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + ZPH - 1) / ZPH);
+  return ((P.nx + BX - 1) / BX) * ((P.ny + BY - 1) / BY) * ((P.nz + P.zch_phi - 1) / P.zch_phi);
+}
+
+// z slices per phi3d workgroup: enough chunks for about three workgroups per compute unit of a
+// 256-unit part (the LDS allows three), each of 16 .. ZPH slices (the pipeline re-reads six
+// slices per chunk).  At 256^3 this gives six chunks of 43 slices (phi3d 116 -> 107 us against
+// four of 64).
+int phi3d_chunk(int nx, int ny, int nz) {
+  const int nxy = ((nx + BX - 1) / BX) * ((ny + BY - 1) / BY);
+  const int nbz = (768 + nxy - 1) / nxy;
+  return std::min(ZPH, std::max(std::min(16, nz), (nz + nbz - 1) / nbz));
 }
 
 template <typename K, typename... A>

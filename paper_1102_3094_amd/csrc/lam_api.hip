@@ -27,6 +27,7 @@ hipError_t launch_phi2d(const KParams& P, int ty, int nsub, const float* in, flo
                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // lam_3d.hip
 int blocks3d(const KParams& P);
+int phi3d_chunk(int nx, int ny, int nz);
 hipError_t launch_lb3d(const KParams& P, int mode, const void* gin, void* gout,
                        const float* phi, const float* Trow, float* u, float* n, double* partials,
                        hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
@@ -321,6 +322,7 @@ int lam_create(const lam_params* p, void* d_workspace, size_t bytes, void* hip_s
   k.n_T = p->xi > 0 ? s->nT : 0;
   k.r_T = p->xi > 0 ? (float)(p->xi / s->nT) : 0.f;
   k.half_pops = p->pop_storage == 1;
+  k.zch_phi = p->dim == 3 ? phi3d_chunk(p->nx, p->ny, p->nz) : 1;
   s->step = 0;
   s->initialised = false;
   *out = s;

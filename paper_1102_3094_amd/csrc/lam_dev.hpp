@@ -23,6 +23,7 @@ struct KParams {
   float r_T;            // xi / n_T
   int n_T;              // FTCS sub-steps (0: temperature frozen)
   int half_pops;        // populations stored as FP16 deviations
+  int zch_phi;          // z slices per workgroup of the 3D phi kernel (1 .. its maximum)
 };
 
 // Storage conversions of the population deviations (FP32 or FP16 storage, FP32 arithmetic;
