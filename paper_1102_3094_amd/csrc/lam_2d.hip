@@ -391,8 +391,24 @@ struct Phi2dDims {
   static constexpr int W = TX + 2 * R;
 };
 
-// Register strips of the phi sub-steps: KS cells of one column per thread.
-constexpr int PHI_KS = 4;
+// Register strips of the phi sub-steps: KS cells of one column per thread, KS from 4 to PHI_KS
+// per phase.
+constexpr int PHI_KS = 6;
+
+// Strip length of a phase over hh x ww cells with nth threads: the fewest cells per thread in
+// sequence (rounds of strips times KS), so that a phase whose strips would need a second, mostly
+// idle round takes longer strips instead (64 x 32 tiles, two sub-steps: 6, 6, 5, 4).
+constexpr int phi_ks(int hh, int ww, int nth) {
+  int best = 4, cost = 1 << 30;
+  for (int k = 4; k <= PHI_KS; ++k) {
+    const int rounds = (ww * ((hh + k - 1) / k) + nth - 1) / nth;
+    if (rounds * k < cost) {
+      cost = rounds * k;
+      best = k;
+    }
+  }
+  return best;
+}
 
 // Every plane has PHI_KS rows beyond its last valid row: a strip that runs past the valid rows
 // reads them (unwritten values that feed only cells that are not computed), so no read is
@@ -489,19 +505,17 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
   __syncthreads();
 
   // Both phases work on vertical strips of KS cells: a thread keeps the column values its strip
-  // shares in registers (the 13-point biharmonic reads 7 instead of 13 LDS values per cell, the
-  // update 15.5 instead of 30).  Consecutive lanes take consecutive columns.  Rows beyond a
+  // shares in registers (with KS = 4 the 13-point biharmonic reads 7 instead of 13 LDS values per
+  // cell, the update 15.5 instead of 30).  Consecutive lanes take consecutive columns.  Rows beyond a
   // plane's valid depth are clamped into the array and only feed cells that are not computed.
-  constexpr int KS = PHI_KS;
   // strips read psi rows up to H - dd + KS (dd >= 2) and mu / velocity rows up to
   // HU - dd + KS + 1 (dd >= 3): within the padded planes
   float(*ps)[W] = A;   // current psi
   float(*nx_)[W] = B;  // next psi
-#pragma unroll
-  for (int s = 0; s < S_; ++s) {
-    const int d = 3 * s;
+  auto sub = [&](auto sc) {
+    constexpr int s = decltype(sc)::value, d = 3 * s;
     {  // mu at depth d + 2: lap^2 as the 13-point square of the 5-point Laplacian
-      const int dd = d + 2, hh = H - 2 * dd, ww = W - 2 * dd;
+      constexpr int dd = d + 2, hh = H - 2 * dd, ww = W - 2 * dd, KS = phi_ks(hh, ww, NTH);
       const int nst = ww * ((hh + KS - 1) / KS);
       for (int t = tid; t < nst; t += NTH) {
         const int rb = t / ww;
@@ -547,8 +561,8 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
     }
     __syncthreads();
     {  // psi' at depth d + 3
-      const int dd = d + 3, hh = H - 2 * dd, ww = W - 2 * dd;
-      const bool last = s == S_ - 1;
+      constexpr int dd = d + 3, hh = H - 2 * dd, ww = W - 2 * dd, KS = phi_ks(hh, ww, NTH);
+      constexpr bool last = s == S_ - 1;
       const int nst = ww * ((hh + KS - 1) / KS);
       for (int t = tid; t < nst; t += NTH) {
         const int rb = t / ww;
@@ -611,7 +625,10 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
     float(*tmp)[W] = ps;
     ps = nx_;
     nx_ = tmp;
-  }
+  };
+  sub(std::integral_constant<int, 0>{});
+  if constexpr (S_ > 1) sub(std::integral_constant<int, 1>{});
+  static_assert(S_ <= 2, "at most two fused sub-steps");
 
   // Temperature: FTCS sub-steps along the wall axis (T is uniform along x); wall layers held.
   if (do_T && t == 0 && P.n_T > 0) {
