@@ -469,37 +469,44 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
   // unconditional (clamped index) and its value is not touched until it is stored.  The memory
   // counter drains in issue order, so the psi stores wait for psi alone, and the velocity (which
   // the first mu phase does not need) is stored to LDS only after that phase, its loads in flight
-  // meanwhile.
-  constexpr int CU = HYDRO ? HU * WU : 0, IU = (CU + NTH - 1) / NTH;
-  float vx[IU > 0 ? IU : 1], vy[IU > 0 ? IU : 1];
+  // meanwhile.  Rows go to waves and columns to lanes: a row is one uniform (scalar) base plus
+  // the lane's column offsets (columns 0..63, then 64..W-1 on the low lanes), fixed per thread;
+  // rows and columns past the tile are clamped to its last one (a duplicate load and store of
+  // the same value).
+  constexpr int NW = NTH / 64, JA = (H + NW - 1) / NW, JU = HYDRO ? (HU + NW - 1) / NW : 0;
+  static_assert(NTH % 64 == 0 && W - 64 <= 64 && W >= 64, "whole waves; one or two columns per lane");
+  const int wave = tid >> 6, lane = tid & 63;
+  const uint32_t ca0 = (uint32_t)colx[lane], ca1 = (uint32_t)colx[min(64 + lane, W - 1)];
+  const uint32_t cu0 = (uint32_t)colx[2 + lane], cu1 = (uint32_t)colx[2 + min(64 + lane, WU - 1)];
+  float vx[JU > 0 ? JU : 1][2], vy[JU > 0 ? JU : 1][2];
   {
-    constexpr int CA = H * W, IA = (CA + NTH - 1) / NTH;
-    float va[IA];
+    float va[JA][2];
 #pragma unroll
-    for (int k = 0; k < IA; ++k) {
-      const int i = min(tid + k * NTH, CA - 1);
-      int r = i / W, c = i - r * W;
-      va[k] = psi_in[(size_t)rowoff[r] + colx[c]];
+    for (int j = 0; j < JA; ++j) {
+      const int r = min(wave + NW * j, H - 1);
+      const float* row = psi_in + __builtin_amdgcn_readfirstlane(rowoff[r]);
+      va[j][0] = *plane_at(row, ca0);
+      va[j][1] = *plane_at(row, ca1);
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the issue order: psi first
     // velocity at depth 2 (plane offset 2); the wall-normal component is odd across a wall (the
     // sign is applied when it is stored)
 #pragma unroll
-    for (int k = 0; k < IU; ++k) {
-      const int i = min(tid + k * NTH, CU - 1);
-      int r = i / WU, c = i - r * WU;
-      size_t s = (size_t)rowoff[r + 2] + colx[c + 2];
-      vx[k] = u[s];
-      vy[k] = u[N + s];
+    for (int j = 0; j < JU; ++j) {
+      const int r = min(wave + NW * j, HU - 1);
+      const int ro = __builtin_amdgcn_readfirstlane(rowoff[r + 2]);
+      const float *rx = u + ro, *ry = u + N + ro;
+      vx[j][0] = *plane_at(rx, cu0);
+      vx[j][1] = *plane_at(rx, cu1);
+      vy[j][0] = *plane_at(ry, cu0);
+      vy[j][1] = *plane_at(ry, cu1);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // stores at the same clamped index (a duplicate store of the same value beyond the end), so
-    // that no load is sunk into a branch and issued late
 #pragma unroll
-    for (int k = 0; k < IA; ++k) {
-      const int i = min(tid + k * NTH, CA - 1);
-      int r = i / W, c = i - r * W;
-      A[r][c] = va[k];
+    for (int j = 0; j < JA; ++j) {
+      const int r = min(wave + NW * j, H - 1);
+      A[r][lane] = va[j][0];
+      A[r][min(64 + lane, W - 1)] = va[j][1];
     }
   }
   __syncthreads();
@@ -552,11 +559,13 @@ __device__ __forceinline__ void phi2d_tile(const KParams& P, const float* __rest
     }
     if (HYDRO && s == 0) {
 #pragma unroll
-      for (int k = 0; k < IU; ++k) {
-        const int i = min(tid + k * NTH, CU - 1);
-        int r = i / WU, c = i - r * WU;
-        Ux[r][c] = vx[k];
-        Uy[r][c] = rowsgn[r + 2] * vy[k];
+      for (int j = 0; j < JU; ++j) {
+        const int r = min(wave + NW * j, HU - 1);
+        const float sg = rowsgn[r + 2];
+        Ux[r][lane] = vx[j][0];
+        Ux[r][min(64 + lane, WU - 1)] = vx[j][1];
+        Uy[r][lane] = sg * vy[j][0];
+        Uy[r][min(64 + lane, WU - 1)] = sg * vy[j][1];
       }
     }
     __syncthreads();
