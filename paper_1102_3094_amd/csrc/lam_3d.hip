@@ -3,15 +3,17 @@
 //
 // Both kernels march along z over a 64 x 8 xy tile ("2.5D" blocking): LDS holds a few xy slices
 // of each field in ring buffers, so the 7-point Laplacian, the 25-point biharmonic and the
-// pressure-tensor divergence need halos only in x and y.  A workgroup owns a chunk of ZLB / ZPH
-// slices and starts the pipeline a few slices early.
+// pressure-tensor divergence need halos only in x and y.  A workgroup owns a chunk of ZLB slices
+// (lb3d) or of the host's chunk length (phi3d, at most ZPH) and starts the pipeline a few slices
+// early.
 //
 // lb3d: per slice, load phi (xy halo 3) -> L = lap phi (halo 2) -> pressure tensor (6 entries,
 //   halo 1) -> for the output slice, -div P, pull of 19 populations (issued one iteration
 //   ahead), moments, BGK + forcing collision, write 19 populations and u.
 // phi3d: per slice, load psi (halo 3) and u (halo 1) -> mu with the 25-point biharmonic (halo 1)
-//   -> psi' = psi + h (Gamma lap mu - div(psi u)) for the output slice.  One Euler sub-step per
-//   launch; the workgroup of tile 0 of the last launch also advances the per-layer temperature.
+//   -> psi' = psi + h (Gamma lap mu - div(psi u)), each slice's mu and fluxes adding their
+//   share to the outputs of the slices below, at and above it.  One Euler sub-step per launch;
+//   the workgroup of tile 0 of the last launch also advances the per-layer temperature.
 // First derivatives (in P, its divergence and the advection) are the isotropic central
 // differences over the D3Q19 set, which reach the edge neighbours in the slices z +- 1.
 #include <hip/hip_ext.h>
