@@ -27,10 +27,11 @@ def test_force_and_velocity_at_start_3d(gpu):
 
 
 @pytest.mark.parametrize("shape,walls", [((20, 16, 24), 1), ((37, 12, 40), 1), ((16, 24, 8), 0),
-                                         ((70, 8, 16), 1)])
+                                         ((70, 8, 16), 1), ((33, 10, 20), 1)])
 def test_parity_3d(gpu, shape, walls):
-    """Several z chunks (the step kernel's 16-slice and the phi kernel's 64-slice chunks, ragged
-    last chunks) and ragged x/y tiles; walls on and fully periodic."""
+    """Several z chunks (16 slices for the step kernel; the phi kernel's chunk length is chosen
+    from the lattice, 16 slices on lattices this small), ragged last chunks (one slice long at
+    nz = 33) and ragged x/y tiles; walls on and fully periodic."""
     nz, ny, nx = shape
     p = params3(nx=nx, ny=ny, nz=nz, walls=walls, Tw=0.9, T0=1.5 if walls else 0.95)
     phi0 = S.phi0(shape, seed=7)
@@ -44,8 +45,8 @@ def test_parity_3d(gpu, shape, walls):
 @pytest.mark.parametrize("shape", [(70, 12, 37), (40, 9, 70)])
 def test_parity_3d_1000_steps(gpu, shape):
     """The spec bar in 3D with hydrodynamics: 1000 steps at 0.9 Tc walls, rel-L2(phi)
-    <= 1e-5, mass and sum(phi) drift < 1e-6.  (70, 12, 37) spans five chunks of the step kernel
-    (16 slices, ragged last) and two of the phi kernel (64 slices), with a ragged x tile;
+    <= 1e-5, mass and sum(phi) drift < 1e-6.  (70, 12, 37) spans five chunks of both kernels
+    (16 slices, ragged last), with a ragged x tile;
     (40, 9, 70) spans two x tiles and two y tiles (the second one row high)."""
     nz, ny, nx = shape
     p = params3(nx=nx, ny=ny, nz=nz, Tw=0.9)
